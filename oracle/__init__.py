@@ -1,0 +1,215 @@
+"""CPU oracle for the fisheye Gaussian-splatting rasterizer (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check in
+``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``.  The
+rendering library (``paper_2409_04751_amd``) never imports it, and it imports
+nothing from the library: scene, pose and camera arguments are any objects
+with the fields of the input generators' dataclasses.
+
+All arithmetic lives in ``fgs_oracle.c`` (double precision); this file only
+marshals numpy arrays.  See that file's header for the paper passages each
+step follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fgs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+TILE = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: IEEE double, no FMA contraction, OpenMP."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("near_dist", ctypes.c_double), ("theta_max", ctypes.c_double)]
+
+
+class _Tol(ctypes.Structure):
+    _fields_ = [("tol_alpha", ctypes.c_double), ("tol_T", ctypes.c_double), ("tol_clamp", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_count_pairs.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "oracle arrays must be C-contiguous"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cam(cam) -> _Cam:
+    return _Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near, cam.theta_max)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _params(scene, pose):
+    """Parameters as doubles (float32 inputs convert exactly)."""
+    return (_f64(scene.means), _f64(scene.scales), _f64(scene.quats), _f64(scene.opacity), _f64(scene.sh),
+            _f64(pose.R).reshape(9), _f64(pose.t).reshape(3))
+
+
+# -- math primitives -------------------------------------------------------
+
+def project(p, fx, fy, cx, cy) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(2)
+    lib().orc_project(_p(p), ctypes.c_double(fx), ctypes.c_double(fy), ctypes.c_double(cx), ctypes.c_double(cy),
+                      _p(out))
+    return out
+
+
+def jacobian(p, fx, fy) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    J = np.zeros(6)
+    lib().orc_jacobian(_p(p), ctypes.c_double(fx), ctypes.c_double(fy), _p(J))
+    return J.reshape(2, 3)
+
+
+def jacobian_grad(p, fx, fy) -> np.ndarray:
+    """[3, 2, 3]: d J / d(x_c, y_c, z_c)."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    dJ = np.zeros(18)
+    lib().orc_jacobian_grad(_p(p), ctypes.c_double(fx), ctypes.c_double(fy), _p(dJ))
+    return dJ.reshape(3, 2, 3)
+
+
+def sh_basis(degree: int, d) -> np.ndarray:
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(16)
+    lib().orc_sh_basis(ctypes.c_int(degree), _p(d), _p(out))
+    return out[: (degree + 1) ** 2]
+
+
+# -- pipeline --------------------------------------------------------------
+
+def preprocess(scene, pose, cam) -> dict:
+    n = scene.n
+    o = dict(
+        visible=np.zeros(n, np.uint8), mu_p=np.zeros((n, 2)), conic=np.zeros((n, 3)), rgb=np.zeros((n, 3)),
+        clamped=np.zeros(n, np.uint8), radius=np.zeros(n, np.int32), rect=np.zeros((n, 4), np.int32),
+        depth=np.zeros(n, np.float32), tiles=np.zeros(n, np.uint32), tie=np.zeros(n, np.uint8))
+    means, scales, quats, opac, sh, R, t = _params(scene, pose)
+    c = _cam(cam)
+    lib().orc_preprocess(ctypes.c_int64(n), _p(means), _p(scales), _p(quats), _p(opac), _p(sh),
+                         ctypes.c_int(scene.sh_degree), _p(R), _p(t), ctypes.byref(c), _p(o["visible"]),
+                         _p(o["mu_p"]), _p(o["conic"]), _p(o["rgb"]), _p(o["clamped"]), _p(o["radius"]),
+                         _p(o["rect"]), _p(o["depth"]), _p(o["tiles"]), _p(o["tie"]))
+    o["opacity"] = opac
+    return o
+
+
+def bin_and_sort(pre: dict, cam) -> dict:
+    n = pre["visible"].shape[0]
+    k = lib().orc_count_pairs(ctypes.c_int64(n), _p(pre["visible"]), _p(pre["tiles"]))
+    keys = np.zeros(max(k, 1), np.uint64)
+    vals = np.zeros(max(k, 1), np.uint32)
+    ranges = np.zeros((cam.tiles_x * cam.tiles_y, 2), np.uint32)
+    lib().orc_bin(ctypes.c_int64(n), _p(pre["visible"]), _p(pre["rect"]), _p(pre["depth"]),
+                  ctypes.c_int32(cam.width), ctypes.c_int32(cam.height), ctypes.c_int64(k), _p(keys), _p(vals),
+                  _p(ranges))
+    return dict(K=int(k), keys=keys[:k], vals=vals[:k], ranges=ranges)
+
+
+DEFAULT_TOL = (1e-5, 1e-4, 1e-5)
+
+
+def blend(pre: dict, bins: dict, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL) -> dict:
+    H, W = cam.height, cam.width
+    image = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    last = np.zeros((H, W), np.int32)
+    flags = np.zeros((H, W), np.uint8)
+    evals = ctypes.c_int64(0)
+    bgv = _f32(bg)
+    vals = bins["vals"] if bins["K"] > 0 else np.zeros(1, np.uint32)
+    tl = _Tol(*tol)
+    lib().orc_blend(ctypes.c_int32(W), ctypes.c_int32(H), _p(bins["ranges"]), _p(vals), _p(pre["mu_p"]),
+                    _p(pre["conic"]), _p(pre["opacity"]), _p(pre["rgb"]), _p(bgv), ctypes.byref(tl), _p(image),
+                    _p(T), _p(last), _p(flags), ctypes.byref(evals))
+    return dict(image=image, T_final=T, last=last, flags=flags, evals=int(evals.value))
+
+
+def blend_bruteforce(pre: dict, cam, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
+    n = pre["visible"].shape[0]
+    image = np.zeros((3, cam.height, cam.width))
+    tl = _Tol(*DEFAULT_TOL)
+    lib().orc_blend_bruteforce(ctypes.c_int64(n), ctypes.c_int32(cam.width), ctypes.c_int32(cam.height),
+                               _p(pre["visible"]), _p(pre["rect"]), _p(pre["depth"]), _p(pre["mu_p"]),
+                               _p(pre["conic"]), _p(pre["opacity"]), _p(pre["rgb"]), _p(_f32(bg)),
+                               ctypes.byref(tl), _p(image))
+    return image
+
+
+def blend_backward(pre: dict, bins: dict, cam, dL_dimg, bg=(0.0, 0.0, 0.0)) -> dict:
+    n = pre["visible"].shape[0]
+    g = dict(mu_p=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+    vals = bins["vals"] if bins["K"] > 0 else np.zeros(1, np.uint32)
+    lib().orc_blend_backward(ctypes.c_int32(cam.width), ctypes.c_int32(cam.height), _p(bins["ranges"]), _p(vals),
+                             _p(pre["mu_p"]), _p(pre["conic"]), _p(pre["opacity"]), _p(pre["rgb"]), _p(_f32(bg)),
+                             _p(_f32(dL_dimg)), _p(g["mu_p"]), _p(g["conic"]), _p(g["opacity"]), _p(g["rgb"]))
+    return g
+
+
+def preprocess_backward(scene, pose, cam, pre: dict, g2d: dict) -> dict:
+    n = scene.n
+    S = scene.sh.shape[0]
+    out = dict(means=np.zeros((3, n)), scales=np.zeros((3, n)), quats=np.zeros((4, n)), opacity=np.zeros(n),
+               sh=np.zeros((S, n)))
+    means, scales, quats, opac, sh, R, t = _params(scene, pose)
+    c = _cam(cam)
+    lib().orc_preprocess_backward(ctypes.c_int64(n), _p(means), _p(scales), _p(quats), _p(opac), _p(sh),
+                                  ctypes.c_int(scene.sh_degree), _p(R), _p(t), ctypes.byref(c),
+                                  _p(pre["visible"]), _p(np.ascontiguousarray(g2d["mu_p"])),
+                                  _p(np.ascontiguousarray(g2d["conic"])), _p(np.ascontiguousarray(g2d["opacity"])),
+                                  _p(np.ascontiguousarray(g2d["rgb"])), _p(out["means"]), _p(out["scales"]),
+                                  _p(out["quats"]), _p(out["opacity"]), _p(out["sh"]))
+    return out
+
+
+def render(scene, pose, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL) -> dict:
+    """Full forward: preprocess, bin + sort, blend."""
+    pre = preprocess(scene, pose, cam)
+    bins = bin_and_sort(pre, cam)
+    out = blend(pre, bins, cam, bg, tol)
+    out.update(pre=pre, bins=bins)
+    return out
+
+
+def render_backward(scene, pose, cam, fwd: dict, dL_dimg, bg=(0.0, 0.0, 0.0)) -> dict:
+    g2d = blend_backward(fwd["pre"], fwd["bins"], cam, dL_dimg, bg)
+    grads = preprocess_backward(scene, pose, cam, fwd["pre"], g2d)
+    grads["g2d"] = g2d
+    return grads

@@ -1,0 +1,772 @@
+/*
+ * CPU oracle for the fisheye Gaussian-splatting rasterizer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The parity tests, the smoke check and the CPU
+ * baseline of the benchmark call this file; the rendering library never
+ * includes, links or calls it, and it includes nothing from the library.
+ *
+ * Plain, slow, obviously correct: double precision throughout, one loop per
+ * step of the method in the order the paper gives them, OpenMP only over
+ * independent Gaussians / tiles.
+ *
+ * Paper: Fisheye-GS (arXiv 2409.04751).
+ *   Eq. 1 and Sec. 3.1 "Definition"   3D Gaussian, Sigma = R S S^T R^T
+ *   Eq. 2 and Sec. 3.1 "Transformation"  mu_c = W mu + b, Sigma_p = J W Sigma W^T J^T
+ *   Eq. 3 and Sec. 3.1 "Rendering"    front-to-back alpha blending, 16x16 tiles,
+ *                                      sort by tile id then depth
+ *   Sec. 3.2, Eq. 4 onward            equidistant model r_d = f theta, pixel coords
+ *   Sec. 4.2                          J_phi (printed with the f factor missing on the
+ *                                      theta terms; read as f times the whole entry)
+ *   Sec. 4.3                          dJ/dx_c, dJ/dy_c, dJ/dz_c via S1..S8 (entry
+ *                                      [0][2] of dJ/dy_c printed with f_y; read as f_x)
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   theta = atan2(l_z, z_c) (the printed arctan(l_z/z_c) only covers z_c > 0);
+ *   near cull on the Euclidean distance |mu_c| <= near, rear cull theta > theta_max;
+ *   depth key = |mu_c| as float32; 0.3 px^2 low-pass dilation of Sigma_p;
+ *   lambda_max = mid + sqrt(max(0.1, mid^2 - det)); radius = ceil(3 sqrt(lambda_max));
+ *   rect = clamp(floor((mu -/+ r (+15)) / 16)); alpha = min(0.99, o e^q),
+ *   skipped when q > 0 or alpha < 1/255; blending stops before a Gaussian whose
+ *   T (1 - alpha) would fall below 1e-4; background added as T_final * bg;
+ *   real SH basis with Condon-Shortley phase, rgb = max(0, sum + 0.5);
+ *   quaternion (w, x, y, z) normalised inside; near-axis J and dJ through the
+ *   series of their closed forms (the closed forms are 0/0 on the axis).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TILE 16
+#define ND 7 /* dual-number directions: scales (3) + quaternion (4), or mean (3) */
+
+typedef struct {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+  double near_dist, theta_max;
+} orc_camera;
+
+/* ------------------------------------------------------------------------ */
+/* Forward-mode dual numbers, used for the parts of the backward that the     */
+/* paper takes from vanilla 3DGS (Sigma -> scale/rotation, SH colour -> mean). */
+/* ------------------------------------------------------------------------ */
+typedef struct { double v, d[ND]; } dual;
+
+static dual d_const(double v) { dual r; r.v = v; for (int k = 0; k < ND; ++k) r.d[k] = 0; return r; }
+static dual d_var(double v, int k) { dual r = d_const(v); r.d[k] = 1.0; return r; }
+static dual d_add(dual a, dual b) { dual r; r.v = a.v + b.v; for (int k = 0; k < ND; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+static dual d_sub(dual a, dual b) { dual r; r.v = a.v - b.v; for (int k = 0; k < ND; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+static dual d_mul(dual a, dual b) { dual r; r.v = a.v * b.v; for (int k = 0; k < ND; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+static dual d_scale(dual a, double s) { dual r; r.v = a.v * s; for (int k = 0; k < ND; ++k) r.d[k] = a.d[k] * s; return r; }
+static dual d_div(dual a, dual b) {
+  dual r; r.v = a.v / b.v;
+  for (int k = 0; k < ND; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+static dual d_sqrt(dual a) {
+  dual r; r.v = sqrt(a.v);
+  for (int k = 0; k < ND; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equidistant projection phi (Sec. 3.2) and its Jacobian (Sec. 4.2, 4.3).     */
+/* ------------------------------------------------------------------------ */
+
+/* mu_p = (c_x + f_x theta x_c / l_z, c_y + f_y theta y_c / l_z). */
+void orc_project(const double p[3], double fx, double fy, double cx, double cy, double out[2]) {
+  double x = p[0], y = p[1], z = p[2];
+  double lz = sqrt(x * x + y * y);
+  double theta = atan2(lz, z);
+  if (lz > 0) {
+    out[0] = cx + fx * theta * x / lz;
+    out[1] = cy + fy * theta * y / lz;
+  } else { /* on the optical axis the limit is the principal point */
+    out[0] = cx;
+    out[1] = cy;
+  }
+}
+
+/* Near-axis series (z > 0, u = l_z / z small).  With
+ *   h = S7 / (l_2^2 l_z^5) = (z l_z / l_2 - theta) / l_z^3,
+ *   m = -S8 / (l_2^2 l_z^5) = (3 h + 2 z / l_2^2) / l_z^2,
+ * expanding u/(1+u^2) - atan(u) and 1/(1+u^2)^2 term by term gives
+ *   h z^3 = sum_{k>=1} (-1)^k 2k/(2k+1) u^(2k-2)
+ *   m z^5 = sum_{k>=2} (-1)^(k+1) 4k(k-1)/(2k+1) u^(2k-4).                  */
+static double h_series(double u) {
+  double s = 0, p = 1, u2 = u * u;
+  for (int k = 1; k <= 10; ++k) {
+    double c = (k % 2 ? -1.0 : 1.0) * (2.0 * k) / (2.0 * k + 1.0);
+    s += c * p;
+    p *= u2;
+  }
+  return s;
+}
+static double m_series(double u) {
+  double s = 0, p = 1, u2 = u * u;
+  for (int k = 2; k <= 11; ++k) {
+    double c = (k % 2 ? 1.0 : -1.0) * 4.0 * k * (k - 1.0) / (2.0 * k + 1.0);
+    s += c * p;
+    p *= u2;
+  }
+  return s;
+}
+#define SERIES_U 1e-2
+
+/* J_phi, row-major 2x3 (Sec. 4.2, with f multiplying the whole entry). */
+void orc_jacobian(const double p[3], double fx, double fy, double J[6]) {
+  double x = p[0], y = p[1], z = p[2];
+  double lz2 = x * x + y * y, l2 = lz2 + z * z, lz = sqrt(lz2);
+  double theta = atan2(lz, z);
+  if (z > 0 && lz < SERIES_U * z) {
+    double h = h_series(lz / z) / (z * z * z);
+    J[0] = fx * (z / l2 - y * y * h);
+    J[1] = fx * x * y * h;
+    J[2] = -fx * x / l2;
+    J[3] = fy * x * y * h;
+    J[4] = fy * (z / l2 - x * x * h);
+    J[5] = -fy * y / l2;
+    return;
+  }
+  double lz3 = lz2 * lz;
+  J[0] = fx * (x * x * z / (lz2 * l2) + y * y * theta / lz3);
+  J[1] = fx * x * y * (z / (lz2 * l2) - theta / lz3);
+  J[2] = -fx * x / l2;
+  J[3] = fy * x * y * (z / (lz2 * l2) - theta / lz3);
+  J[4] = fy * (y * y * z / (lz2 * l2) + x * x * theta / lz3);
+  J[5] = -fy * y / l2;
+}
+
+/* dJ/dx_c, dJ/dy_c, dJ/dz_c (Sec. 4.3).  Output dJ[c*6 + r*3 + k] =
+ * d J[r][k] / d(coordinate c).  The four S1..S4 entries share the
+ * denominator D = l_2^2 l_z^5. */
+void orc_jacobian_grad(const double p[3], double fx, double fy, double dJ[18]) {
+  double x = p[0], y = p[1], z = p[2];
+  double lz2 = x * x + y * y, l2 = lz2 + z * z, lz = sqrt(lz2);
+  double theta = atan2(lz, z);
+  double l22 = l2 * l2;
+  double S1, S2, S3, S4; /* already divided by D */
+  if (z > 0 && lz < SERIES_U * z) {
+    double u = lz / z;
+    double h = h_series(u) / (z * z * z);
+    double m = m_series(u) / (z * z * z * z * z);
+    S1 = x * (3 * h - x * x * m);
+    S2 = y * (h - x * x * m);
+    S3 = x * (h - y * y * m);
+    S4 = y * (3 * h - y * y * m);
+  } else {
+    double lz3 = lz2 * lz, lz5 = lz3 * lz2;
+    double S7 = -l22 * lz2 * theta + l2 * lz3 * z;
+    double S8 = 3 * l22 * theta - 3 * l2 * lz * z - 2 * lz3 * z;
+    double D = l22 * lz5;
+    S1 = x * (3 * S7 + x * x * S8) / D;
+    S2 = y * (S7 + x * x * S8) / D;
+    S3 = x * (S7 + y * y * S8) / D;
+    S4 = y * (3 * S7 + y * y * S8) / D;
+  }
+  double S5 = x * x - y * y - z * z;
+  double S6 = y * y - x * x - z * z;
+  /* d/dx_c */
+  dJ[0] = fx * S1;  dJ[1] = fx * S2;  dJ[2] = fx * S5 / l22;
+  dJ[3] = fy * S2;  dJ[4] = fy * S3;  dJ[5] = 2 * fy * x * y / l22;
+  /* d/dy_c */
+  dJ[6] = fx * S2;  dJ[7] = fx * S3;  dJ[8] = 2 * fx * x * y / l22;
+  dJ[9] = fy * S3;  dJ[10] = fy * S4; dJ[11] = fy * S6 / l22;
+  /* d/dz_c */
+  dJ[12] = fx * S5 / l22;          dJ[13] = 2 * fx * x * y / l22; dJ[14] = 2 * fx * x * z / l22;
+  dJ[15] = 2 * fy * x * y / l22;   dJ[16] = fy * S6 / l22;        dJ[17] = 2 * fy * y * z / l22;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics, degree <= 3, by the associated-Legendre          */
+/* recurrence (Condon-Shortley phase).  Index k = l (l + 1) + m.              */
+/*   Y_l0  = N_l^0 P_l(z)                                                      */
+/*   Y_lm  = sqrt2 N_l^m Pt_l^m(z) Re((x + i y)^m)     m > 0                   */
+/*   Y_l-m = sqrt2 N_l^m Pt_l^m(z) Im((x + i y)^m)     m > 0                   */
+/* with Pt_l^m = P_l^m / (1 - z^2)^(m/2), N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!). */
+/* ------------------------------------------------------------------------ */
+static double factorial(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+static void sh_basis_dual(int degree, dual x, dual y, dual z, dual Y[16]) {
+  dual Pt[4][4]; /* Pt[l][m] */
+  for (int m = 0; m <= degree; ++m) {
+    double dfact = 1; /* (2m-1)!! */
+    for (int i = 2 * m - 1; i > 1; i -= 2) dfact *= i;
+    Pt[m][m] = d_const((m % 2 ? -1.0 : 1.0) * dfact);
+    if (m + 1 <= degree) Pt[m + 1][m] = d_scale(d_mul(z, Pt[m][m]), 2.0 * m + 1.0);
+    for (int l = m + 2; l <= degree; ++l)
+      Pt[l][m] = d_scale(d_sub(d_scale(d_mul(z, Pt[l - 1][m]), 2.0 * l - 1.0),
+                               d_scale(Pt[l - 2][m], l + m - 1.0)),
+                         1.0 / (l - m));
+  }
+  dual cm[4], sm[4];
+  cm[0] = d_const(1.0);
+  sm[0] = d_const(0.0);
+  for (int m = 1; m <= degree; ++m) {
+    cm[m] = d_sub(d_mul(x, cm[m - 1]), d_mul(y, sm[m - 1]));
+    sm[m] = d_add(d_mul(x, sm[m - 1]), d_mul(y, cm[m - 1]));
+  }
+  for (int l = 0; l <= degree; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - m) / factorial(l + m));
+      if (m == 0) {
+        Y[l * (l + 1)] = d_scale(Pt[l][0], N);
+      } else {
+        Y[l * (l + 1) + m] = d_scale(d_mul(Pt[l][m], cm[m]), sqrt(2.0) * N);
+        Y[l * (l + 1) - m] = d_scale(d_mul(Pt[l][m], sm[m]), sqrt(2.0) * N);
+      }
+    }
+  }
+}
+
+void orc_sh_basis(int degree, const double dir[3], double out[16]) {
+  dual Y[16];
+  sh_basis_dual(degree, d_const(dir[0]), d_const(dir[1]), d_const(dir[2]), Y);
+  int nb = (degree + 1) * (degree + 1);
+  for (int k = 0; k < nb; ++k) out[k] = Y[k].v;
+}
+
+/* rgb_c = max(0, sum_k sh[k*3+c] Y_k(dir) + 0.5), dir = (mu - cam)/|mu - cam|.
+ * Derivatives (if wanted) are with respect to mu, in d[0..2]. */
+static void sh_color(int degree, const double mu[3], const double cam[3], const double* sh, int64_t n,
+                     int64_t i, dual rgb[3], double Yv[16]) {
+  dual v[3];
+  for (int a = 0; a < 3; ++a) v[a] = d_sub(d_var(mu[a], a), d_const(cam[a]));
+  dual len = d_sqrt(d_add(d_add(d_mul(v[0], v[0]), d_mul(v[1], v[1])), d_mul(v[2], v[2])));
+  dual dir[3];
+  for (int a = 0; a < 3; ++a) dir[a] = d_div(v[a], len);
+  dual Y[16];
+  sh_basis_dual(degree, dir[0], dir[1], dir[2], Y);
+  int nb = (degree + 1) * (degree + 1);
+  for (int c = 0; c < 3; ++c) {
+    dual s = d_const(0.5);
+    for (int k = 0; k < nb; ++k) s = d_add(s, d_scale(Y[k], sh[(int64_t)(k * 3 + c) * n + i]));
+    rgb[c] = s;
+  }
+  for (int k = 0; k < nb; ++k) Yv[k] = Y[k].v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D covariance (Eq. 1): Sigma = R S S^T R^T, R from the normalised           */
+/* quaternion (w, x, y, z).  Dual directions 0..2 = scale, 3..6 = quaternion. */
+/* ------------------------------------------------------------------------ */
+static void cov3d_dual(const double s[3], const double q[4], dual Sig[9]) {
+  dual sd[3], qd[4];
+  for (int a = 0; a < 3; ++a) sd[a] = d_var(s[a], a);
+  for (int a = 0; a < 4; ++a) qd[a] = d_var(q[a], 3 + a);
+  dual qn2 = d_const(0);
+  for (int a = 0; a < 4; ++a) qn2 = d_add(qn2, d_mul(qd[a], qd[a]));
+  dual qn = d_sqrt(qn2);
+  dual w = d_div(qd[0], qn), x = d_div(qd[1], qn), y = d_div(qd[2], qn), z = d_div(qd[3], qn);
+  dual one = d_const(1.0);
+  dual R[9];
+  R[0] = d_sub(one, d_scale(d_add(d_mul(y, y), d_mul(z, z)), 2));
+  R[1] = d_scale(d_sub(d_mul(x, y), d_mul(w, z)), 2);
+  R[2] = d_scale(d_add(d_mul(x, z), d_mul(w, y)), 2);
+  R[3] = d_scale(d_add(d_mul(x, y), d_mul(w, z)), 2);
+  R[4] = d_sub(one, d_scale(d_add(d_mul(x, x), d_mul(z, z)), 2));
+  R[5] = d_scale(d_sub(d_mul(y, z), d_mul(w, x)), 2);
+  R[6] = d_scale(d_sub(d_mul(x, z), d_mul(w, y)), 2);
+  R[7] = d_scale(d_add(d_mul(y, z), d_mul(w, x)), 2);
+  R[8] = d_sub(one, d_scale(d_add(d_mul(x, x), d_mul(y, y)), 2));
+  dual M[9]; /* M = R S */
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M[r * 3 + c] = d_mul(R[r * 3 + c], sd[c]);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      dual acc = d_const(0);
+      for (int k = 0; k < 3; ++k) acc = d_add(acc, d_mul(M[r * 3 + k], M[c * 3 + k]));
+      Sig[r * 3 + c] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preprocess: one Gaussian at a time, in the order of the paper's            */
+/* commented PreprocessCUDA algorithm (frustum test, project, cov3D, cov2D,   */
+/* det test, eigenvalues, radius, rect, colour, depth).                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double pc[3];
+  double theta;
+  double mu_p[2];
+  double J[6];
+  double T[6];
+  double Sig[9];
+  double Sp[4]; /* dilated 2D covariance */
+  double conic[3];
+} geom;
+
+/* Returns 0 if culled. */
+static int geometry(int64_t i, int64_t n, const double* means, const double* scales, const double* quats,
+                    const double* opac, const double* Rw, const double* tw, const orc_camera* cam, geom* g,
+                    dual Sig[9]) {
+  double mf[3] = {means[i], means[n + i], means[2 * n + i]};
+  double sf[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+  double qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+  for (int a = 0; a < 3; ++a) if (!isfinite(mf[a]) || !isfinite(sf[a])) return 0;
+  for (int a = 0; a < 4; ++a) if (!isfinite(qf[a])) return 0;
+  if (!isfinite(opac[i])) return 0;
+  double q2 = 0;
+  for (int a = 0; a < 4; ++a) q2 += qf[a] * qf[a];
+  if (!(q2 > 0)) return 0;
+  /* mu_c = W mu + b (Eq. 2), each row summed left to right. */
+  for (int r = 0; r < 3; ++r)
+    g->pc[r] = ((Rw[r * 3 + 0] * mf[0] + Rw[r * 3 + 1] * mf[1]) + Rw[r * 3 + 2] * mf[2]) + tw[r];
+  double dist = sqrt((g->pc[0] * g->pc[0] + g->pc[1] * g->pc[1]) + g->pc[2] * g->pc[2]);
+  if (!(dist > cam->near_dist)) return 0;
+  double lz = sqrt(g->pc[0] * g->pc[0] + g->pc[1] * g->pc[1]);
+  g->theta = atan2(lz, g->pc[2]);
+  if (!(g->theta <= cam->theta_max)) return 0;
+  orc_project(g->pc, cam->fx, cam->fy, cam->cx, cam->cy, g->mu_p);
+  double s[3] = {sf[0], sf[1], sf[2]}, q[4] = {qf[0], qf[1], qf[2], qf[3]};
+  cov3d_dual(s, q, Sig);
+  for (int k = 0; k < 9; ++k) g->Sig[k] = Sig[k].v;
+  orc_jacobian(g->pc, cam->fx, cam->fy, g->J);
+  /* T = J W */
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += g->J[r * 3 + k] * Rw[k * 3 + c];
+      g->T[r * 3 + c] = acc;
+    }
+  /* Sigma_p = T Sigma T^T, plus the 0.3 px^2 low-pass dilation */
+  double TS[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += g->T[r * 3 + k] * g->Sig[k * 3 + c];
+      TS[r * 3 + c] = acc;
+    }
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += TS[r * 3 + k] * g->T[c * 3 + k];
+      g->Sp[r * 2 + c] = acc;
+    }
+  g->Sp[0] += 0.3;
+  g->Sp[3] += 0.3;
+  double det = g->Sp[0] * g->Sp[3] - g->Sp[1] * g->Sp[2];
+  if (!(det > 0)) return 0;
+  g->conic[0] = g->Sp[3] / det;
+  g->conic[1] = -g->Sp[1] / det;
+  g->conic[2] = g->Sp[0] / det;
+  return 1;
+}
+
+static double tie_dist(double v) { return fabs(v - nearbyint(v)); }
+
+/*
+ * Outputs (arrays of length n unless stated):
+ *   visible u8, mu_p [n][2], conic [n][3] (A, B, C with q = -(A dx^2 + C dy^2)/2 - B dx dy),
+ *   rgb [n][3], clamped u8 (bit c = channel c clamped at 0), radius i32,
+ *   rect [n][4] (x0, y0, x1, y1, tile units, half-open), depth f32 (|mu_c|),
+ *   tiles u32, tie u8 (1 = radius or rect decision within 1e-9 of a boundary).
+ */
+void orc_preprocess(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
+                    const double* sh, int sh_degree, const double* Rw, const double* tw, const orc_camera* cam,
+                    uint8_t* visible, double* mu_p, double* conic, double* rgb, uint8_t* clamped,
+                    int32_t* radius, int32_t* rect, float* depth, uint32_t* tiles, uint8_t* tie) {
+  const int gx = (cam->width + TILE - 1) / TILE, gy = (cam->height + TILE - 1) / TILE;
+  double campos[3];
+  for (int a = 0; a < 3; ++a) campos[a] = -(Rw[0 * 3 + a] * tw[0] + Rw[1 * 3 + a] * tw[1] + Rw[2 * 3 + a] * tw[2]);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i) {
+    visible[i] = 0; radius[i] = 0; tiles[i] = 0; clamped[i] = 0; tie[i] = 0; depth[i] = 0;
+    for (int a = 0; a < 4; ++a) rect[i * 4 + a] = 0;
+    for (int a = 0; a < 2; ++a) mu_p[i * 2 + a] = 0;
+    for (int a = 0; a < 3; ++a) { conic[i * 3 + a] = 0; rgb[i * 3 + a] = 0; }
+    geom g;
+    dual Sig[9];
+    if (!geometry(i, n, means, scales, quats, opac, Rw, tw, cam, &g, Sig)) continue;
+    double mid = 0.5 * (g.Sp[0] + g.Sp[3]);
+    double det = g.Sp[0] * g.Sp[3] - g.Sp[1] * g.Sp[2];
+    double lam = mid + sqrt(fmax(0.1, mid * mid - det));
+    double r3 = 3.0 * sqrt(lam);
+    double rad = ceil(r3);
+    uint8_t t = 0;
+    if (tie_dist(r3) < 1e-9 * r3) t = 1;
+    double v[4] = {(g.mu_p[0] - rad) / TILE, (g.mu_p[1] - rad) / TILE, (g.mu_p[0] + rad + TILE - 1) / TILE,
+                   (g.mu_p[1] + rad + TILE - 1) / TILE};
+    int lim[4] = {gx, gy, gx, gy};
+    int rc[4];
+    for (int a = 0; a < 4; ++a) {
+      double f = floor(v[a]);
+      if (f < 0) f = 0;
+      if (f > lim[a]) f = lim[a];
+      rc[a] = (int)f;
+      if (v[a] > -1 && v[a] < lim[a] + 1 && tie_dist(v[a]) < 1e-9 * fmax(1.0, fabs(v[a]))) t = 1;
+    }
+    int area = (rc[2] - rc[0]) * (rc[3] - rc[1]);
+    if (area == 0) continue;
+    dual col[3];
+    double Yv[16];
+    double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+    sh_color(sh_degree, mu, campos, sh, n, i, col, Yv);
+    int ok = 1;
+    for (int c = 0; c < 3; ++c) if (!isfinite(col[c].v)) ok = 0;
+    if (!ok) continue;
+    uint8_t cl = 0;
+    for (int c = 0; c < 3; ++c) {
+      double val = col[c].v;
+      if (val < 0) { cl |= (uint8_t)(1u << c); val = 0; }
+      rgb[i * 3 + c] = val;
+    }
+    visible[i] = 1;
+    clamped[i] = cl;
+    tie[i] = t;
+    mu_p[i * 2 + 0] = g.mu_p[0];
+    mu_p[i * 2 + 1] = g.mu_p[1];
+    for (int a = 0; a < 3; ++a) conic[i * 3 + a] = g.conic[a];
+    radius[i] = (int32_t)rad;
+    for (int a = 0; a < 4; ++a) rect[i * 4 + a] = rc[a];
+    depth[i] = (float)sqrt((g.pc[0] * g.pc[0] + g.pc[1] * g.pc[1]) + g.pc[2] * g.pc[2]);
+    tiles[i] = (uint32_t)area;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tile binning and sort (Sec. 3.1 "Rendering").                              */
+/* ------------------------------------------------------------------------ */
+int64_t orc_count_pairs(int64_t n, const uint8_t* visible, const uint32_t* tiles) {
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (visible[i]) k += tiles[i];
+  return k;
+}
+
+typedef struct { uint64_t key; uint32_t val; } pair_t;
+
+static int cmp_pair(const void* a, const void* b) {
+  const pair_t* x = (const pair_t*)a;
+  const pair_t* y = (const pair_t*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->val != y->val) return x->val < y->val ? -1 : 1;
+  return 0;
+}
+
+/* Emit one (key, id) pair per (Gaussian, tile of its rect), key =
+ * tile_id << 32 | float bits of depth, then sort by (key, id) and find
+ * each tile's [start, end) in the sorted list.  ranges is [ntiles][2]. */
+void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float* depth, int32_t width,
+             int32_t height, int64_t kcount, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+  const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
+  pair_t* p = (pair_t*)malloc(sizeof(pair_t) * (size_t)(kcount > 0 ? kcount : 1));
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!visible[i]) continue;
+    uint32_t bits;
+    memcpy(&bits, &depth[i], 4);
+    for (int ty = rect[i * 4 + 1]; ty < rect[i * 4 + 3]; ++ty)
+      for (int tx = rect[i * 4 + 0]; tx < rect[i * 4 + 2]; ++tx) {
+        p[k].key = ((uint64_t)(uint32_t)(ty * gx + tx) << 32) | bits;
+        p[k].val = (uint32_t)i;
+        ++k;
+      }
+  }
+  qsort(p, (size_t)k, sizeof(pair_t), cmp_pair);
+  for (int64_t t = 0; t < (int64_t)gx * gy * 2; ++t) ranges[t] = 0;
+  for (int64_t j = 0; j < k; ++j) {
+    keys[j] = p[j].key;
+    vals[j] = p[j].val;
+    uint32_t tile = (uint32_t)(p[j].key >> 32);
+    if (j == 0 || (uint32_t)(p[j - 1].key >> 32) != tile) ranges[tile * 2] = (uint32_t)j;
+    if (j == k - 1 || (uint32_t)(p[j + 1].key >> 32) != tile) ranges[tile * 2 + 1] = (uint32_t)(j + 1);
+  }
+  free(p);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alpha blending (Eq. 3), per pixel of each 16x16 tile, front to back.      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double tol_alpha; /* relative margin around 1/255 flagged as ambiguous */
+  double tol_T;     /* relative margin around the 1e-4 transmittance stop */
+  double tol_clamp; /* relative margin around the 0.99 alpha clamp */
+} orc_tol;
+
+#define ALPHA_MIN (1.0 / 255.0)
+#define ALPHA_MAX 0.99
+#define T_MIN 1e-4
+
+typedef struct {
+  uint32_t id;
+  double alpha, T, eq, dx, dy;
+  int clampd;
+} contrib;
+
+/* Walks one pixel's list; if rec != NULL stores every blended Gaussian.
+ * Returns number blended; writes colour, final T, last (1 + list index of
+ * the last blended Gaussian) and the ambiguity flags (1 alpha cut, 2 T stop,
+ * 4 alpha clamp, 8 q ~ 0). */
+static int walk_pixel(double px, double py, const uint32_t* ids, int64_t count, const double* mu_p,
+                      const double* conic, const double* opac, const double* rgb, const orc_tol* tol,
+                      double C[3], double* Tout, int64_t* last, uint8_t* flag, int64_t* evals, contrib* rec,
+                      int64_t rec_cap) {
+  double T = 1.0;
+  int nb = 0;
+  C[0] = C[1] = C[2] = 0;
+  *last = 0;
+  *flag = 0;
+  int64_t ev = 0;
+  for (int64_t j = 0; j < count; ++j) {
+    uint32_t g = ids[j];
+    ++ev;
+    double dx = mu_p[g * 2 + 0] - px, dy = mu_p[g * 2 + 1] - py;
+    double A = conic[g * 3 + 0], B = conic[g * 3 + 1], Cc = conic[g * 3 + 2];
+    double q = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy;
+    if (fabs(q) < 1e-10) *flag |= 8;
+    if (q > 0) continue;
+    double eq = exp(q);
+    double raw = opac[g] * eq;
+    double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
+    if (fabs(alpha - ALPHA_MIN) <= tol->tol_alpha * ALPHA_MIN) *flag |= 1;
+    if (alpha < ALPHA_MIN) continue;
+    if (fabs(raw - ALPHA_MAX) <= tol->tol_clamp * ALPHA_MAX) *flag |= 4;
+    double tn = T * (1.0 - alpha);
+    if (fabs(tn - T_MIN) <= tol->tol_T * T_MIN) *flag |= 2;
+    if (tn < T_MIN) break;
+    for (int c = 0; c < 3; ++c) C[c] += rgb[g * 3 + c] * alpha * T;
+    if (rec && nb < rec_cap) {
+      rec[nb].id = g; rec[nb].alpha = alpha; rec[nb].T = T; rec[nb].eq = eq;
+      rec[nb].dx = dx; rec[nb].dy = dy; rec[nb].clampd = !(raw < ALPHA_MAX);
+    }
+    ++nb;
+    T = tn;
+    *last = j + 1;
+  }
+  *Tout = T;
+  if (evals) *evals = ev;
+  return nb;
+}
+
+/* image [3][H][W]; T_final [H][W]; last [H][W] (int32); flags [H][W]. */
+void orc_blend(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* vals, const double* mu_p,
+               const double* conic, const double* opac, const double* rgb, const float bg[3], const orc_tol* tol,
+               double* image, double* T_final, int32_t* last, uint8_t* flags, int64_t* eval_total) {
+  const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
+  int64_t evsum = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evsum)
+  for (int t = 0; t < gx * gy; ++t) {
+    int tx = t % gx, ty = t / gx;
+    uint32_t s = ranges[t * 2], e = ranges[t * 2 + 1];
+    for (int j = 0; j < TILE; ++j)
+      for (int i = 0; i < TILE; ++i) {
+        int px = tx * TILE + i, py = ty * TILE + j;
+        if (px >= width || py >= height) continue;
+        double C[3], T;
+        int64_t lst, ev;
+        uint8_t f;
+        walk_pixel(px, py, vals + s, (int64_t)e - s, mu_p, conic, opac, rgb, tol, C, &T, &lst, &f, &ev, NULL, 0);
+        int64_t pix = (int64_t)py * width + px;
+        for (int c = 0; c < 3; ++c) image[(int64_t)c * width * height + pix] = C[c] + T * bg[c];
+        T_final[pix] = T;
+        last[pix] = (int32_t)lst;
+        flags[pix] = f;
+        evsum += ev;
+      }
+  }
+  if (eval_total) *eval_total = evsum;
+}
+
+/* Untiled reference: each pixel walks every visible Gaussian in (depth, id)
+ * order, keeping those whose rect contains the pixel's tile. */
+void orc_blend_bruteforce(int64_t n, int32_t width, int32_t height, const uint8_t* visible, const int32_t* rect,
+                          const float* depth, const double* mu_p, const double* conic, const double* opac,
+                          const double* rgb, const float bg[3], const orc_tol* tol, double* image) {
+  int64_t nv = 0;
+  for (int64_t i = 0; i < n; ++i) nv += visible[i];
+  pair_t* order = (pair_t*)malloc(sizeof(pair_t) * (size_t)(nv > 0 ? nv : 1));
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (visible[i]) {
+      uint32_t bits;
+      memcpy(&bits, &depth[i], 4);
+      order[k].key = bits;
+      order[k].val = (uint32_t)i;
+      ++k;
+    }
+  qsort(order, (size_t)nv, sizeof(pair_t), cmp_pair);
+  uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nv > 0 ? nv : 1));
+  for (int py = 0; py < height; ++py)
+    for (int px = 0; px < width; ++px) {
+      int tx = px / TILE, ty = py / TILE;
+      int64_t c = 0;
+      for (int64_t j = 0; j < nv; ++j) {
+        uint32_t g = order[j].val;
+        if (tx >= rect[g * 4 + 0] && tx < rect[g * 4 + 2] && ty >= rect[g * 4 + 1] && ty < rect[g * 4 + 3])
+          ids[c++] = g;
+      }
+      double C[3], T;
+      int64_t lst;
+      uint8_t f;
+      walk_pixel(px, py, ids, c, mu_p, conic, opac, rgb, tol, C, &T, &lst, &f, NULL, NULL, 0);
+      int64_t pix = (int64_t)py * width + px;
+      for (int ch = 0; ch < 3; ++ch) image[(int64_t)ch * width * height + pix] = C[ch] + T * bg[ch];
+    }
+  free(ids);
+  free(order);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Blend backward: exact derivatives of walk_pixel, per pixel last to first. */
+/* Outputs per Gaussian (accumulated, caller zeroes): g_mu_p [n][2],          */
+/* g_conic [n][3] (d/dA, d/dB, d/dC), g_opac [n], g_rgb [n][3].               */
+/* ------------------------------------------------------------------------ */
+void orc_blend_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* vals,
+                        const double* mu_p, const double* conic, const double* opac, const double* rgb,
+                        const float bg[3], const float* dL_dimg, double* g_mu_p, double* g_conic, double* g_opac,
+                        double* g_rgb) {
+  const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
+  orc_tol tol = {0, 0, 0};
+#pragma omp parallel
+  {
+    int64_t cap = 1 << 16;
+    contrib* rec = (contrib*)malloc(sizeof(contrib) * (size_t)cap);
+#pragma omp for schedule(dynamic, 1)
+    for (int t = 0; t < gx * gy; ++t) {
+      int tx = t % gx, ty = t / gx;
+      uint32_t s = ranges[t * 2], e = ranges[t * 2 + 1];
+      if ((int64_t)(e - s) > cap) {
+        cap = (int64_t)(e - s);
+        rec = (contrib*)realloc(rec, sizeof(contrib) * (size_t)cap);
+      }
+      for (int j = 0; j < TILE; ++j)
+        for (int i = 0; i < TILE; ++i) {
+          int px = tx * TILE + i, py = ty * TILE + j;
+          if (px >= width || py >= height) continue;
+          int64_t pix = (int64_t)py * width + px;
+          double C[3], T;
+          int64_t lst;
+          uint8_t f;
+          int nb = walk_pixel(px, py, vals + s, (int64_t)e - s, mu_p, conic, opac, rgb, &tol, C, &T, &lst, &f,
+                              NULL, rec, cap);
+          double G[3];
+          for (int c = 0; c < 3; ++c) G[c] = dL_dimg[(int64_t)c * width * height + pix];
+          double Bk[3] = {bg[0], bg[1], bg[2]}; /* colour seen behind the current Gaussian */
+          for (int k = nb - 1; k >= 0; --k) {
+            const contrib* r = &rec[k];
+            uint32_t g = r->id;
+            double a = r->alpha, Ti = r->T;
+            double dLda = 0;
+            for (int c = 0; c < 3; ++c) {
+              double col = rgb[g * 3 + c];
+#pragma omp atomic
+              g_rgb[g * 3 + c] += a * Ti * G[c];
+              dLda += Ti * (col - Bk[c]) * G[c];
+              Bk[c] = a * col + (1.0 - a) * Bk[c];
+            }
+            if (r->clampd) continue; /* alpha = 0.99 does not depend on o or q */
+            double dLdq = dLda * a;
+            double dLdo = dLda * r->eq;
+            double A = conic[g * 3 + 0], B = conic[g * 3 + 1], Cc = conic[g * 3 + 2];
+            double dx = r->dx, dy = r->dy;
+#pragma omp atomic
+            g_opac[g] += dLdo;
+#pragma omp atomic
+            g_mu_p[g * 2 + 0] += dLdq * -(A * dx + B * dy);
+#pragma omp atomic
+            g_mu_p[g * 2 + 1] += dLdq * -(B * dx + Cc * dy);
+#pragma omp atomic
+            g_conic[g * 3 + 0] += dLdq * -0.5 * dx * dx;
+#pragma omp atomic
+            g_conic[g * 3 + 1] += dLdq * -dx * dy;
+#pragma omp atomic
+            g_conic[g * 3 + 2] += dLdq * -0.5 * dy * dy;
+          }
+        }
+    }
+    free(rec);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preprocess backward (Sec. 4.2, 4.3).                                        */
+/*   dL/dSigma'  = -Q G Q           (Q = conic matrix, G its gradient)         */
+/*   dL/dT       = 2 dL/dSigma_p T Sigma,  dL/dSigma = T^T dL/dSigma_p T       */
+/*   dL/dJ       = dL/dT W^T                                                   */
+/*   dL/dmu_c    = J_phi^T dL/dmu_p + sum_ij dL/dJ_ij dJ_ij/dmu_c              */
+/*   dL/dmu      = W^T dL/dmu_c + (d rgb / d mu)^T dL/drgb                     */
+/* Outputs (written, same SoA layout as the parameters): g_means [3][n],       */
+/* g_scales [3][n], g_quats [4][n], g_opac [n], g_sh [S][n].                   */
+/* ------------------------------------------------------------------------ */
+void orc_preprocess_backward(int64_t n, const double* means, const double* scales, const double* quats,
+                             const double* opac, const double* sh, int sh_degree, const double* Rw, const double* tw,
+                             const orc_camera* cam, const uint8_t* visible, const double* g_mu_p,
+                             const double* g_conic, const double* g_opac2d, const double* g_rgb, double* g_means,
+                             double* g_scales, double* g_quats, double* g_opac, double* g_sh) {
+  const int S = 3 * (sh_degree + 1) * (sh_degree + 1);
+  double campos[3];
+  for (int a = 0; a < 3; ++a) campos[a] = -(Rw[0 * 3 + a] * tw[0] + Rw[1 * 3 + a] * tw[1] + Rw[2 * 3 + a] * tw[2]);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) { g_means[a * n + i] = 0; g_scales[a * n + i] = 0; }
+    for (int a = 0; a < 4; ++a) g_quats[a * n + i] = 0;
+    g_opac[i] = 0;
+    for (int k = 0; k < S; ++k) g_sh[(int64_t)k * n + i] = 0;
+    if (!visible[i]) continue;
+    geom g;
+    dual Sig[9];
+    if (!geometry(i, n, means, scales, quats, opac, Rw, tw, cam, &g, Sig)) continue;
+    /* conic gradient as a symmetric matrix: dL = sum_ij G_ij dQ_ij */
+    double Q[4] = {g.conic[0], g.conic[1], g.conic[1], g.conic[2]};
+    double Gm[4] = {g_conic[i * 3 + 0], 0.5 * g_conic[i * 3 + 1], 0.5 * g_conic[i * 3 + 1], g_conic[i * 3 + 2]};
+    double QG[4], H[4];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) QG[r * 2 + c] = Q[r * 2 + 0] * Gm[0 * 2 + c] + Q[r * 2 + 1] * Gm[1 * 2 + c];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) H[r * 2 + c] = -(QG[r * 2 + 0] * Q[0 * 2 + c] + QG[r * 2 + 1] * Q[1 * 2 + c]);
+    /* dL/dT = 2 H T Sigma ; dL/dSigma = T^T H T */
+    double HT[6], dT[6], dSig[9];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) HT[r * 3 + c] = H[r * 2 + 0] * g.T[0 * 3 + c] + H[r * 2 + 1] * g.T[1 * 3 + c];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0;
+        for (int k = 0; k < 3; ++k) acc += HT[r * 3 + k] * g.Sig[k * 3 + c];
+        dT[r * 3 + c] = 2.0 * acc;
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) dSig[r * 3 + c] = g.T[0 * 3 + r] * HT[0 * 3 + c] + g.T[1 * 3 + r] * HT[1 * 3 + c];
+    /* dL/dJ = dL/dT W^T */
+    double dJm[6];
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0;
+        for (int k = 0; k < 3; ++k) acc += dT[r * 3 + k] * Rw[c * 3 + k];
+        dJm[r * 3 + c] = acc;
+      }
+    /* dL/dmu_c: mean projection + Jacobian's dependence on mu_c */
+    double dJ[18];
+    orc_jacobian_grad(g.pc, cam->fx, cam->fy, dJ);
+    double gmc[3];
+    for (int c = 0; c < 3; ++c) {
+      double acc = g.J[0 * 3 + c] * g_mu_p[i * 2 + 0] + g.J[1 * 3 + c] * g_mu_p[i * 2 + 1];
+      for (int e = 0; e < 6; ++e) acc += dJm[e] * dJ[c * 6 + e];
+      gmc[c] = acc;
+    }
+    double gm[3];
+    for (int c = 0; c < 3; ++c)
+      gm[c] = Rw[0 * 3 + c] * gmc[0] + Rw[1 * 3 + c] * gmc[1] + Rw[2 * 3 + c] * gmc[2];
+    /* colour: SH coefficients and the view direction */
+    dual col[3];
+    double Yv[16];
+    double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+    sh_color(sh_degree, mu, campos, sh, n, i, col, Yv);
+    int nb = (sh_degree + 1) * (sh_degree + 1);
+    for (int c = 0; c < 3; ++c) {
+      if (col[c].v < 0) continue; /* clamped channel */
+      double gc = g_rgb[i * 3 + c];
+      for (int k = 0; k < nb; ++k) g_sh[(int64_t)(k * 3 + c) * n + i] = Yv[k] * gc;
+      for (int a = 0; a < 3; ++a) gm[a] += col[c].d[a] * gc;
+    }
+    for (int a = 0; a < 3; ++a) g_means[a * n + i] = gm[a];
+    /* scale and rotation through Sigma(s, q) */
+    for (int k = 0; k < 7; ++k) {
+      double acc = 0;
+      for (int e = 0; e < 9; ++e) acc += dSig[e] * Sig[e].d[k];
+      if (k < 3) g_scales[k * n + i] = acc;
+      else g_quats[(k - 3) * n + i] = acc;
+    }
+    g_opac[i] = g_opac2d[i];
+  }
+}

@@ -1,0 +1,93 @@
+"""Finite-difference pin of the oracle's backward.
+
+The oracle's analytic gradients (blend backward, then the Sec. 4.2-4.3
+chain through J_phi and dJ/dmu_c, then covariance and SH) are compared with
+central differences of its own double-precision forward, for every parameter
+block.  L = sum(w * image) with random weights w; pixels where any discrete
+decision (alpha cut, transmittance stop, alpha clamp) sits within 1e-3 of its
+threshold get w = 0, and a parameter whose perturbation changes a Gaussian's
+visibility, radius or rectangle is skipped (none is expected).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_04751_amd import synth
+
+
+def _scene_and_view(seed, degree=3, n=10):
+    rng = np.random.default_rng(seed)
+    # a posed camera looking at a cluster of Gaussians
+    cam = synth.fisheye_camera(48, 40, 200.0)
+    R = synth._haar_rotation(rng)
+    pos = rng.normal(size=3)
+    # Gaussians in front of the camera: camera-space points mapped to world
+    theta = rng.uniform(0, math.radians(95), n)
+    psi = rng.uniform(0, 2 * math.pi, n)
+    r = rng.uniform(1.0, 3.0, n)
+    pc = np.stack([r * np.sin(theta) * np.cos(psi), r * np.sin(theta) * np.sin(psi), r * np.cos(theta)])
+    means = R.T @ pc + pos[:, None]
+    S = 3 * (degree + 1) ** 2
+    sh = rng.normal(0, 0.2, size=(S, n))
+    sh[:3] = rng.random((3, n))
+    quats = rng.normal(size=(4, n)) * rng.uniform(0.5, 2.0, n)  # not normalised on purpose
+    scene = synth.Scene(means.astype(np.float64), np.exp(rng.normal(-1.8, 0.4, (3, n))), quats,
+                        1 / (1 + np.exp(-rng.normal(0.5, 1.0, n))), sh, degree)
+    pose = synth.Pose(R, -R @ pos)
+    return scene, pose, cam
+
+
+def _loss_and_state(scene, pose, cam, w, bg):
+    out = oracle.render(scene, pose, cam, bg, tol=TOL)
+    pre = out["pre"]
+    state = (pre["visible"].copy(), pre["radius"].copy(), pre["rect"].copy())
+    return float((w * out["image"]).sum()), state, out
+
+
+# Relative margin around each discrete threshold inside which a pixel's
+# weight is zeroed.  It must exceed the relative change of alpha that the
+# largest step below causes.
+TOL = (1e-3, 1e-3, 1e-3)
+# Step per block, relative to max(|value|, 0.05).  Means move splats fastest
+# (f / z ~ 100 px per metre), SH enters linearly.
+STEP = {"means": 1e-7, "scales": 1e-6, "quats": 1e-6, "opacity": 1e-6, "sh": 1e-5}
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_gradients_match_finite_differences(seed):
+    scene, pose, cam = _scene_and_view(seed)
+    rng = np.random.default_rng(100 + seed)
+    bg = (0.2, 0.1, 0.3)
+    w = rng.normal(size=(3, cam.height, cam.width))
+    out = oracle.render(scene, pose, cam, bg, tol=TOL)
+    assert out["pre"]["visible"].sum() >= 6
+    w[:, out["flags"] > 0] = 0.0
+    grads = oracle.render_backward(scene, pose, cam, out, w, bg)
+    _, base_state, _ = _loss_and_state(scene, pose, cam, w, bg)
+    blocks = {"means": scene.means, "scales": scene.scales, "quats": scene.quats, "opacity": scene.opacity,
+              "sh": scene.sh}
+    skipped = 0
+    for name, arr in blocks.items():
+        fd = np.zeros(arr.shape)
+        an = grads[name]
+        for idx in np.ndindex(arr.shape):
+            v0 = arr[idx]
+            h = STEP[name] * max(abs(v0), 0.05)
+            arr[idx] = v0 + h
+            lp, sp_, _ = _loss_and_state(scene, pose, cam, w, bg)
+            arr[idx] = v0 - h
+            lm, sm_, _ = _loss_and_state(scene, pose, cam, w, bg)
+            arr[idx] = v0
+            if any(not np.array_equal(a, b) for a, b in zip(sp_ + sm_, base_state + base_state)):
+                skipped += 1
+                fd[idx] = an[idx]
+                continue
+            fd[idx] = (lp - lm) / (2 * h)
+        norm = np.linalg.norm(fd)
+        assert norm > 0, name
+        rel = np.linalg.norm(an - fd) / norm
+        assert rel < 1e-6, (name, rel)
+        assert np.all(np.abs(an - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())), name
+    assert skipped == 0

@@ -1,0 +1,178 @@
+/*
+ * fgs.h - C ABI of the MI355X fisheye Gaussian-splatting rasterizer.
+ *
+ * The library renders 3D Gaussians (Fisheye-GS, arXiv 2409.04751) through
+ * the equidistant fisheye model r = f theta (Sec. 3.2) with the tile-based
+ * pipeline the paper keeps from 3DGS (Sec. 4.1): a per-Gaussian preprocess,
+ * tile binning, a sort by (tile, depth) and front-to-back alpha blending
+ * (Eq. 3), plus the backward pass whose projection gradients the paper
+ * derives (Sec. 4.2, 4.3).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is DEVICE memory owned by the caller; the library
+ *     never allocates, frees or retains it.  Structs and bg[3] are HOST memory
+ *     read during the call only.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Work is enqueued on it; calls return before it finishes except
+ *     where stated (fgs_render_forward reads one counter back).
+ *   - Parameter layout is structure-of-arrays float32, plane-major:
+ *       means [3][n], scales [3][n] (activated, > 0), quats [4][n] (w,x,y,z;
+ *       any non-zero norm, normalised inside), opacities [n] (activated, in
+ *       (0,1)), sh [S][n] with S = 3 (sh_degree+1)^2 and plane k*3+c holding
+ *       real-SH basis function k (index l(l+1)+m, Condon-Shortley phase) for
+ *       colour channel c.
+ *   - Images are planar float32 [3][height][width]; pixel (x, y) has its
+ *     centre at image coordinate (x, y).
+ *   - Return value: FGS_OK (0) or a negative FGS_ERR_* code; the message of
+ *     the last failure on the calling thread is available from
+ *     fgs_last_error().  No C++ exception crosses this boundary.
+ *   - n = 0, or every Gaussian culled, is not an error: the image is bg.
+ *     Gaussians with a non-finite mean, scale, quaternion, opacity or colour,
+ *     or a zero quaternion, are culled.
+ */
+#ifndef FGS_H
+#define FGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGS_OK 0
+#define FGS_ERR_ARG (-1)       /* null pointer, bad size, unsupported model or degree */
+#define FGS_ERR_WORKSPACE (-2) /* workspace too small; *k_out holds the intersections needed */
+#define FGS_ERR_HIP (-3)       /* HIP runtime error; text in fgs_last_error() */
+#define FGS_ERR_OVERFLOW (-4)  /* more than 2^31 - 1 intersections or Gaussians */
+
+#define FGS_MODEL_EQUIDISTANT 0 /* r_d = f theta (Sec. 3.2) */
+
+/* Forward flags */
+#define FGS_SAVE_PIXEL_STATE 1u /* also store per-pixel final transmittance and
+                                   contributor count; the backward then reads
+                                   them instead of recomputing them */
+
+/* Intrinsics of one view (Sec. 3.2: f_x, f_y, c_x, c_y).  Gaussians are culled
+ * when |mu_c| <= near_dist or when the incidence angle theta exceeds
+ * theta_max (radians, < pi: the splat of a Gaussian near the rear axis is
+ * unbounded). */
+typedef struct fgs_camera {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+  int32_t model;
+  double near_dist;
+  double theta_max;
+} fgs_camera;
+
+/* View transform x_c = W x + b (Sec. 3.1 "Transformation"), W row-major. */
+typedef struct fgs_pose {
+  double R[9];
+  double t[3];
+} fgs_pose;
+
+/* Gaussian parameters (Eq. 1; Sigma = R S S^T R^T), device SoA planes. */
+typedef struct fgs_gaussians {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+} fgs_gaussians;
+
+/* Gradient outputs, same layouts as fgs_gaussians.  Every element is
+ * WRITTEN (culled Gaussians get 0), not accumulated.  means2d, if not NULL,
+ * receives dL/dmu_p as [2][n] (pixel units). */
+typedef struct fgs_grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+  float* means2d;
+} fgs_grads;
+
+/* Byte offsets of the arrays inside a workspace, for inspection.  All
+ * offsets are from the workspace base and 256-byte aligned. */
+typedef struct fgs_layout {
+  int64_t n;
+  int32_t width, height, tiles_x, tiles_y;
+  int64_t k_capacity;  /* intersections the workspace can hold */
+  size_t bytes;        /* bytes the layout uses (<= workspace size) */
+  size_t splats;       /* float4 [n][3]: (mu_x hi, mu_y hi, mu_x lo, mu_y lo),
+                          (-A/2 log2 e, B/A, -(C - B^2/A)/2 log2 e, log2(1/(255 o))),
+                          (o, r, g, b) */
+  size_t depth_keys;   /* uint32 [n]: float bits of |mu_c|, 0xFFFFFFFF if culled */
+  size_t tiles;        /* uint32 [n]: tiles touched (0 if culled) */
+  size_t rects;        /* uint32 [n][2]: x0 | y0 << 16, x1 | y1 << 16 (half-open) */
+  size_t radii;        /* int32 [n]: screen radius ceil(3 sqrt(lambda_max)), 0 if culled */
+  size_t depth_order;  /* uint32 [n]: Gaussian ids sorted by (depth, id), culled last */
+  size_t offsets;      /* uint32 [n]: exclusive scan of tiles in depth order */
+  size_t tile_keys;    /* uint32 [K]: sorted tile id per intersection */
+  size_t tile_ids;     /* uint32 [K]: Gaussian id per sorted intersection */
+  size_t ranges;       /* uint32 [tiles][2]: [start, end) of each tile's run */
+  size_t grad2d;       /* float [9][n]: backward scratch (dL/d mu_p xy, conic A B C, opacity, rgb) */
+  size_t pixel_T;      /* float [H][W]: final transmittance (FGS_SAVE_PIXEL_STATE) */
+  size_t pixel_last;   /* uint32 [H][W]: 1 + list index of the last blended Gaussian */
+  size_t counters;     /* uint32 [16]: [0] K, [1] visible count, [2] forward flags */
+} fgs_layout;
+
+/* Library version string (static storage). */
+const char* fgs_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fgs_last_error(void);
+
+/* Bytes of workspace a forward + backward of one view needs for n Gaussians,
+ * a width x height image and up to k_capacity intersections. */
+int fgs_workspace_bytes(int64_t n, int32_t width, int32_t height, int64_t k_capacity, size_t* bytes);
+
+/* Layout of a workspace of `bytes` bytes (host-only computation). */
+int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes, fgs_layout* out);
+
+/*
+ * Forward render of one view: preprocess (cull, project mu by the
+ * equidistant model, Sigma_p = J W Sigma W^T J^T, conic, 3-sigma radius, tile
+ * rectangle, SH colour, depth |mu_c|), sort the visible Gaussians by depth,
+ * emit one (tile, id) pair per covered tile, sort the pairs stably by tile,
+ * find each tile's run and blend every pixel front to back (Eq. 3):
+ *   alpha = min(0.99, o exp(q)), skipped if alpha < 1/255, stop before the
+ *   Gaussian that would take T below 1e-4, C = sum c alpha T + T_final bg.
+ *
+ * workspace / workspace_bytes: device scratch, kept by the caller until the
+ *   matching fgs_render_backward; its layout is fgs_workspace_layout().
+ * out_rgb: device [3][H][W].
+ * k_out: host, may be NULL; receives the number of intersections K.
+ * flags: 0 or FGS_SAVE_PIXEL_STATE.
+ * Synchronises `stream` once, after the binning scan, to read K.  If K
+ * exceeds the workspace's capacity it returns FGS_ERR_WORKSPACE with *k_out
+ * = K and out_rgb untouched; the caller grows the workspace
+ * (fgs_workspace_bytes(n, w, h, K, ...)) and calls again.
+ */
+int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                       uint32_t flags, void* workspace, size_t workspace_bytes, float* out_rgb, int64_t* k_out,
+                       void* stream);
+
+/*
+ * Backward of the same view.  Inputs must be those of the preceding
+ * fgs_render_forward on this workspace.  dL_drgb: device [3][H][W].
+ * Blend backward walks each pixel's contributors last to first, recovering
+ * T_i = T_{i+1} / (1 - alpha_i) from the final transmittance (recomputed by a
+ * front-to-back sweep unless the forward saved it), reduces per-Gaussian
+ * gradients within each tile and adds them to global accumulators; the
+ * preprocess backward then applies the chain of Sec. 4.2-4.3 (J_phi and
+ * dJ/dmu_c) and the covariance / SH derivatives.  Overwrites the
+ * workspace's grad2d scratch.  Gradients are deterministic up to the order of
+ * float atomic additions.
+ */
+int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                        void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGS_H */

@@ -1,0 +1,298 @@
+// C ABI of libfgs: argument checks, workspace layout and the launch order of
+// the forward and backward passes.  All device memory comes from the caller.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fgs_internal.hpp"
+
+namespace fgs {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(FGS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int bits_for(int64_t values) {  // bits needed to represent 0 .. values-1
+  int b = 0;
+  while (((int64_t)1 << b) < values) ++b;
+  return b;
+}
+
+}  // namespace
+
+Layout make_layout(int64_t n, int32_t width, int32_t height, int64_t kcap) {
+  Layout L;
+  L.n = n;
+  L.width = width;
+  L.height = height;
+  L.tiles_x = (width + kTile - 1) / kTile;
+  L.tiles_y = (height + kTile - 1) / kTile;
+  L.kcap = kcap;
+  const int64_t ntiles = (int64_t)L.tiles_x * L.tiles_y;
+  const int64_t P = (int64_t)width * height;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + (bytes > 0 ? bytes : 1));
+    return o;
+  };
+  L.counters = take(16 * sizeof(uint32_t));
+  L.splats = take(nn * 3 * sizeof(float4));
+  L.depth_keys = take(nn * 4);
+  L.tiles = take(nn * 4);
+  L.rects = take(nn * 8);
+  L.radii = take(nn * 4);
+  L.dkeys_a = take(nn * 4);
+  L.dvals_a = take(nn * 4);
+  L.dkeys_b = take(nn * 4);
+  L.dvals_b = take(nn * 4);
+  L.offsets = take(nn * 4);
+  L.grad2d = take(nn * 9 * 4);
+  L.ranges = take((size_t)ntiles * 8);
+  L.pixel_T = take((size_t)P * 4);
+  L.pixel_last = take((size_t)P * 4);
+  const int64_t kk = kcap > 0 ? kcap : 1;
+  const int64_t nb_max = ceil_div(std::max<int64_t>((int64_t)nn, kk), kItemsPerBlock);
+  L.hist = take((size_t)nb_max * kRadix * 4);
+  const int64_t scan_items = std::max<int64_t>({(int64_t)nn, nb_max * kRadix});
+  L.partials = take((size_t)(ceil_div(scan_items, kItemsPerBlock) + 1) * 4);
+  L.tkeys_a = take((size_t)kk * 4);
+  L.tvals_a = take((size_t)kk * 4);
+  L.tkeys_b = take((size_t)kk * 4);
+  L.tvals_b = take((size_t)kk * 4);
+  L.bytes = off;
+  L.tile_bits = bits_for(ntiles);
+  L.tile_passes = radix_passes(L.tile_bits);
+  const bool in_b = L.tile_passes % 2 == 1;
+  L.tile_keys_final = in_b ? L.tkeys_b : L.tkeys_a;
+  L.tile_ids_final = in_b ? L.tvals_b : L.tvals_a;
+  return L;
+}
+
+Layout fit_layout(int64_t n, int32_t width, int32_t height, size_t bytes) {
+  Layout L0 = make_layout(n, width, height, 0);
+  if (L0.bytes > bytes) {
+    L0.kcap = -1;
+    return L0;
+  }
+  // largest kcap with make_layout(kcap).bytes <= bytes (monotone in kcap)
+  int64_t lo = 0, hi = (int64_t)(bytes / 16) + 1;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (make_layout(n, width, height, mid).bytes <= bytes) lo = mid; else hi = mid;
+  }
+  return make_layout(n, width, height, lo);
+}
+
+}  // namespace fgs
+
+using namespace fgs;
+
+namespace {
+
+int check_common(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
+  if (!g || !pose || !cam || !bg) return fail(FGS_ERR_ARG, "null struct argument");
+  if (g->n < 0) return fail(FGS_ERR_ARG, "n < 0");
+  if (g->n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 Gaussians");
+  if (g->sh_degree < 0 || g->sh_degree > 3) return fail(FGS_ERR_ARG, "sh_degree must be 0..3");
+  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
+    return fail(FGS_ERR_ARG, "null parameter array");
+  if (cam->width <= 0 || cam->height <= 0) return fail(FGS_ERR_ARG, "image size must be positive");
+  if ((int64_t)cam->width * cam->height > ((int64_t)1 << 31)) return fail(FGS_ERR_ARG, "image too large");
+  if (((cam->width + kTile - 1) / kTile) > 0xFFFF || ((cam->height + kTile - 1) / kTile) > 0xFFFF)
+    return fail(FGS_ERR_ARG, "more than 65535 tiles along one axis");
+  if (cam->model != FGS_MODEL_EQUIDISTANT) return fail(FGS_ERR_ARG, "unsupported camera model");
+  if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(FGS_ERR_ARG, "focal lengths must be positive and the principal point finite");
+  if (!(cam->theta_max > 0) || !(cam->theta_max < 3.14159265358979323846)) return fail(FGS_ERR_ARG, "theta_max must be in (0, pi)");
+  if (!(cam->near_dist >= 0)) return fail(FGS_ERR_ARG, "near_dist must be >= 0");
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(pose->R[k])) return fail(FGS_ERR_ARG, "non-finite pose");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pose->t[k]) || !std::isfinite(bg[k])) return fail(FGS_ERR_ARG, "non-finite pose or bg");
+  return FGS_OK;
+}
+
+ViewParams make_view(const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
+  ViewParams v;
+  for (int k = 0; k < 9; ++k) v.R[k] = pose->R[k];
+  for (int k = 0; k < 3; ++k) v.t[k] = pose->t[k];
+  v.fx = cam->fx;
+  v.fy = cam->fy;
+  v.cx = cam->cx;
+  v.cy = cam->cy;
+  v.near_dist = cam->near_dist;
+  v.theta_max = cam->theta_max;
+  v.width = cam->width;
+  v.height = cam->height;
+  v.tiles_x = (cam->width + kTile - 1) / kTile;
+  v.tiles_y = (cam->height + kTile - 1) / kTile;
+  for (int k = 0; k < 3; ++k) v.bg[k] = bg[k];
+  return v;
+}
+
+void export_layout(const Layout& L, fgs_layout* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->n = L.n;
+  out->width = L.width;
+  out->height = L.height;
+  out->tiles_x = L.tiles_x;
+  out->tiles_y = L.tiles_y;
+  out->k_capacity = L.kcap;
+  out->bytes = L.bytes;
+  out->splats = L.splats;
+  out->depth_keys = L.depth_keys;
+  out->tiles = L.tiles;
+  out->rects = L.rects;
+  out->radii = L.radii;
+  out->depth_order = L.dvals_a;
+  out->offsets = L.offsets;
+  out->tile_keys = L.tile_keys_final;
+  out->tile_ids = L.tile_ids_final;
+  out->ranges = L.ranges;
+  out->grad2d = L.grad2d;
+  out->pixel_T = L.pixel_T;
+  out->pixel_last = L.pixel_last;
+  out->counters = L.counters;
+}
+
+#define HIP_TRY(expr, where)               \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* fgs_version(void) { return "fgs 0.1 gfx950"; }
+
+const char* fgs_last_error(void) { return g_last_error.c_str(); }
+
+int fgs_workspace_bytes(int64_t n, int32_t width, int32_t height, int64_t k_capacity, size_t* bytes) {
+  if (!bytes || n < 0 || width <= 0 || height <= 0 || k_capacity < 0) return fail(FGS_ERR_ARG, "bad argument");
+  if (n > 0x7FFFFFFF || k_capacity > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "size beyond 2^31-1");
+  *bytes = make_layout(n, width, height, k_capacity).bytes;
+  return FGS_OK;
+}
+
+int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes, fgs_layout* out) {
+  if (!out || n < 0 || width <= 0 || height <= 0) return fail(FGS_ERR_ARG, "bad argument");
+  const Layout L = fit_layout(n, width, height, bytes);
+  if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
+  export_layout(L, out);
+  return FGS_OK;
+}
+
+int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                       uint32_t flags, void* workspace, size_t workspace_bytes, float* out_rgb, int64_t* k_out,
+                       void* stream) {
+  int rc = check_common(g, pose, cam, bg);
+  if (rc != FGS_OK) return rc;
+  if (!workspace || !out_rgb) return fail(FGS_ERR_ARG, "null workspace or output");
+  if (flags & ~FGS_SAVE_PIXEL_STATE) return fail(FGS_ERR_ARG, "unknown flags");
+  const Layout L = fit_layout(g->n, cam->width, cam->height, workspace_bytes);
+  if (L.kcap < 0) {
+    if (k_out) *k_out = -1;
+    return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const ViewParams v = make_view(pose, cam, bg);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  const int64_t n = g->n;
+  const int32_t ntiles = L.tiles_x * L.tiles_y;
+
+  HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
+  HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
+  HIP_TRY(launch_preprocess(*g, v, ws, L, s), "preprocess");
+  bool in_b = false;
+  HIP_TRY(launch_radix_sort(reinterpret_cast<uint32_t*>(ws + L.dkeys_a), reinterpret_cast<uint32_t*>(ws + L.dvals_a),
+                            reinterpret_cast<uint32_t*>(ws + L.dkeys_b), reinterpret_cast<uint32_t*>(ws + L.dvals_b), n,
+                            32, reinterpret_cast<uint32_t*>(ws + L.hist), reinterpret_cast<uint32_t*>(ws + L.partials),
+                            &in_b, s),
+          "depth sort");
+  // 4 passes: the depth order ends in dvals_a
+  const uint32_t* depth_order = reinterpret_cast<const uint32_t*>(ws + L.dvals_a);
+  HIP_TRY(launch_scan(reinterpret_cast<const uint32_t*>(ws + L.tiles), depth_order,
+                      reinterpret_cast<uint32_t*>(ws + L.offsets), n, reinterpret_cast<uint32_t*>(ws + L.partials),
+                      counters + kCountK, s),
+          "tile count scan");
+  uint32_t K32 = 0;
+  HIP_TRY(hipMemcpyAsync(&K32, counters + kCountK, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read K");
+  HIP_TRY(hipStreamSynchronize(s), "sync for K");
+  const int64_t K = K32;
+  if (k_out) *k_out = K;
+  if (K > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 intersections");
+  if (K > L.kcap) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "workspace holds %lld intersections, %lld needed", (long long)L.kcap,
+                  (long long)K);
+    return fail(FGS_ERR_WORKSPACE, msg);
+  }
+  HIP_TRY(launch_duplicate(depth_order, reinterpret_cast<const uint32_t*>(ws + L.tiles),
+                           reinterpret_cast<const uint32_t*>(ws + L.offsets),
+                           reinterpret_cast<const uint2*>(ws + L.rects), n, L.tiles_x,
+                           reinterpret_cast<uint32_t*>(ws + L.tkeys_a), reinterpret_cast<uint32_t*>(ws + L.tvals_a), s),
+          "duplicate");
+  HIP_TRY(launch_radix_sort(reinterpret_cast<uint32_t*>(ws + L.tkeys_a), reinterpret_cast<uint32_t*>(ws + L.tvals_a),
+                            reinterpret_cast<uint32_t*>(ws + L.tkeys_b), reinterpret_cast<uint32_t*>(ws + L.tvals_b), K,
+                            L.tile_bits, reinterpret_cast<uint32_t*>(ws + L.hist),
+                            reinterpret_cast<uint32_t*>(ws + L.partials), &in_b, s),
+          "tile sort");
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(ws + (in_b ? L.tkeys_b : L.tkeys_a));
+  const uint32_t* ids = reinterpret_cast<const uint32_t*>(ws + (in_b ? L.tvals_b : L.tvals_a));
+  if ((in_b ? L.tkeys_b : L.tkeys_a) != L.tile_keys_final)
+    return fail(FGS_ERR_HIP, "internal: tile sort result buffer disagrees with the layout");
+  uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);
+  HIP_TRY(launch_ranges(keys, K, ranges, ntiles, s), "ranges");
+  HIP_TRY(launch_blend_forward(v, ranges, ids, reinterpret_cast<const float4*>(ws + L.splats), out_rgb,
+                               reinterpret_cast<float*>(ws + L.pixel_T), reinterpret_cast<uint32_t*>(ws + L.pixel_last),
+                               (flags & FGS_SAVE_PIXEL_STATE) != 0, s),
+          "blend forward");
+  return FGS_OK;
+}
+
+int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                        void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
+                        void* stream) {
+  int rc = check_common(g, pose, cam, bg);
+  if (rc != FGS_OK) return rc;
+  if (!workspace || !dL_drgb || !grads) return fail(FGS_ERR_ARG, "null workspace, dL_drgb or grads");
+  if (g->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->sh))
+    return fail(FGS_ERR_ARG, "null gradient array");
+  const Layout L = fit_layout(g->n, cam->width, cam->height, workspace_bytes);
+  if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
+  if (g->n == 0) return FGS_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const ViewParams v = make_view(pose, cam, bg);
+  float* grad2d = reinterpret_cast<float*>(ws + L.grad2d);
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * g->n, s), "clear grad2d");
+  HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges),
+                                reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final),
+                                reinterpret_cast<const float4*>(ws + L.splats), dL_drgb,
+                                reinterpret_cast<const float*>(ws + L.pixel_T),
+                                reinterpret_cast<const uint32_t*>(ws + L.pixel_last),
+                                reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, g->n, s),
+          "blend backward");
+  HIP_TRY(launch_preprocess_backward(*g, v, ws, L, *grads, s), "preprocess backward");
+  return FGS_OK;
+}
+
+}  // extern "C"

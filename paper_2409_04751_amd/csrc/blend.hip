@@ -1,0 +1,328 @@
+// Front-to-back alpha blending of each 16x16 tile (Eq. 3) and its reverse-
+// order backward.
+//
+// One block of 256 threads per tile, one thread per pixel.  The four wave64s
+// of a block each own an 8x8 quadrant, so a small splat touches few waves and
+// the backward can skip whole waves.  The tile's sorted list is consumed in
+// batches of 256 Gaussians whose 2D records are staged in LDS once and then
+// read by all 256 pixels (broadcast reads, no bank conflicts).
+//
+// Per (pixel, Gaussian) the exponent is evaluated as
+//   q = -(A t^2 + D dy^2) / 2,  t = dx + (B/A) dy,  D = C - B^2/A,
+// a sum of two non-negative terms, which avoids the cancellation of
+// A dx^2 + 2 B dx dy + C dy^2 for thin splats; the record stores A and D
+// pre-scaled by -log2(e)/2 so that e^q is one v_exp_f32.  The mean is stored
+// as a float hi + lo pair and converted to tile-relative coordinates once per
+// staged Gaussian, so dx, dy carry no rounding of |mu_p| ~ 10^3 px.
+//
+// Decisions (Eq. 3 plus the 3DGS cut-offs): skip when alpha < 1/255
+// (equivalently q2 < log2(1/(255 o))), alpha = min(0.99, o e^q), stop before
+// the Gaussian that would take T below 1e-4.
+#include "fgs_internal.hpp"
+
+namespace fgs {
+namespace {
+
+constexpr float kTmin = 1e-4f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kNegTwoLn2 = -1.3862943611198906f;  // converts the log2-scaled A, D back to natural units
+
+struct BlendArgs {
+  const uint2* ranges;
+  const uint32_t* ids;
+  const float4* splats;
+  int32_t width, height, tiles_x;
+  float bg[3];
+  float* out;
+  float* pixel_T;
+  uint32_t* pixel_last;
+  int save;
+};
+
+// Pixel of this thread inside its tile: wave w owns quadrant (w & 1, w >> 1).
+__device__ inline void pixel_of_thread(int& i, int& j) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  i = (w & 1) * 8 + (l & 7);
+  j = (w >> 1) * 8 + (l >> 3);
+}
+
+struct Staged {
+  float4 a;  // mx, my (tile-relative), A', beta
+  float4 b;  // D', q2min, o, r
+  float2 c;  // g, b
+};
+
+__device__ inline void stage_splat(const float4* splats, uint32_t g, float x0, float y0, float4& a, float4& b,
+                                   float2& c) {
+  const float4 p = splats[3 * (size_t)g + 0];
+  const float4 q = splats[3 * (size_t)g + 1];
+  const float4 r = splats[3 * (size_t)g + 2];
+  a = make_float4((p.x - x0) + p.z, (p.y - y0) + p.w, q.x, q.y);
+  b = make_float4(q.z, q.w, r.x, r.y);
+  c = make_float2(r.z, r.w);
+}
+
+// log2-scaled exponent at tile-relative pixel (fi, fj).
+__device__ inline float exponent2(const float4& a, const float4& b, float fi, float fj, float& dx, float& dy,
+                                  float& t) {
+  dx = a.x - fi;
+  dy = a.y - fj;
+  t = __builtin_fmaf(a.w, dy, dx);
+  return __builtin_fmaf(a.z * t, t, (b.x * dy) * dy);
+}
+
+__global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
+  __shared__ float4 sa[kBlock];
+  __shared__ float4 sb[kBlock];
+  __shared__ float2 sc[kBlock];
+  const int tile = blockIdx.x;
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  int i, j;
+  pixel_of_thread(i, j);
+  const int px = tx * kTile + i, py = ty * kTile + j;
+  const bool inside = px < a.width && py < a.height;
+  const float fi = (float)i, fj = (float)j;
+  const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
+  const uint2 r = a.ranges[tile];
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (uint32_t base = r.x; base < r.y; base += kBlock) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t k = base + threadIdx.x;
+    if (k < r.y) stage_splat(a.splats, a.ids[k], x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kBlock, r.y - base);
+    if (!done) {
+      for (int e = 0; e < cnt; ++e) {
+        const float4 ga = sa[e], gb = sb[e];
+        float dx, dy, t;
+        const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
+        if (!(q2 >= gb.y)) continue;
+        const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
+        const float tn = T * (1.0f - alpha);
+        if (tn < kTmin) {
+          done = true;
+          break;
+        }
+        const float2 gc = sc[e];
+        const float w = alpha * T;
+        C0 = __builtin_fmaf(gb.w, w, C0);
+        C1 = __builtin_fmaf(gc.x, w, C1);
+        C2 = __builtin_fmaf(gc.y, w, C2);
+        T = tn;
+        last = base - r.x + (uint32_t)e + 1u;
+      }
+    }
+  }
+  if (inside) {
+    const size_t hw = (size_t)a.width * a.height, p = (size_t)py * a.width + px;
+    a.out[p] = __builtin_fmaf(T, a.bg[0], C0);
+    a.out[hw + p] = __builtin_fmaf(T, a.bg[1], C1);
+    a.out[2 * hw + p] = __builtin_fmaf(T, a.bg[2], C2);
+    if (a.save) {
+      a.pixel_T[p] = T;
+      a.pixel_last[p] = last;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+struct BlendBwdArgs {
+  const uint2* ranges;
+  const uint32_t* ids;
+  const float4* splats;
+  int32_t width, height, tiles_x;
+  float bg[3];
+  const float* dL;
+  const float* pixel_T;
+  const uint32_t* pixel_last;
+  const uint32_t* counters;
+  float* grad2d;  // [9][n]
+  uint32_t n;
+};
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) {
+  __shared__ float4 sa[kBlock];
+  __shared__ float4 sb[kBlock];
+  __shared__ float2 sc[kBlock];
+  __shared__ uint32_t sid[kBlock];
+  __shared__ float acc[9][kBlock];
+  __shared__ uint32_t s_maxlast;
+  const int tile = blockIdx.x;
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  int i, j;
+  pixel_of_thread(i, j);
+  const int px = tx * kTile + i, py = ty * kTile + j;
+  const bool inside = px < a.width && py < a.height;
+  const float fi = (float)i, fj = (float)j;
+  const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
+  const uint2 r = a.ranges[tile];
+  const size_t hw = (size_t)a.width * a.height, p = (size_t)py * a.width + px;
+  const bool saved = (a.counters[kCountFlags] & FGS_SAVE_PIXEL_STATE) != 0;
+
+  // ---- final transmittance and last contributor of each pixel ----
+  float T = 1.0f;
+  uint32_t last = 0;
+  if (saved) {
+    if (inside) {
+      T = a.pixel_T[p];
+      last = a.pixel_last[p];
+    }
+  } else {
+    // front-to-back re-sweep with the forward's arithmetic (no colour)
+    bool done = !inside;
+    for (uint32_t base = r.x; base < r.y; base += kBlock) {
+      if (__syncthreads_count(!done) == 0) break;
+      const uint32_t k = base + threadIdx.x;
+      if (k < r.y) stage_splat(a.splats, a.ids[k], x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
+      __syncthreads();
+      const int cnt = (int)min((uint32_t)kBlock, r.y - base);
+      if (!done) {
+        for (int e = 0; e < cnt; ++e) {
+          const float4 ga = sa[e], gb = sb[e];
+          float dx, dy, t;
+          const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
+          if (!(q2 >= gb.y)) continue;
+          const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
+          const float tn = T * (1.0f - alpha);
+          if (tn < kTmin) {
+            done = true;
+            break;
+          }
+          T = tn;
+          last = base - r.x + (uint32_t)e + 1u;
+        }
+      }
+    }
+  }
+  if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
+  atomicMax(&s_maxlast, last);
+  __syncthreads();
+  const uint32_t maxlast = s_maxlast;
+
+  // ---- reverse sweep ----
+  float G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+  if (inside) {
+    G0 = a.dL[p];
+    G1 = a.dL[hw + p];
+    G2 = a.dL[2 * hw + p];
+  }
+  float B0 = a.bg[0], B1 = a.bg[1], B2 = a.bg[2];  // colour behind the current Gaussian
+  float Tc = T;
+  for (int end = (int)maxlast; end > 0; end -= kBlock) {
+    const int beg = max(end - kBlock, 0);
+    __syncthreads();
+    if (beg + (int)threadIdx.x < end) {
+      const uint32_t g = a.ids[r.x + beg + threadIdx.x];
+      sid[threadIdx.x] = g;
+      stage_splat(a.splats, g, x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
+    }
+    for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
+    __syncthreads();
+    for (int e = end - 1; e >= beg; --e) {
+      const int idx = e - beg;
+      float v[9];
+      for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+      bool contrib = false;
+      if ((uint32_t)e < last) {
+        const float4 ga = sa[idx], gb = sb[idx];
+        float dx, dy, t;
+        const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
+        if (q2 >= gb.y) {
+          contrib = true;
+          const float eq = __builtin_amdgcn_exp2f(q2);
+          const float raw = gb.z * eq;
+          const float alpha = fminf(kAlphaMax, raw);
+          const float Ti = Tc / (1.0f - alpha);
+          const float w = alpha * Ti;
+          const float2 gc = sc[idx];
+          v[6] = w * G0;
+          v[7] = w * G1;
+          v[8] = w * G2;
+          const float dLda = Ti * ((gb.w - B0) * G0 + (gc.x - B1) * G1 + (gc.y - B2) * G2);
+          B0 = alpha * gb.w + (1.0f - alpha) * B0;
+          B1 = alpha * gc.x + (1.0f - alpha) * B1;
+          B2 = alpha * gc.y + (1.0f - alpha) * B2;
+          Tc = Ti;
+          if (raw < kAlphaMax) {
+            const float dLdq = dLda * alpha;
+            v[5] = dLda * eq;
+            const float A = kNegTwoLn2 * ga.z, D = kNegTwoLn2 * gb.x;
+            const float At = A * t;
+            v[0] = -dLdq * At;
+            v[1] = -dLdq * (ga.w * At + D * dy);
+            v[2] = -0.5f * dLdq * dx * dx;
+            v[3] = -dLdq * dx * dy;
+            v[4] = -0.5f * dLdq * dy * dy;
+          }
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+        for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
+        if ((threadIdx.x & 63) == 0)
+          for (int k = 0; k < 9; ++k) atomicAdd(&acc[k][idx], v[k]);
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < end - beg) {
+      const uint32_t g = sid[threadIdx.x];
+      for (int k = 0; k < 9; ++k) {
+        const float val = acc[k][threadIdx.x];
+        if (val != 0.0f) atomicAdd(&a.grad2d[(size_t)k * a.n + g], val);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_blend_forward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
+                                float* out, float* pixel_T, uint32_t* pixel_last, bool save, hipStream_t s) {
+  BlendArgs a;
+  a.ranges = ranges;
+  a.ids = ids;
+  a.splats = splats;
+  a.width = v.width;
+  a.height = v.height;
+  a.tiles_x = v.tiles_x;
+  for (int c = 0; c < 3; ++c) a.bg[c] = v.bg[c];
+  a.out = out;
+  a.pixel_T = pixel_T;
+  a.pixel_last = pixel_last;
+  a.save = save ? 1 : 0;
+  const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  hipLaunchKernelGGL(blend_forward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
+                                 const float* dL_dimg, const float* pixel_T, const uint32_t* pixel_last,
+                                 const uint32_t* counters, float* grad2d, int64_t n, hipStream_t s) {
+  BlendBwdArgs a;
+  a.ranges = ranges;
+  a.ids = ids;
+  a.splats = splats;
+  a.width = v.width;
+  a.height = v.height;
+  a.tiles_x = v.tiles_x;
+  for (int c = 0; c < 3; ++c) a.bg[c] = v.bg[c];
+  a.dL = dL_dimg;
+  a.pixel_T = pixel_T;
+  a.pixel_last = pixel_last;
+  a.counters = counters;
+  a.grad2d = grad2d;
+  a.n = (uint32_t)n;
+  const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fgs

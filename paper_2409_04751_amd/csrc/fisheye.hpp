@@ -1,0 +1,183 @@
+// Device math for the equidistant fisheye projection (Fisheye-GS, Sec. 3.2,
+// 4.2, 4.3), the 3D covariance (Eq. 1) and the SH colour.
+//
+// Geometry runs in double precision: the per-Gaussian stage is bound by the
+// 236 B of parameters it reads, so fp64 costs little, and the integer
+// decisions taken from it (radius, tile rectangle, depth key) then agree
+// with any other careful evaluation except at exact ties.
+//
+// The Jacobian is written through two scalars of the camera-space point
+// p = (x, y, z), l_z = |(x, y)|, l_2 = |p|^2, theta = atan2(l_z, z):
+//   h = (z l_z / l_2 - theta) / l_z^3        (the paper's S7 / (l_2^2 l_z^5))
+//   m = (3 h + 2 z / l_2^2) / l_z^2           (the paper's -S8 / (l_2^2 l_z^5))
+// so that J_phi (Sec. 4.2, f multiplying each whole entry) is
+//   [[fx (z/l_2 - y^2 h), fx x y h, -fx x / l_2],
+//    [fy x y h, fy (z/l_2 - x^2 h), -fy y / l_2]]
+// and, since dh/dx = -x m, dh/dy = -y m, dh/dz = 2 / l_2^2, the entries of
+// dJ/dp (Sec. 4.3) are S1 = x(3h - x^2 m), S2 = y(h - x^2 m),
+// S3 = x(h - y^2 m), S4 = y(3h - y^2 m) plus the S5, S6 terms.  Near the
+// optical axis h and m are 0/0; there they come from their Taylor series in
+// u = l_z / z, which also removes the cancellation of the closed forms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fgs {
+
+constexpr double kSeriesU = 0.05;
+
+// h z^3 = sum_{k>=1} (-1)^k 2k/(2k+1) u^(2k-2)
+// m z^5 = sum_{k>=2} (-1)^(k+1) 4k(k-1)/(2k+1) u^(2k-4)
+__device__ inline double h_z3_series(double u2) {
+  double s = -16.0 / 17.0;
+  s = s * u2 + 14.0 / 15.0;
+  s = s * u2 - 12.0 / 13.0;
+  s = s * u2 + 10.0 / 11.0;
+  s = s * u2 - 8.0 / 9.0;
+  s = s * u2 + 6.0 / 7.0;
+  s = s * u2 - 4.0 / 5.0;
+  s = s * u2 + 2.0 / 3.0;
+  return -s;
+}
+__device__ inline double m_z5_series(double u2) {
+  double s = 288.0 / 19.0;
+  s = s * u2 - 224.0 / 17.0;
+  s = s * u2 + 168.0 / 15.0;
+  s = s * u2 - 120.0 / 13.0;
+  s = s * u2 + 80.0 / 11.0;
+  s = s * u2 - 48.0 / 9.0;
+  s = s * u2 + 24.0 / 7.0;
+  s = s * u2 - 8.0 / 5.0;
+  return s;
+}
+
+struct FisheyePoint {
+  double x, y, z, lz2, lz, l2, theta;
+  double h, m;
+};
+
+__device__ inline void fisheye_terms(FisheyePoint& P, bool need_m) {
+  const double x = P.x, y = P.y, z = P.z;
+  P.lz2 = x * x + y * y;
+  P.lz = sqrt(P.lz2);
+  P.l2 = P.lz2 + z * z;
+  P.theta = atan2(P.lz, z);
+  if (z > 0.0 && P.lz < kSeriesU * z) {
+    const double u = P.lz / z;
+    const double u2 = u * u;
+    const double z3 = z * z * z;
+    P.h = h_z3_series(u2) / z3;
+    P.m = need_m ? m_z5_series(u2) / (z3 * z * z) : 0.0;
+  } else {
+    P.h = (z * P.lz / P.l2 - P.theta) / (P.lz2 * P.lz);
+    P.m = need_m ? (3.0 * P.h + 2.0 * z / (P.l2 * P.l2)) / P.lz2 : 0.0;
+  }
+}
+
+// J_phi, row-major 2x3.
+__device__ inline void fisheye_jacobian(const FisheyePoint& P, double fx, double fy, double J[6]) {
+  const double x = P.x, y = P.y, z = P.z, h = P.h, il2 = 1.0 / P.l2;
+  J[0] = fx * (z * il2 - y * y * h);
+  J[1] = fx * x * y * h;
+  J[2] = -fx * x * il2;
+  J[3] = fy * x * y * h;
+  J[4] = fy * (z * il2 - x * x * h);
+  J[5] = -fy * y * il2;
+}
+
+// g[k] += sum_ij G[i][j] dJ_ij / dp_k   (G = dL/dJ, row-major 2x3)
+__device__ inline void fisheye_jacobian_vjp(const FisheyePoint& P, double fx, double fy, const double G[6],
+                                            double g[3]) {
+  const double x = P.x, y = P.y, z = P.z, h = P.h, m = P.m;
+  const double il22 = 1.0 / (P.l2 * P.l2);
+  const double S1 = x * (3.0 * h - x * x * m);
+  const double S2 = y * (h - x * x * m);
+  const double S3 = x * (h - y * y * m);
+  const double S4 = y * (3.0 * h - y * y * m);
+  const double S5 = (x * x - y * y - z * z) * il22;
+  const double S6 = (y * y - x * x - z * z) * il22;
+  const double xy2 = 2.0 * x * y * il22, xz2 = 2.0 * x * z * il22, yz2 = 2.0 * y * z * il22;
+  const double a0 = fx * G[0], a1 = fx * G[1], a2 = fx * G[2];
+  const double b0 = fy * G[3], b1 = fy * G[4], b2 = fy * G[5];
+  g[0] += a0 * S1 + a1 * S2 + a2 * S5 + b0 * S2 + b1 * S3 + b2 * xy2;
+  g[1] += a0 * S2 + a1 * S3 + a2 * xy2 + b0 * S3 + b1 * S4 + b2 * S6;
+  g[2] += a0 * S5 + a1 * xy2 + a2 * xz2 + b0 * xy2 + b1 * S6 + b2 * yz2;
+}
+
+// Rotation of the normalised quaternion (w, x, y, z), row-major.
+__device__ inline void quat_to_rot(const double q[4], double R[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Real SH basis, Condon-Shortley phase, index l(l+1)+m.  Constants are
+// sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times the factors of the Cartesian
+// polynomials; e.g. 0.4886 = sqrt(3/(4 pi)), 1.0925 = sqrt(15/(4 pi)).
+constexpr float kY00 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float kY1 = 0.4886025119029199f;     // sqrt(3/(4 pi))
+constexpr float kY2a = 1.0925484305920792f;    // sqrt(15/(4 pi))
+constexpr float kY2b = 0.31539156525252005f;   // sqrt(5/(16 pi))
+constexpr float kY2c = 0.5462742152960396f;    // sqrt(15/(16 pi))
+constexpr float kY3a = 0.5900435899266435f;    // sqrt(35/(32 pi))
+constexpr float kY3b = 2.890611442640554f;     // sqrt(105/(4 pi))
+constexpr float kY3c = 0.4570457994644658f;    // sqrt(21/(32 pi))
+constexpr float kY3d = 0.3731763325901154f;    // sqrt(7/(16 pi))
+constexpr float kY3e = 1.445305721320277f;     // sqrt(105/(16 pi))
+
+__device__ inline void sh_basis(int degree, float x, float y, float z, float Y[16]) {
+  Y[0] = kY00;
+  if (degree < 1) return;
+  Y[1] = -kY1 * y;
+  Y[2] = kY1 * z;
+  Y[3] = -kY1 * x;
+  if (degree < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kY2a * x * y;
+  Y[5] = -kY2a * y * z;
+  Y[6] = kY2b * (2.0f * zz - xx - yy);
+  Y[7] = -kY2a * x * z;
+  Y[8] = kY2c * (xx - yy);
+  if (degree < 3) return;
+  Y[9] = -kY3a * y * (3.0f * xx - yy);
+  Y[10] = kY3b * x * y * z;
+  Y[11] = -kY3c * y * (4.0f * zz - xx - yy);
+  Y[12] = kY3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -kY3c * x * (4.0f * zz - xx - yy);
+  Y[14] = kY3e * z * (xx - yy);
+  Y[15] = -kY3a * x * (xx - 3.0f * yy);
+}
+
+// Gradient of each basis polynomial with respect to (x, y, z):
+// dY[k][0..2].
+__device__ inline void sh_basis_grad(int degree, float x, float y, float z, float dY[16][3]) {
+  for (int k = 0; k < 16; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0f;
+  if (degree < 1) return;
+  dY[1][1] = -kY1;
+  dY[2][2] = kY1;
+  dY[3][0] = -kY1;
+  if (degree < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  dY[4][0] = kY2a * y;  dY[4][1] = kY2a * x;
+  dY[5][1] = -kY2a * z; dY[5][2] = -kY2a * y;
+  dY[6][0] = -2.0f * kY2b * x; dY[6][1] = -2.0f * kY2b * y; dY[6][2] = 4.0f * kY2b * z;
+  dY[7][0] = -kY2a * z; dY[7][2] = -kY2a * x;
+  dY[8][0] = 2.0f * kY2c * x; dY[8][1] = -2.0f * kY2c * y;
+  if (degree < 3) return;
+  dY[9][0] = -6.0f * kY3a * x * y;           dY[9][1] = -3.0f * kY3a * (xx - yy);
+  dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
+  dY[11][0] = 2.0f * kY3c * x * y; dY[11][1] = -kY3c * (4.0f * zz - xx - 3.0f * yy); dY[11][2] = -8.0f * kY3c * y * z;
+  dY[12][0] = -6.0f * kY3d * x * z; dY[12][1] = -6.0f * kY3d * y * z; dY[12][2] = kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+  dY[13][0] = -kY3c * (4.0f * zz - 3.0f * xx - yy); dY[13][1] = 2.0f * kY3c * x * y; dY[13][2] = -8.0f * kY3c * x * z;
+  dY[14][0] = 2.0f * kY3e * x * z; dY[14][1] = -2.0f * kY3e * y * z; dY[14][2] = kY3e * (xx - yy);
+  dY[15][0] = -3.0f * kY3a * (xx - yy); dY[15][1] = 6.0f * kY3a * x * y;
+}
+
+}  // namespace fgs

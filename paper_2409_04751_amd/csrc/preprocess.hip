@@ -1,0 +1,395 @@
+// Per-Gaussian preprocess (forward) and its backward.
+//
+// Forward, one thread per Gaussian, in the order of the 3DGS preprocess the
+// paper modifies (Sec. 4.1; only the projection changes, Sec. 4.2-4.3):
+// cull (non-finite, |mu_c| <= near, theta > theta_max), project the mean by
+// the equidistant model (Sec. 3.2), Sigma = R S S^T R^T (Eq. 1), T = J W,
+// Sigma_p = T Sigma T^T (Eq. 2) plus a 0.3 px^2 low-pass dilation, conic,
+// radius = ceil(3 sqrt(lambda_max)), tile rectangle, SH colour, depth key.
+//
+// Loads are structure-of-arrays, so every load instruction of a wave is one
+// contiguous 256-byte segment per plane.
+#include "fgs_internal.hpp"
+#include "fisheye.hpp"
+
+namespace fgs {
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kDilation = 0.3;
+constexpr double kMaxRadius = 1073741824.0;  // 2^30: keeps the radius an int; the rect is clamped anyway
+
+struct PreArgs {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  uint32_t n;
+  int sh_degree;
+  ViewParams v;
+  double campos[3];
+  float4* splats;
+  uint32_t* depth_keys;
+  uint32_t* tiles;
+  uint2* rects;
+  int32_t* radii;
+  uint32_t* dkeys;
+  uint32_t* dvals;
+};
+
+struct Geometry {
+  double pc[3];
+  FisheyePoint P;
+  double mu[2];
+  double Rq[9];  // rotation of the normalised quaternion
+  double qn[4], qnorm;
+  double s[3];
+  double Sig[6];  // xx xy xz yy yz zz
+  double T[6];    // J W
+  double J[6];
+  double Sp[3];   // dilated 2D covariance: xx xy yy
+  double det;
+  double conic[3];
+};
+
+// Returns false if culled.  Shared by forward and backward so both take the
+// same decisions on the same inputs.
+__device__ inline bool compute_geometry(const float* means, const float* scales, const float* quats,
+                                        const float* opac, uint32_t i, uint32_t n, const ViewParams& v,
+                                        bool need_m, Geometry& G) {
+  const float mf[3] = {means[i], means[n + i], means[2 * n + i]};
+  const float sf[3] = {scales[i], scales[n + i], scales[2 * n + i]};
+  const float qf[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+  const float o = opac[i];
+  bool finite = isfinite(o);
+  for (int a = 0; a < 3; ++a) finite = finite && isfinite(mf[a]) && isfinite(sf[a]);
+  for (int a = 0; a < 4; ++a) finite = finite && isfinite(qf[a]);
+  if (!finite) return false;
+  double q2 = 0.0;
+  for (int a = 0; a < 4; ++a) q2 += (double)qf[a] * (double)qf[a];
+  if (!(q2 > 0.0)) return false;
+  // mu_c = W mu + b, rows summed left to right
+  for (int r = 0; r < 3; ++r)
+    G.pc[r] = ((v.R[r * 3 + 0] * (double)mf[0] + v.R[r * 3 + 1] * (double)mf[1]) + v.R[r * 3 + 2] * (double)mf[2]) +
+              v.t[r];
+  const double x = G.pc[0], y = G.pc[1], z = G.pc[2];
+  const double dist = sqrt((x * x + y * y) + z * z);
+  if (!(dist > v.near_dist)) return false;
+  G.P.x = x;
+  G.P.y = y;
+  G.P.z = z;
+  fisheye_terms(G.P, need_m);
+  if (!(G.P.theta <= v.theta_max)) return false;
+  if (G.P.lz > 0.0) {
+    G.mu[0] = v.cx + v.fx * G.P.theta * x / G.P.lz;
+    G.mu[1] = v.cy + v.fy * G.P.theta * y / G.P.lz;
+  } else {
+    G.mu[0] = v.cx;
+    G.mu[1] = v.cy;
+  }
+  // Sigma = M M^T, M = R S
+  G.qnorm = sqrt(q2);
+  for (int a = 0; a < 4; ++a) G.qn[a] = (double)qf[a] / G.qnorm;
+  quat_to_rot(G.qn, G.Rq);
+  for (int a = 0; a < 3; ++a) G.s[a] = (double)sf[a];
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M[r * 3 + c] = G.Rq[r * 3 + c] * G.s[c];
+  G.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  G.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  G.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  G.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  G.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  fisheye_jacobian(G.P, v.fx, v.fy, G.J);
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c)
+      G.T[r * 3 + c] = G.J[r * 3 + 0] * v.R[0 * 3 + c] + G.J[r * 3 + 1] * v.R[1 * 3 + c] + G.J[r * 3 + 2] * v.R[2 * 3 + c];
+  // Sigma_p = T Sigma T^T
+  double TS[6];
+  for (int r = 0; r < 2; ++r) {
+    const double* t = &G.T[r * 3];
+    TS[r * 3 + 0] = t[0] * G.Sig[0] + t[1] * G.Sig[1] + t[2] * G.Sig[2];
+    TS[r * 3 + 1] = t[0] * G.Sig[1] + t[1] * G.Sig[3] + t[2] * G.Sig[4];
+    TS[r * 3 + 2] = t[0] * G.Sig[2] + t[1] * G.Sig[4] + t[2] * G.Sig[5];
+  }
+  G.Sp[0] = TS[0] * G.T[0] + TS[1] * G.T[1] + TS[2] * G.T[2] + kDilation;
+  G.Sp[1] = TS[0] * G.T[3] + TS[1] * G.T[4] + TS[2] * G.T[5];
+  G.Sp[2] = TS[3] * G.T[3] + TS[4] * G.T[4] + TS[5] * G.T[5] + kDilation;
+  G.det = G.Sp[0] * G.Sp[2] - G.Sp[1] * G.Sp[1];
+  if (!(G.det > 0.0)) return false;
+  G.conic[0] = G.Sp[2] / G.det;
+  G.conic[1] = -G.Sp[1] / G.det;
+  G.conic[2] = G.Sp[0] / G.det;
+  return true;
+}
+
+// Colour from SH in float: rgb_c = sum_k sh[k*3+c] Y_k(dir) + 0.5, clamped at 0.
+__device__ inline void sh_color(const float* sh, int degree, uint32_t i, uint32_t n, const float dir[3], float rgb[3],
+                                float Y[16]) {
+  sh_basis(degree, dir[0], dir[1], dir[2], Y);
+  const int nb = (degree + 1) * (degree + 1);
+  float acc[3] = {0.5f, 0.5f, 0.5f};
+  for (int k = 0; k < nb; ++k)
+    for (int c = 0; c < 3; ++c) acc[c] += sh[(size_t)(k * 3 + c) * n + i] * Y[k];
+  for (int c = 0; c < 3; ++c) rgb[c] = acc[c];
+}
+
+__device__ inline void view_dir(const float* means, uint32_t i, uint32_t n, const double campos[3], float dir[3],
+                                double vdir[3], double& vlen) {
+  for (int a = 0; a < 3; ++a) vdir[a] = (double)means[a * n + i] - campos[a];
+  vlen = sqrt(vdir[0] * vdir[0] + vdir[1] * vdir[1] + vdir[2] * vdir[2]);
+  for (int a = 0; a < 3; ++a) dir[a] = (float)(vdir[a] / vlen);
+}
+
+__global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const uint32_t n = a.n;
+  uint32_t key = 0xFFFFFFFFu, ntiles = 0;
+  uint2 rect = make_uint2(0, 0);
+  int32_t radius = 0;
+  float4 s0 = make_float4(0, 0, 0, 0), s1 = make_float4(0, 0, 0, 0), s2 = make_float4(0, 0, 0, 0);
+  Geometry G;
+  do {
+    if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, false, G)) break;
+    const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
+    const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
+    double rad = ceil(3.0 * sqrt(lam));
+    if (rad > kMaxRadius) rad = kMaxRadius;
+    const double gx = a.v.tiles_x, gy = a.v.tiles_y;
+    const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
+    const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile), vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
+    const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
+    const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
+    const uint32_t area = (x1 - x0) * (y1 - y0);
+    if (area == 0) break;
+    float dir[3], Y[16], rgb[3];
+    double vd[3], vlen;
+    view_dir(a.means, i, n, a.campos, dir, vd, vlen);
+    sh_color(a.sh, a.sh_degree, i, n, dir, rgb, Y);
+    if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) break;
+    const float o = a.opac[i];
+    const double A = G.conic[0], B = G.conic[1];
+    const float hx = (float)G.mu[0], hy = (float)G.mu[1];
+    s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+    s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
+                     (float)(-log2(255.0 * (double)o)));
+    s2 = make_float4(o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+    const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
+    key = __float_as_uint((float)dist);
+    ntiles = area;
+    rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+    radius = (int32_t)rad;
+  } while (false);
+  a.splats[3 * (size_t)i + 0] = s0;
+  a.splats[3 * (size_t)i + 1] = s1;
+  a.splats[3 * (size_t)i + 2] = s2;
+  a.depth_keys[i] = key;
+  a.tiles[i] = ntiles;
+  a.rects[i] = rect;
+  a.radii[i] = radius;
+  a.dkeys[i] = key;
+  a.dvals[i] = i;
+}
+
+// ---------------------------------------------------------------------------
+// Backward.  Inputs per Gaussian: the blend's accumulated dL/d(mu_p, conic A B
+// C, opacity, rgb).  Chain (Sec. 4.2, 4.3):
+//   dL/dSigma' = -Q G Q,  dL/dT = 2 dL/dSigma' T Sigma,
+//   dL/dSigma = T^T dL/dSigma' T,  dL/dJ = dL/dT W^T,
+//   dL/dmu_c = J^T dL/dmu_p + sum_ij dL/dJ_ij dJ_ij/dmu_c,
+//   dL/dmu = W^T dL/dmu_c + colour term;  Sigma -> (s, q) through M = R S.
+// ---------------------------------------------------------------------------
+struct PreBwdArgs {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  uint32_t n;
+  int sh_degree;
+  ViewParams v;
+  double campos[3];
+  const uint32_t* tiles;
+  const float* grad2d;  // [9][n]
+  float* g_means;
+  float* g_scales;
+  float* g_quats;
+  float* g_opac;
+  float* g_sh;
+  float* g_means2d;
+};
+
+__global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs a) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const uint32_t n = a.n;
+  const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+  Geometry G;
+  const bool visible = a.tiles[i] != 0 && compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
+  if (!visible) {
+    for (int c = 0; c < 3; ++c) { a.g_means[c * n + i] = 0.0f; a.g_scales[c * n + i] = 0.0f; }
+    for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = 0.0f;
+    a.g_opac[i] = 0.0f;
+    for (int k = 0; k < 3 * nb; ++k) a.g_sh[(size_t)k * n + i] = 0.0f;
+    if (a.g_means2d) { a.g_means2d[i] = 0.0f; a.g_means2d[n + i] = 0.0f; }
+    return;
+  }
+  const double gmu[2] = {a.grad2d[0 * (size_t)n + i], a.grad2d[1 * (size_t)n + i]};
+  const double gA = a.grad2d[2 * (size_t)n + i], gB = a.grad2d[3 * (size_t)n + i], gC = a.grad2d[4 * (size_t)n + i];
+  const float go = a.grad2d[5 * (size_t)n + i];
+  const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
+  // H = dL/dSigma' = -Q Gs Q with Gs = [[gA, gB/2], [gB/2, gC]]
+  const double Q00 = G.conic[0], Q01 = G.conic[1], Q11 = G.conic[2];
+  const double G00 = gA, G01 = 0.5 * gB, G11 = gC;
+  const double QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
+  const double QG10 = Q01 * G00 + Q11 * G01, QG11 = Q01 * G01 + Q11 * G11;
+  const double H00 = -(QG00 * Q00 + QG01 * Q01);
+  const double H01 = -(QG00 * Q01 + QG01 * Q11);
+  const double H11 = -(QG10 * Q01 + QG11 * Q11);
+  // dL/dT = 2 H T Sigma
+  double HT[6];
+  for (int c = 0; c < 3; ++c) {
+    HT[0 * 3 + c] = H00 * G.T[0 * 3 + c] + H01 * G.T[1 * 3 + c];
+    HT[1 * 3 + c] = H01 * G.T[0 * 3 + c] + H11 * G.T[1 * 3 + c];
+  }
+  const double* S = G.Sig;
+  double dT[6];
+  for (int r = 0; r < 2; ++r) {
+    const double* h = &HT[r * 3];
+    dT[r * 3 + 0] = 2.0 * (h[0] * S[0] + h[1] * S[1] + h[2] * S[2]);
+    dT[r * 3 + 1] = 2.0 * (h[0] * S[1] + h[1] * S[3] + h[2] * S[4]);
+    dT[r * 3 + 2] = 2.0 * (h[0] * S[2] + h[1] * S[4] + h[2] * S[5]);
+  }
+  // dL/dSigma = T^T H T (full symmetric 3x3)
+  double dS[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) dS[r * 3 + c] = G.T[0 * 3 + r] * HT[0 * 3 + c] + G.T[1 * 3 + r] * HT[1 * 3 + c];
+  // dL/dJ = dL/dT W^T
+  double dJ[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c)
+      dJ[r * 3 + c] = dT[r * 3 + 0] * a.v.R[c * 3 + 0] + dT[r * 3 + 1] * a.v.R[c * 3 + 1] + dT[r * 3 + 2] * a.v.R[c * 3 + 2];
+  // dL/dmu_c
+  double gpc[3];
+  for (int c = 0; c < 3; ++c) gpc[c] = G.J[0 * 3 + c] * gmu[0] + G.J[1 * 3 + c] * gmu[1];
+  fisheye_jacobian_vjp(G.P, a.v.fx, a.v.fy, dJ, gpc);
+  double gm[3];
+  for (int c = 0; c < 3; ++c)
+    gm[c] = a.v.R[0 * 3 + c] * gpc[0] + a.v.R[1 * 3 + c] * gpc[1] + a.v.R[2 * 3 + c] * gpc[2];
+  // colour
+  float dir[3], Y[16], rgb[3];
+  double vd[3], vlen;
+  view_dir(a.means, i, n, a.campos, dir, vd, vlen);
+  sh_color(a.sh, a.sh_degree, i, n, dir, rgb, Y);
+  float gcol[3];
+  for (int c = 0; c < 3; ++c) gcol[c] = rgb[c] < 0.0f ? 0.0f : grgb[c];
+  for (int k = 0; k < nb; ++k)
+    for (int c = 0; c < 3; ++c) a.g_sh[(size_t)(k * 3 + c) * n + i] = Y[k] * gcol[c];
+  if (nb > 1) {
+    float dY[16][3];
+    sh_basis_grad(a.sh_degree, dir[0], dir[1], dir[2], dY);
+    float gd[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 1; k < nb; ++k) {
+      float w = 0.0f;
+      for (int c = 0; c < 3; ++c) w += a.sh[(size_t)(k * 3 + c) * n + i] * gcol[c];
+      for (int e = 0; e < 3; ++e) gd[e] += w * dY[k][e];
+    }
+    // d dir / d v = (I - dir dir^T) / |v|
+    const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
+    for (int e = 0; e < 3; ++e) gm[e] += ((double)gd[e] - (double)dir[e] * dd) / vlen;
+  }
+  for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)gm[c];
+  // Sigma = M M^T, M = R S: dL/dM = 2 dS M
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M[r * 3 + c] = G.Rq[r * 3 + c] * G.s[c];
+  double dM[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      dM[r * 3 + c] = 2.0 * (dS[r * 3 + 0] * M[0 * 3 + c] + dS[r * 3 + 1] * M[1 * 3 + c] + dS[r * 3 + 2] * M[2 * 3 + c]);
+  for (int c = 0; c < 3; ++c)
+    a.g_scales[c * n + i] = (float)(dM[0 * 3 + c] * G.Rq[0 * 3 + c] + dM[1 * 3 + c] * G.Rq[1 * 3 + c] +
+                                    dM[2 * 3 + c] * G.Rq[2 * 3 + c]);
+  double dR[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * G.s[c];
+  const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+  double gq[4];
+  gq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  gq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                 2.0 * x * dR[8]);
+  gq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                 2.0 * y * dR[8]);
+  gq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                 y * dR[7]);
+  // through the normalisation q / |q|
+  const double qd = G.qn[0] * gq[0] + G.qn[1] * gq[1] + G.qn[2] * gq[2] + G.qn[3] * gq[3];
+  for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = (float)((gq[c] - G.qn[c] * qd) / G.qnorm);
+  a.g_opac[i] = go;
+  if (a.g_means2d) {
+    a.g_means2d[i] = (float)gmu[0];
+    a.g_means2d[n + i] = (float)gmu[1];
+  }
+}
+
+}  // namespace
+
+static void fill_view(PreArgs& a, const ViewParams& v) {
+  a.v = v;
+  for (int c = 0; c < 3; ++c) a.campos[c] = -(v.R[0 * 3 + c] * v.t[0] + v.R[1 * 3 + c] * v.t[1] + v.R[2 * 3 + c] * v.t[2]);
+}
+
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* ws, const Layout& L,
+                             hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  PreArgs a;
+  a.means = g.means;
+  a.scales = g.scales;
+  a.quats = g.quats;
+  a.opac = g.opacities;
+  a.sh = g.sh;
+  a.n = (uint32_t)g.n;
+  a.sh_degree = g.sh_degree;
+  fill_view(a, v);
+  a.splats = reinterpret_cast<float4*>(ws + L.splats);
+  a.depth_keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
+  a.tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
+  a.rects = reinterpret_cast<uint2*>(ws + L.rects);
+  a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
+  a.dkeys = reinterpret_cast<uint32_t*>(ws + L.dkeys_a);
+  a.dvals = reinterpret_cast<uint32_t*>(ws + L.dvals_a);
+  const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
+  hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& v, const char* ws,
+                                      const Layout& L, const fgs_grads& out, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  PreBwdArgs a;
+  a.means = g.means;
+  a.scales = g.scales;
+  a.quats = g.quats;
+  a.opac = g.opacities;
+  a.sh = g.sh;
+  a.n = (uint32_t)g.n;
+  a.sh_degree = g.sh_degree;
+  a.v = v;
+  for (int c = 0; c < 3; ++c) a.campos[c] = -(v.R[0 * 3 + c] * v.t[0] + v.R[1 * 3 + c] * v.t[1] + v.R[2 * 3 + c] * v.t[2]);
+  a.tiles = reinterpret_cast<const uint32_t*>(ws + L.tiles);
+  a.grad2d = reinterpret_cast<const float*>(ws + L.grad2d);
+  a.g_means = out.means;
+  a.g_scales = out.scales;
+  a.g_quats = out.quats;
+  a.g_opac = out.opacities;
+  a.g_sh = out.sh;
+  a.g_means2d = out.means2d;
+  const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
+  hipLaunchKernelGGL(preprocess_backward_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fgs

@@ -1,0 +1,156 @@
+"""PyTorch-facing entry points.
+
+PyTorch supplies device memory (tensors, the workspace) and the stream; every
+step of the rasterizer runs in libfgs through the C ABI.  Tensors must be
+float32, contiguous, on the GPU, in the structure-of-arrays layout of
+include/fgs.h: means [3, N], scales [3, N], quats [4, N], opacities [N],
+sh [S, N].
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib as L
+
+FGS_SAVE_PIXEL_STATE = L.FGS_SAVE_PIXEL_STATE
+
+
+def _check_param(name, t, rows, n):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous float32")
+    shape = (rows, n) if rows else (n,)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+
+
+def gaussians_struct(means, scales, quats, opacities, sh, sh_degree: int) -> L.fgs_gaussians:
+    n = int(means.shape[1]) if means.dim() == 2 else -1
+    S = 3 * (sh_degree + 1) ** 2
+    _check_param("means", means, 3, n)
+    _check_param("scales", scales, 3, n)
+    _check_param("quats", quats, 4, n)
+    _check_param("opacities", opacities, 0, n)
+    _check_param("sh", sh, S, n)
+    return L.fgs_gaussians(means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacities.data_ptr(),
+                           sh.data_ptr(), n, sh_degree)
+
+
+def camera_struct(cam) -> L.fgs_camera:
+    return L.fgs_camera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                        int(getattr(cam, "model", 0)), float(cam.near), float(cam.theta_max))
+
+
+def pose_struct(pose) -> L.fgs_pose:
+    R = [float(v) for v in torch.as_tensor(pose.R, dtype=torch.float64).reshape(9).tolist()]
+    t = [float(v) for v in torch.as_tensor(pose.t, dtype=torch.float64).reshape(3).tolist()]
+    return L.fgs_pose((ctypes.c_double * 9)(*R), (ctypes.c_double * 3)(*t))
+
+
+class Workspace:
+    """Device scratch of one view, owned by PyTorch.  Keep it alive from a
+    forward to its backward; it grows when a view needs more intersections."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.buf: torch.Tensor | None = None
+
+    @property
+    def nbytes(self) -> int:
+        return 0 if self.buf is None else int(self.buf.numel())
+
+    @property
+    def ptr(self) -> int:
+        return 0 if self.buf is None else int(self.buf.data_ptr())
+
+    def ensure(self, nbytes: int) -> None:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+
+    def layout(self, n: int, width: int, height: int) -> L.fgs_layout:
+        return L.fgs_workspace_layout(n, width, height, self.nbytes)
+
+    def view(self, offset: int, count: int, dtype: torch.dtype) -> torch.Tensor:
+        """A typed view of `count` elements at byte `offset`."""
+        size = torch.empty((), dtype=dtype).element_size()
+        return self.buf[offset:offset + count * size].view(dtype)
+
+
+def _stream_handle(device) -> int:
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg=(0.0, 0.0, 0.0),
+                   workspace: Workspace | None = None, save_pixel_state: bool = False, out: torch.Tensor | None = None,
+                   k_hint: int | None = None):
+    """Render one view.  Returns (image [3, H, W], workspace, K)."""
+    g = gaussians_struct(means, scales, quats, opacities, sh, sh_degree)
+    c = camera_struct(cam)
+    p = pose_struct(pose)
+    dev = means.device
+    ws = workspace if workspace is not None else Workspace(dev)
+    if out is None:
+        out = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+    if ws.buf is None:
+        kcap = k_hint if k_hint is not None else 8 * g.n + 65536
+        ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, kcap))
+    flags = FGS_SAVE_PIXEL_STATE if save_pixel_state else 0
+    for _ in range(3):
+        rc, K = L.fgs_render_forward(g, p, c, bg, flags, ws.ptr, ws.nbytes, out.data_ptr(), _stream_handle(dev))
+        if rc == L.FGS_ERR_WORKSPACE and K >= 0:
+            ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, int(math.ceil(K * 1.15)) + 65536))
+            continue
+        L.check(rc)
+        return out, ws, K
+    raise L.FgsError(L.FGS_ERR_WORKSPACE, "workspace did not converge")
+
+
+def render_backward(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg, workspace: Workspace,
+                    dL_dimg: torch.Tensor, want_means2d: bool = False) -> dict:
+    """Gradients of one view for the workspace of its forward."""
+    g = gaussians_struct(means, scales, quats, opacities, sh, sh_degree)
+    if not dL_dimg.is_contiguous() or dL_dimg.dtype != torch.float32 or tuple(dL_dimg.shape) != (3, cam.height, cam.width):
+        raise ValueError("dL_dimg must be contiguous float32 [3, H, W]")
+    out = dict(means=torch.empty_like(means), scales=torch.empty_like(scales), quats=torch.empty_like(quats),
+               opacities=torch.empty_like(opacities), sh=torch.empty_like(sh))
+    if want_means2d:
+        out["means2d"] = torch.empty((2, g.n), dtype=torch.float32, device=means.device)
+    gr = L.fgs_grads(out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(),
+                     out["opacities"].data_ptr(), out["sh"].data_ptr(),
+                     out["means2d"].data_ptr() if want_means2d else None)
+    rc = L.fgs_render_backward(g, pose_struct(pose), camera_struct(cam), bg, workspace.ptr,
+                               workspace.nbytes, dL_dimg.data_ptr(), gr, _stream_handle(means.device))
+    L.check(rc)
+    return out
+
+
+class _FisheyeRasterize(torch.autograd.Function):
+    """Forward keeps the sorted lists and 2D records in the workspace but no
+    per-pixel transmittance; the backward recomputes it with a front-to-back
+    re-sweep before the reverse pass."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, workspace):
+        img, ws, K = render_forward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, workspace)
+        ctx.save_for_backward(means, scales, quats, opacities, sh)
+        ctx.meta = (sh_degree, pose, cam, bg, ws)
+        return img
+
+    @staticmethod
+    def backward(ctx, dL):
+        means, scales, quats, opacities, sh = ctx.saved_tensors
+        sh_degree, pose, cam, bg, ws = ctx.meta
+        g = render_backward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, ws, dL.contiguous())
+        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None, None
+
+
+def rasterize(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg=(0.0, 0.0, 0.0),
+              workspace: Workspace | None = None) -> torch.Tensor:
+    """Differentiable fisheye render of one view, [3, H, W]."""
+    return _FisheyeRasterize.apply(means, scales, quats, opacities, sh, sh_degree, pose, cam, tuple(bg),
+                                   workspace if workspace is not None else Workspace(means.device))

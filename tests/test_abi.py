@@ -1,0 +1,98 @@
+"""The C-ABI library loads, exports every symbol include/fgs.h declares with
+the signatures the binding uses, and its host-only entry points behave
+(layout arithmetic, argument validation).  No GPU work is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_04751_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fgs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(fgs_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    assert names == sorted(L.SIGNATURES), names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_c_layout():
+    # natural C alignment on x86-64: int32 pairs then doubles
+    assert ctypes.sizeof(L.fgs_camera) == 4 + 4 + 8 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(L.fgs_pose) == 12 * 8
+    assert ctypes.sizeof(L.fgs_gaussians) == 5 * 8 + 8 + 8
+    assert ctypes.sizeof(L.fgs_grads) == 6 * 8
+
+
+def test_version_and_workspace_arithmetic():
+    assert "gfx950" in L.fgs_version()
+    b0 = L.fgs_workspace_bytes(1000, 256, 256, 0)
+    b1 = L.fgs_workspace_bytes(1000, 256, 256, 10000)
+    assert b1 > b0 and (b1 - b0) >= 16 * 10000
+    lay = L.fgs_workspace_layout(1000, 256, 256, b1)
+    assert lay.k_capacity >= 10000 and lay.bytes <= b1
+    assert lay.tiles_x == 16 and lay.tiles_y == 16
+    offs = [lay.splats, lay.depth_keys, lay.tiles, lay.rects, lay.radii, lay.depth_order, lay.offsets,
+            lay.tile_keys, lay.tile_ids, lay.ranges, lay.grad2d, lay.pixel_T, lay.pixel_last, lay.counters]
+    assert all(o % 256 == 0 for o in offs)
+    assert len(set(offs)) == len(offs)
+    # 256 tiles = 8 key bits, one radix pass: the sorted pairs end in the second buffer
+    lay2 = L.fgs_workspace_layout(1000, 4096, 16, b1 * 2)
+    assert lay2.tiles_x == 256 and lay2.tiles_y == 1
+
+
+def test_workspace_too_small():
+    with pytest.raises(L.FgsError) as e:
+        L.fgs_workspace_layout(10**6, 1752, 1168, 1024)
+    assert e.value.code == L.FGS_ERR_WORKSPACE
+
+
+def _structs(n=10, deg=0, width=64, height=48, theta_max=2.0, model=0):
+    g = L.fgs_gaussians(1, 1, 1, 1, 1, n, deg)  # dummy non-null pointers, never dereferenced
+    cam = L.fgs_camera(width, height, 30.0, 30.0, width / 2, height / 2, model, 0.2, theta_max)
+    pose = L.fgs_pose((ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1), (ctypes.c_double * 3)(0, 0, 0))
+    return g, pose, cam
+
+
+@pytest.mark.parametrize("bad", ["degree", "n", "size", "model", "theta", "nullptr", "flags"])
+def test_forward_rejects_bad_arguments_before_any_gpu_call(bad):
+    g, pose, cam = _structs()
+    flags = 0
+    if bad == "degree":
+        g.sh_degree = 4
+    elif bad == "n":
+        g.n = -1
+    elif bad == "size":
+        cam.width = 0
+    elif bad == "model":
+        cam.model = 7
+    elif bad == "theta":
+        cam.theta_max = 3.5
+    elif bad == "nullptr":
+        g.means = None
+    elif bad == "flags":
+        flags = 8
+    rc, _ = L.fgs_render_forward(g, pose, cam, (0, 0, 0), flags, 1, 1 << 30, 1, 0)
+    assert rc == L.FGS_ERR_ARG
+    assert L.fgs_last_error() != ""
+
+
+def test_backward_rejects_null_gradients():
+    g, pose, cam = _structs()
+    grads = L.fgs_grads(None, None, None, None, None, None)
+    rc = L.fgs_render_backward(g, pose, cam, (0, 0, 0), 1, 1 << 30, 1, grads, 0)
+    assert rc == L.FGS_ERR_ARG

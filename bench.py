@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Fisheye Gaussian-splatting fwd+bwd benchmark on one MI355X.
+
+Workload (the headline configuration): 3,000,000 Gaussians, SH degree 3,
+fp32 parameters, means uniform in a 10 x 4 x 10 m room, log-scales
+N(-4, 0.7) with 1% large N(-1, 0.5), one 1752x1168 equidistant-fisheye view
+at 180 deg from the room centre, L1 loss against a seeded random target.
+
+One step = one view through the differentiable rasterizer: preprocess, depth
+sort, tile duplication, tile sort, ranges, blend, then the backward with
+transmittance recomputation (blend backward, preprocess backward), driven by
+torch autograd with the L1 loss.  Inputs are resident in HBM before timing.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/view @3M Gaussians 1752×1168; served views/s + p99 vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | None:
+    """Algorithmic HBM bytes of ONE launch of `name` (byte model)."""
+    if name == "preprocess":
+        return 44.0 * N + 4.0 * S * V + 76.0 * N
+    if name == "depth_sort_scatter":
+        return 16.0 * N
+    if name == "depth_sort_hist":
+        return 4.0 * N
+    if name == "duplicate":
+        return 20.0 * V + 8.0 * K
+    if name == "tile_sort_hist":
+        return 4.0 * K
+    if name == "tile_sort_scatter":
+        return 16.0 * K
+    if name == "ranges":
+        return 4.0 * K
+    if name == "preprocess_backward":
+        return (44.0 + 4.0 * S + 40.0) * V + (44.0 + 4.0 * S) * N
+    return None
+
+
+def traffic_for(kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2409_04751_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(scene, pose, cam, target):
+    """The oracle (plain fp64 C, OpenMP) timed on the host on one full view."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ora = oracle.render(scene, pose, cam)
+    g = (np.sign(ora["image"] - target) / ora["image"].size).astype(np.float32)
+    oracle.render_backward(scene, pose, cam, ora, g)
+    dt = time.perf_counter() - t0
+    return dict(value=dt * 1000.0, unit="ms/view", cores=threads, kind="oracle",
+                sample="1 full view of the same workload (fwd + bwd, fp64), OMP threads = cores")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the fisheye rasterizer has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2409_04751_amd import _lib as L
+    from paper_2409_04751_amd import render as R
+    from paper_2409_04751_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    scene = synth.room_scene(args.n, 0, 0.01, 3)
+    cam = synth.fisheye_camera(1752, 1168, 180.0)
+    pose = synth.identity_pose()
+    target_np = synth.target_image(cam.width, cam.height, 1)
+    log(f"scene generated in {time.perf_counter() - t:.1f}s")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    leaves = [f(a).requires_grad_(True) for a in (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
+    target = f(target_np)
+    deg = scene.sh_degree
+    ws = R.Workspace(dev)
+    bg = (0.0, 0.0, 0.0)
+    stats = {}
+
+    def step():
+        img = R.rasterize(*leaves, deg, pose, cam, bg, ws)
+        loss = (img - target).abs().mean()
+        grads = torch.autograd.grad(loss, leaves)
+        return loss, grads
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    if not args.no_profile:
+        L.fgs_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    if not args.no_profile:
+        prof = L.fgs_profile_read()
+        L.fgs_profile_enable(False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
+
+    # counts of the workload (from the library's own state)
+    _, ws2, K = R.render_forward(*[x.detach() for x in leaves], deg, pose, cam, bg)
+    lay = ws2.layout(scene.n, cam.width, cam.height)
+    tiles = ws2.view(lay.tiles, scene.n, torch.int32)
+    V = int((tiles > 0).sum().item())
+    N, P, S = scene.n, cam.width * cam.height, scene.sh.shape[0]
+
+    kernels = {k: dict(launches=v[0] // args.steps if args.steps else 0, ms=v[1] / args.steps,
+                       avg_ms=v[1] / max(v[0], 1)) for k, v in prof.items()}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["ms"])
+        d = kernels[dom]
+        b = kernel_bytes(dom, N, V, K, P, S)
+        if b is not None:
+            ach = b / (d["avg_ms"] * 1e-3) / 1e9
+            roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for(dom),
+                            bytes_per_launch=b, avg_launch_ms=round(d["avg_ms"], 5))
+        else:
+            roofline = dict(kernel=dom, bound="alu", achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=None, traffic=traffic_for(dom), avg_launch_ms=round(d["avg_ms"], 5))
+        for k, v in kernels.items():
+            bb = kernel_bytes(k, N, V, K, P, S)
+            if bb is not None:
+                v["GBs"] = round(bb * v["launches"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None
+            v["ms"] = round(v["ms"], 5)
+            v["avg_ms"] = round(v["avg_ms"], 5)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        cpu = cpu_baseline(scene, pose, cam, target_np)
+        cpu["value"] = round(cpu["value"], 1)
+        log(f"oracle: {cpu['value']:.0f} ms/view on {cpu['cores']} threads")
+
+    out = dict(metric=METRIC, value=round(ms, 4), unit="ms/view", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(ms, 4), higher_is_better=False, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload="room3m_fisheye1752x1168_180deg", gaussians=N, sh_degree=3, width=cam.width,
+                           height=cam.height, fov_deg=180.0, views_per_step=1, visible=V, intersections=K,
+                           geometry_dtype="f64"),
+               roofline=roofline, cpu_baseline=cpu, kernels=kernels)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

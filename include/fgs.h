@@ -171,6 +171,25 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
                         void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
                         void* stream);
 
+/*
+ * Per-kernel timing with HIP events, for benchmarks and tracing.  While
+ * enabled, every kernel launch of the library is bracketed by two events
+ * recorded on the stream it is launched on; fgs_profile_read waits for the
+ * recorded events and returns the accumulated milliseconds and launch count
+ * per kernel.  Turning recording on clears earlier data.  Process-wide, not
+ * meant for concurrent calls from several threads.
+ */
+#define FGS_PROF_MAX_KERNELS 32
+typedef struct fgs_profile {
+  int32_t count;                                /* kernels listed */
+  const char* names[FGS_PROF_MAX_KERNELS];      /* static strings */
+  int64_t launches[FGS_PROF_MAX_KERNELS];
+  double total_ms[FGS_PROF_MAX_KERNELS];
+} fgs_profile;
+
+int fgs_profile_enable(int32_t on);
+int fgs_profile_read(fgs_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -173,13 +173,23 @@ def blend_bruteforce(pre: dict, cam, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
     return image
 
 
-def blend_backward(pre: dict, bins: dict, cam, dL_dimg, bg=(0.0, 0.0, 0.0)) -> dict:
+def blend_backward(pre: dict, bins: dict, cam, dL_dimg, bg=(0.0, 0.0, 0.0), abs_sums: bool = False) -> dict:
+    """Per-Gaussian 2D gradients; with abs_sums also `abs` [n, 9] (operand
+    magnitudes summed over pixels) and `pos` [n, 9] (sensitivity to the pixel
+    offset) for (mu_x, mu_y, A, B, C, o, r, g, b)."""
     n = pre["visible"].shape[0]
     g = dict(mu_p=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+    if abs_sums:
+        g["abs18"] = np.zeros((n, 18))
     vals = bins["vals"] if bins["K"] > 0 else np.zeros(1, np.uint32)
     lib().orc_blend_backward(ctypes.c_int32(cam.width), ctypes.c_int32(cam.height), _p(bins["ranges"]), _p(vals),
                              _p(pre["mu_p"]), _p(pre["conic"]), _p(pre["opacity"]), _p(pre["rgb"]), _p(_f32(bg)),
-                             _p(_f32(dL_dimg)), _p(g["mu_p"]), _p(g["conic"]), _p(g["opacity"]), _p(g["rgb"]))
+                             _p(_f32(dL_dimg)), _p(g["mu_p"]), _p(g["conic"]), _p(g["opacity"]), _p(g["rgb"]),
+                             _p(g["abs18"]) if abs_sums else None)
+    if abs_sums:
+        g["abs"] = np.ascontiguousarray(g["abs18"][:, :9])
+        g["pos"] = np.ascontiguousarray(g["abs18"][:, 9:])
+        del g["abs18"]
     return g
 
 
@@ -208,8 +218,8 @@ def render(scene, pose, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL) -> dict:
     return out
 
 
-def render_backward(scene, pose, cam, fwd: dict, dL_dimg, bg=(0.0, 0.0, 0.0)) -> dict:
-    g2d = blend_backward(fwd["pre"], fwd["bins"], cam, dL_dimg, bg)
+def render_backward(scene, pose, cam, fwd: dict, dL_dimg, bg=(0.0, 0.0, 0.0), abs_sums: bool = False) -> dict:
+    g2d = blend_backward(fwd["pre"], fwd["bins"], cam, dL_dimg, bg, abs_sums)
     grads = preprocess_backward(scene, pose, cam, fwd["pre"], g2d)
     grads["g2d"] = g2d
     return grads

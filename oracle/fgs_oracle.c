@@ -610,12 +610,18 @@ void orc_blend_bruteforce(int64_t n, int32_t width, int32_t height, const uint8_
 /* ------------------------------------------------------------------------ */
 /* Blend backward: exact derivatives of walk_pixel, per pixel last to first. */
 /* Outputs per Gaussian (accumulated, caller zeroes): g_mu_p [n][2],          */
-/* g_conic [n][3] (d/dA, d/dB, d/dC), g_opac [n], g_rgb [n][3].               */
+/* g_conic [n][3] (d/dA, d/dB, d/dC), g_opac [n], g_rgb [n][3].  If g_abs     */
+/* is not NULL it receives [n][18]: per Gaussian and component in the order   */
+/* (mu_x, mu_y, A, B, C, o, r, g, b), first the sum over pixels of the         */
+/* magnitudes of each term's operands (|rgb| + |B| in place of rgb - B), the   */
+/* scale of the rounding error of any floating-point evaluation; then the sum  */
+/* of |d term / d delta_x| + |d term / d delta_y|, the sensitivity of each     */
+/* term to the rounding of the pixel offset delta = mu_p - pixel.              */
 /* ------------------------------------------------------------------------ */
 void orc_blend_backward(int32_t width, int32_t height, const uint32_t* ranges, const uint32_t* vals,
                         const double* mu_p, const double* conic, const double* opac, const double* rgb,
                         const float bg[3], const float* dL_dimg, double* g_mu_p, double* g_conic, double* g_opac,
-                        double* g_rgb) {
+                        double* g_rgb, double* g_abs) {
   const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
   orc_tol tol = {0, 0, 0};
 #pragma omp parallel
@@ -647,12 +653,17 @@ void orc_blend_backward(int32_t width, int32_t height, const uint32_t* ranges, c
             const contrib* r = &rec[k];
             uint32_t g = r->id;
             double a = r->alpha, Ti = r->T;
-            double dLda = 0;
+            double dLda = 0, dLda_abs = 0;
             for (int c = 0; c < 3; ++c) {
               double col = rgb[g * 3 + c];
 #pragma omp atomic
               g_rgb[g * 3 + c] += a * Ti * G[c];
+              if (g_abs) {
+#pragma omp atomic
+                g_abs[g * 18 + 6 + c] += fabs(a * Ti * G[c]);
+              }
               dLda += Ti * (col - Bk[c]) * G[c];
+              dLda_abs += Ti * (fabs(col) + fabs(Bk[c])) * fabs(G[c]);
               Bk[c] = a * col + (1.0 - a) * Bk[c];
             }
             if (r->clampd) continue; /* alpha = 0.99 does not depend on o or q */
@@ -672,6 +683,23 @@ void orc_blend_backward(int32_t width, int32_t height, const uint32_t* ranges, c
             g_conic[g * 3 + 1] += dLdq * -dx * dy;
 #pragma omp atomic
             g_conic[g * 3 + 2] += dLdq * -0.5 * dy * dy;
+            if (g_abs) {
+              /* magnitudes of the operands, not of the result: dL/dalpha
+               * carries the difference rgb - B */
+              const double q_abs = dLda_abs * a, o_abs = dLda_abs * r->eq;
+              const double t[6] = {q_abs * (fabs(A * dx) + fabs(B * dy)), q_abs * (fabs(B * dx) + fabs(Cc * dy)),
+                                   q_abs * 0.5 * dx * dx, q_abs * fabs(dx * dy), q_abs * 0.5 * dy * dy, o_abs};
+              const double p[5] = {q_abs * (fabs(A) + fabs(B)), q_abs * (fabs(B) + fabs(Cc)), q_abs * fabs(dx),
+                                   q_abs * (fabs(dx) + fabs(dy)), q_abs * fabs(dy)};
+              for (int e = 0; e < 6; ++e) {
+#pragma omp atomic
+                g_abs[g * 18 + e] += t[e];
+              }
+              for (int e = 0; e < 5; ++e) {
+#pragma omp atomic
+                g_abs[g * 18 + 9 + e] += p[e];
+              }
+            }
           }
         }
     }

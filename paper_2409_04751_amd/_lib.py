@@ -53,6 +53,15 @@ class fgs_layout(ctypes.Structure):
                 ("pixel_last", c_size), ("counters", c_size)]
 
 
+FGS_PROF_MAX_KERNELS = 32
+
+
+class fgs_profile(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("names", ctypes.c_char_p * FGS_PROF_MAX_KERNELS),
+                ("launches", ctypes.c_int64 * FGS_PROF_MAX_KERNELS),
+                ("total_ms", ctypes.c_double * FGS_PROF_MAX_KERNELS)]
+
+
 # Exported symbols, argtypes and restype.  Kept in one table so a CPU test can
 # check it against the header.
 SIGNATURES = {
@@ -68,6 +77,8 @@ SIGNATURES = {
     "fgs_render_backward": ([ctypes.POINTER(fgs_gaussians), ctypes.POINTER(fgs_pose), ctypes.POINTER(fgs_camera),
                              ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, c_size, ctypes.c_void_p,
                              ctypes.POINTER(fgs_grads), ctypes.c_void_p], ctypes.c_int),
+    "fgs_profile_enable": ([ctypes.c_int32], ctypes.c_int),
+    "fgs_profile_read": ([ctypes.POINTER(fgs_profile)], ctypes.c_int),
 }
 
 _lib = None
@@ -137,3 +148,15 @@ def fgs_render_backward(g: fgs_gaussians, pose: fgs_pose, cam: fgs_camera, bg, w
                         dL_drgb: int, grads: fgs_grads, stream: int) -> int:
     return lib().fgs_render_backward(ctypes.byref(g), ctypes.byref(pose), ctypes.byref(cam), _bg(bg), workspace,
                                      workspace_bytes, dL_drgb, ctypes.byref(grads), stream)
+
+
+def fgs_profile_enable(on: bool) -> None:
+    check(lib().fgs_profile_enable(1 if on else 0))
+
+
+def fgs_profile_read() -> dict:
+    """{kernel name: (launches, total ms)} for kernels launched while enabled."""
+    out = fgs_profile()
+    check(lib().fgs_profile_read(ctypes.byref(out)))
+    return {out.names[k].decode(): (int(out.launches[k]), float(out.total_ms[k])) for k in range(out.count)
+            if out.launches[k] > 0}

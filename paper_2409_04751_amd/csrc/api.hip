@@ -58,15 +58,19 @@ Layout make_layout(int64_t n, int32_t width, int32_t height, int64_t kcap) {
   L.radii = take(nn * 4);
   L.dkeys_a = take(nn * 4);
   L.dvals_a = take(nn * 4);
+  L.drx_a = take(nn * 4);
+  L.dry_a = take(nn * 4);
   L.dkeys_b = take(nn * 4);
   L.dvals_b = take(nn * 4);
+  L.drx_b = take(nn * 4);
+  L.dry_b = take(nn * 4);
   L.offsets = take(nn * 4);
   L.grad2d = take(nn * 9 * 4);
   L.ranges = take((size_t)ntiles * 8);
   L.pixel_T = take((size_t)P * 4);
   L.pixel_last = take((size_t)P * 4);
   const int64_t kk = kcap > 0 ? kcap : 1;
-  const int64_t nb_max = ceil_div(std::max<int64_t>((int64_t)nn, kk), kItemsPerBlock);
+  const int64_t nb_max = std::max(radix_blocks((int64_t)nn, 3), radix_blocks(kk, 1));
   L.hist = take((size_t)nb_max * kRadix * 4);
   const int64_t scan_items = std::max<int64_t>({(int64_t)nn, nb_max * kRadix});
   L.partials = take((size_t)(ceil_div(scan_items, kItemsPerBlock) + 1) * 4);
@@ -221,17 +225,24 @@ int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_c
   HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
   HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
   HIP_TRY(launch_preprocess(*g, v, ws, L, s), "preprocess");
-  bool in_b = false;
-  HIP_TRY(launch_radix_sort(reinterpret_cast<uint32_t*>(ws + L.dkeys_a), reinterpret_cast<uint32_t*>(ws + L.dvals_a),
-                            reinterpret_cast<uint32_t*>(ws + L.dkeys_b), reinterpret_cast<uint32_t*>(ws + L.dvals_b), n,
-                            32, reinterpret_cast<uint32_t*>(ws + L.hist), reinterpret_cast<uint32_t*>(ws + L.partials),
-                            &in_b, s),
-          "depth sort");
-  // 4 passes: the depth order ends in dvals_a
-  const uint32_t* depth_order = reinterpret_cast<const uint32_t*>(ws + L.dvals_a);
-  HIP_TRY(launch_scan(reinterpret_cast<const uint32_t*>(ws + L.tiles), depth_order,
-                      reinterpret_cast<uint32_t*>(ws + L.offsets), n, reinterpret_cast<uint32_t*>(ws + L.partials),
-                      counters + kCountK, s),
+  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  uint32_t* partials = U(L.partials);
+  uint32_t* hist = U(L.hist);
+  const uint32_t* d_visible = counters + kCountVisible;
+  // stable compaction of the visible Gaussians (id order); offsets holds the
+  // positions until the tile-count scan reuses it
+  HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, n, kScanFlag, partials, counters + kCountVisible, U(L.offsets), s),
+          "visibility scan");
+  HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects), U(L.offsets), n,
+                         U(L.dkeys_a), U(L.dvals_a), U(L.drx_a), U(L.dry_a), s),
+          "compact");
+  // depth sort of the visible Gaussians carrying (id, rect); positive float
+  // bits use 31 key bits -> 4 passes, result back in the *_a planes
+  RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
+                  {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
+  HIP_TRY(launch_radix_sort(DB, d_visible, n, 31, hist, partials, s, kKDepthHist, kKDepthScatter), "depth sort");
+  HIP_TRY(launch_scan(U(L.drx_a), U(L.dry_a), d_visible, n, kScanRectArea, partials, counters + kCountK, U(L.offsets),
+                      s),
           "tile count scan");
   uint32_t K32 = 0;
   HIP_TRY(hipMemcpyAsync(&K32, counters + kCountK, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read K");
@@ -245,20 +256,13 @@ int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_c
                   (long long)K);
     return fail(FGS_ERR_WORKSPACE, msg);
   }
-  HIP_TRY(launch_duplicate(depth_order, reinterpret_cast<const uint32_t*>(ws + L.tiles),
-                           reinterpret_cast<const uint32_t*>(ws + L.offsets),
-                           reinterpret_cast<const uint2*>(ws + L.rects), n, L.tiles_x,
-                           reinterpret_cast<uint32_t*>(ws + L.tkeys_a), reinterpret_cast<uint32_t*>(ws + L.tvals_a), s),
+  HIP_TRY(launch_duplicate(U(L.dvals_a), U(L.drx_a), U(L.dry_a), U(L.offsets), d_visible, n, L.tiles_x, U(L.tkeys_a),
+                           U(L.tvals_a), s),
           "duplicate");
-  HIP_TRY(launch_radix_sort(reinterpret_cast<uint32_t*>(ws + L.tkeys_a), reinterpret_cast<uint32_t*>(ws + L.tvals_a),
-                            reinterpret_cast<uint32_t*>(ws + L.tkeys_b), reinterpret_cast<uint32_t*>(ws + L.tvals_b), K,
-                            L.tile_bits, reinterpret_cast<uint32_t*>(ws + L.hist),
-                            reinterpret_cast<uint32_t*>(ws + L.partials), &in_b, s),
-          "tile sort");
-  const uint32_t* keys = reinterpret_cast<const uint32_t*>(ws + (in_b ? L.tkeys_b : L.tkeys_a));
-  const uint32_t* ids = reinterpret_cast<const uint32_t*>(ws + (in_b ? L.tvals_b : L.tvals_a));
-  if ((in_b ? L.tkeys_b : L.tkeys_a) != L.tile_keys_final)
-    return fail(FGS_ERR_HIP, "internal: tile sort result buffer disagrees with the layout");
+  RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
+  HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter), "tile sort");
+  const uint32_t* keys = U(L.tile_keys_final);
+  const uint32_t* ids = U(L.tile_ids_final);
   uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);
   HIP_TRY(launch_ranges(keys, K, ranges, ntiles, s), "ranges");
   HIP_TRY(launch_blend_forward(v, ranges, ids, reinterpret_cast<const float4*>(ws + L.splats), out_rgb,

@@ -142,10 +142,48 @@ struct BlendBwdArgs {
   uint32_t n;
 };
 
-__device__ inline float wave_sum(float v) {
+// DPP lane exchange inside each 16-lane row (all patterns are permutations,
+// so every lane has a valid source).
+template <int CTRL>
+__device__ inline float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppRowMirror = 0x140;      // lane i <- lane 15 - i   (partner differs in bit 3)
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <- lane 7 - i    (same bit 3, differs in bit 2)
+constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2,3,0,1]     (differs in bit 1 only)
+constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1,0,3,2]     (differs in bit 0 only)
+
+// Reduce-scatter of 9 per-lane values over the 16 lanes of each row by
+// recursive halving: at each step a lane keeps half of its value slots and
+// adds its partner's copy of them.  Afterwards the lane with row position
+// (b3 b2 b1 b0) holds the row sum of value (b3 ? 5 : 0) + (b2 ? 3 : 0) +
+// (b1 ? 2 : 0) + b0; positions outside kRowValid hold padding.
+constexpr uint32_t kRowValid = 0x1737u;  // positions 0,1,2,4,5,8,9,10,12 -> values 0..8
+
+__device__ inline float row_reduce_scatter9(const float v[9], bool b3, bool b2, bool b1, bool b0) {
+  float K[5];
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  for (int s = 0; s < 5; ++s) {
+    const float lo = v[s], hi = (s + 5 < 9) ? v[s + 5] : 0.0f;
+    const float keep = b3 ? hi : lo, send = b3 ? lo : hi;
+    K[s] = keep + dpp<kDppRowMirror>(send);
+  }
+  float L[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const float lo = K[s], hi = (s + 3 < 5) ? K[s + 3] : 0.0f;
+    const float keep = b2 ? hi : lo, send = b2 ? lo : hi;
+    L[s] = keep + dpp<kDppRowHalfMirror>(send);
+  }
+  float M[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const float lo = L[s], hi = (s + 2 < 3) ? L[s + 2] : 0.0f;
+    const float keep = b1 ? hi : lo, send = b1 ? lo : hi;
+    M[s] = keep + dpp<kDppQuadXor2>(send);
+  }
+  const float keep = b0 ? M[1] : M[0], send = b0 ? M[0] : M[1];
+  return keep + dpp<kDppQuadXor1>(send);
 }
 
 __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) {
@@ -217,6 +255,11 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
   }
   float B0 = a.bg[0], B1 = a.bg[1], B2 = a.bg[2];  // colour behind the current Gaussian
   float Tc = T;
+  // this lane's slot in the row reduce-scatter
+  const uint32_t rpos = threadIdx.x & 15u;
+  const bool rb3 = (rpos >> 3) & 1u, rb2 = (rpos >> 2) & 1u, rb1 = (rpos >> 1) & 1u, rb0 = rpos & 1u;
+  const int rval = (rb3 ? 5 : 0) + (rb2 ? 3 : 0) + (rb1 ? 2 : 0) + (rb0 ? 1 : 0);
+  const bool rvalid = (kRowValid >> rpos) & 1u;
   for (int end = (int)maxlast; end > 0; end -= kBlock) {
     const int beg = max(end - kBlock, 0);
     __syncthreads();
@@ -241,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
           const float eq = __builtin_amdgcn_exp2f(q2);
           const float raw = gb.z * eq;
           const float alpha = fminf(kAlphaMax, raw);
-          const float Ti = Tc / (1.0f - alpha);
+          const float Ti = Tc * __builtin_amdgcn_rcpf(1.0f - alpha);
           const float w = alpha * Ti;
           const float2 gc = sc[idx];
           v[6] = w * G0;
@@ -266,9 +309,9 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
         }
       }
       if (__ballot(contrib) != 0ull) {
-        for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
-        if ((threadIdx.x & 63) == 0)
-          for (int k = 0; k < 9; ++k) atomicAdd(&acc[k][idx], v[k]);
+        // wave-uniform: every lane takes part in the DPP exchanges
+        const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
+        if (rvalid) atomicAdd(&acc[rval][idx], part);
       }
     }
     __syncthreads();
@@ -299,6 +342,7 @@ hipError_t launch_blend_forward(const ViewParams& v, const uint2* ranges, const 
   a.pixel_last = pixel_last;
   a.save = save ? 1 : 0;
   const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  ProfScope prof(s, kKBlendForward);
   hipLaunchKernelGGL(blend_forward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -321,6 +365,7 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.grad2d = grad2d;
   a.n = (uint32_t)n;
   const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  ProfScope prof(s, kKBlendBackward);
   hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

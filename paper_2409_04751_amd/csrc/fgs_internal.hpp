@@ -16,6 +16,57 @@ constexpr int kItemsPerThread = 16;
 constexpr int kItemsPerBlock = kBlock * kItemsPerThread;  // radix sort / scan tile
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kIptPayload1 = 16;  // radix items per thread with one payload word
+constexpr int kIptPayload3 = 8;   // ... with three payload words (LDS staging size)
+
+// What a device-wide scan reads.
+enum ScanMode {
+  kScanPlain = 0,     // in_a[i]
+  kScanFlag = 1,      // in_a[i] != 0
+  kScanRectArea = 2,  // tile count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
+};
+
+// Key / payload planes of a radix sort: input in *_a, scratch in *_b.
+struct RadixBuffers {
+  int payload;  // 1 or 3
+  uint32_t* keys_a;
+  uint32_t* keys_b;
+  uint32_t* vals_a[3];
+  uint32_t* vals_b[3];
+};
+
+// Kernels known to the event profiler (fgs_profile_*).
+enum KernelId {
+  kKPreprocess = 0,
+  kKCompact,
+  kKDepthHist,
+  kKDepthScatter,
+  kKScan,
+  kKDuplicate,
+  kKTileHist,
+  kKTileScatter,
+  kKRanges,
+  kKFill,
+  kKBlendForward,
+  kKBlendBackward,
+  kKPreprocessBackward,
+  kKNumKernels
+};
+const char* kernel_name(int id);
+
+// Records a start event on construction and a stop event on destruction
+// (no-op unless profiling is enabled).
+class ProfScope {
+ public:
+  ProfScope(hipStream_t s, int id);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  hipStream_t s_;
+  int slot_;
+};
 
 // Counters slots in the workspace.
 enum Counter { kCountK = 0, kCountVisible = 1, kCountFlags = 2 };
@@ -27,7 +78,7 @@ struct Layout {
   int64_t kcap = 0;
   size_t bytes = 0;
   size_t splats, depth_keys, tiles, rects, radii;
-  size_t dkeys_a, dvals_a, dkeys_b, dvals_b;
+  size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
   size_t hist, partials;
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
@@ -58,22 +109,29 @@ struct ViewParams {
 hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* ws, const Layout& L,
                              hipStream_t s);
 
-// Exclusive scan of `count` u32 values.  If `gather` is non-null the i-th
-// input is in[gather[i]].  Writes total to *total (device) if non-null.
-hipError_t launch_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t count,
-                       uint32_t* partials, uint32_t* total, hipStream_t s);
+// Exclusive scan of u32 values read as `mode` says; the item count is
+// *d_count if d_count is non-null (device), capped by max_count (host).
+// Writes the total to *total (device) if non-null.  out may alias in_a.
+hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_t* d_count, int64_t max_count,
+                       int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s);
 
-// Stable LSD radix sort of (key, val) u32 pairs on bits [0, bits).  Buffers
-// a (input) and b (scratch); returns in *result_in_b whether the sorted data
-// ended in b.
-hipError_t launch_radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
-                             int64_t count, int bits, uint32_t* hist, uint32_t* partials, bool* result_in_b,
-                             hipStream_t s);
+// Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
+// bits [0, bits), same item-count convention as launch_scan.  The result is
+// in the *_a buffers after an even number of passes, else in *_b.
+hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
+                             uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id);
 int radix_passes(int bits);
+int64_t radix_blocks(int64_t max_count, int payload);
 
-// One (tile, id) pair per covered tile, Gaussians taken in depth order.
-hipError_t launch_duplicate(const uint32_t* depth_order, const uint32_t* tiles, const uint32_t* offsets,
-                            const uint2* rects, int64_t n, int32_t tiles_x, uint32_t* out_keys,
+// Visible Gaussians (tiles > 0) in id order: key, id and rect planes at
+// position pos[i] (exclusive scan of the visibility flags).
+hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
+                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, hipStream_t s);
+
+// One (tile, id) pair per covered tile of each depth-ordered visible
+// Gaussian (ids, rect planes rx / ry), at the exclusive-scan offsets.
+hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
+                            const uint32_t* d_count, int64_t max_count, int32_t tiles_x, uint32_t* out_keys,
                             uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);

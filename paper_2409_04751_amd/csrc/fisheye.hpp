@@ -132,52 +132,79 @@ constexpr float kY3c = 0.4570457994644658f;    // sqrt(21/(32 pi))
 constexpr float kY3d = 0.3731763325901154f;    // sqrt(7/(16 pi))
 constexpr float kY3e = 1.445305721320277f;     // sqrt(105/(16 pi))
 
-__device__ inline void sh_basis(int degree, float x, float y, float z, float Y[16]) {
+template <int DEG>
+__device__ inline void sh_basis(float x, float y, float z, float Y[16]) {
   Y[0] = kY00;
-  if (degree < 1) return;
-  Y[1] = -kY1 * y;
-  Y[2] = kY1 * z;
-  Y[3] = -kY1 * x;
-  if (degree < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kY2a * x * y;
-  Y[5] = -kY2a * y * z;
-  Y[6] = kY2b * (2.0f * zz - xx - yy);
-  Y[7] = -kY2a * x * z;
-  Y[8] = kY2c * (xx - yy);
-  if (degree < 3) return;
-  Y[9] = -kY3a * y * (3.0f * xx - yy);
-  Y[10] = kY3b * x * y * z;
-  Y[11] = -kY3c * y * (4.0f * zz - xx - yy);
-  Y[12] = kY3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-  Y[13] = -kY3c * x * (4.0f * zz - xx - yy);
-  Y[14] = kY3e * z * (xx - yy);
-  Y[15] = -kY3a * x * (xx - 3.0f * yy);
+  if constexpr (DEG >= 1) {
+    Y[1] = -kY1 * y;
+    Y[2] = kY1 * z;
+    Y[3] = -kY1 * x;
+  }
+  if constexpr (DEG >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kY2a * x * y;
+    Y[5] = -kY2a * y * z;
+    Y[6] = kY2b * (2.0f * zz - xx - yy);
+    Y[7] = -kY2a * x * z;
+    Y[8] = kY2c * (xx - yy);
+  }
+  if constexpr (DEG >= 3) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[9] = -kY3a * y * (3.0f * xx - yy);
+    Y[10] = kY3b * x * y * z;
+    Y[11] = -kY3c * y * (4.0f * zz - xx - yy);
+    Y[12] = kY3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -kY3c * x * (4.0f * zz - xx - yy);
+    Y[14] = kY3e * z * (xx - yy);
+    Y[15] = -kY3a * x * (xx - 3.0f * yy);
+  }
 }
 
-// Gradient of each basis polynomial with respect to (x, y, z):
-// dY[k][0..2].
-__device__ inline void sh_basis_grad(int degree, float x, float y, float z, float dY[16][3]) {
-  for (int k = 0; k < 16; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0f;
-  if (degree < 1) return;
-  dY[1][1] = -kY1;
-  dY[2][2] = kY1;
-  dY[3][0] = -kY1;
-  if (degree < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  dY[4][0] = kY2a * y;  dY[4][1] = kY2a * x;
-  dY[5][1] = -kY2a * z; dY[5][2] = -kY2a * y;
-  dY[6][0] = -2.0f * kY2b * x; dY[6][1] = -2.0f * kY2b * y; dY[6][2] = 4.0f * kY2b * z;
-  dY[7][0] = -kY2a * z; dY[7][2] = -kY2a * x;
-  dY[8][0] = 2.0f * kY2c * x; dY[8][1] = -2.0f * kY2c * y;
-  if (degree < 3) return;
-  dY[9][0] = -6.0f * kY3a * x * y;           dY[9][1] = -3.0f * kY3a * (xx - yy);
-  dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
-  dY[11][0] = 2.0f * kY3c * x * y; dY[11][1] = -kY3c * (4.0f * zz - xx - 3.0f * yy); dY[11][2] = -8.0f * kY3c * y * z;
-  dY[12][0] = -6.0f * kY3d * x * z; dY[12][1] = -6.0f * kY3d * y * z; dY[12][2] = kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy);
-  dY[13][0] = -kY3c * (4.0f * zz - 3.0f * xx - yy); dY[13][1] = 2.0f * kY3c * x * y; dY[13][2] = -8.0f * kY3c * x * z;
-  dY[14][0] = 2.0f * kY3e * x * z; dY[14][1] = -2.0f * kY3e * y * z; dY[14][2] = kY3e * (xx - yy);
-  dY[15][0] = -3.0f * kY3a * (xx - yy); dY[15][1] = 6.0f * kY3a * x * y;
+// g = sum_k w[k] grad Y_k at (x, y, z), each Y_k read as a polynomial in R^3
+// (only its tangential part matters once multiplied by d dir / d v).
+template <int DEG>
+__device__ inline void sh_grad_dir(float x, float y, float z, const float w[16], float g[3]) {
+  g[0] = g[1] = g[2] = 0.0f;
+  if constexpr (DEG >= 1) {
+    g[1] -= kY1 * w[1];
+    g[2] += kY1 * w[2];
+    g[0] -= kY1 * w[3];
+  }
+  if constexpr (DEG >= 2) {
+    g[0] += kY2a * y * w[4];
+    g[1] += kY2a * x * w[4];
+    g[1] -= kY2a * z * w[5];
+    g[2] -= kY2a * y * w[5];
+    g[0] -= 2.0f * kY2b * x * w[6];
+    g[1] -= 2.0f * kY2b * y * w[6];
+    g[2] += 4.0f * kY2b * z * w[6];
+    g[0] -= kY2a * z * w[7];
+    g[2] -= kY2a * x * w[7];
+    g[0] += 2.0f * kY2c * x * w[8];
+    g[1] -= 2.0f * kY2c * y * w[8];
+  }
+  if constexpr (DEG >= 3) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    g[0] -= 6.0f * kY3a * x * y * w[9];
+    g[1] -= 3.0f * kY3a * (xx - yy) * w[9];
+    g[0] += kY3b * y * z * w[10];
+    g[1] += kY3b * x * z * w[10];
+    g[2] += kY3b * x * y * w[10];
+    g[0] += 2.0f * kY3c * x * y * w[11];
+    g[1] -= kY3c * (4.0f * zz - xx - 3.0f * yy) * w[11];
+    g[2] -= 8.0f * kY3c * y * z * w[11];
+    g[0] -= 6.0f * kY3d * x * z * w[12];
+    g[1] -= 6.0f * kY3d * y * z * w[12];
+    g[2] += kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+    g[0] -= kY3c * (4.0f * zz - 3.0f * xx - yy) * w[13];
+    g[1] += 2.0f * kY3c * x * y * w[13];
+    g[2] -= 8.0f * kY3c * x * z * w[13];
+    g[0] += 2.0f * kY3e * x * z * w[14];
+    g[1] -= 2.0f * kY3e * y * z * w[14];
+    g[2] += kY3e * (xx - yy) * w[14];
+    g[0] -= 3.0f * kY3a * (xx - yy) * w[15];
+    g[1] += 6.0f * kY3a * x * y * w[15];
+  }
 }
 
 }  // namespace fgs

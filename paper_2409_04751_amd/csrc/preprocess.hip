@@ -34,8 +34,6 @@ struct PreArgs {
   uint32_t* tiles;
   uint2* rects;
   int32_t* radii;
-  uint32_t* dkeys;
-  uint32_t* dvals;
 };
 
 struct Geometry {
@@ -125,13 +123,17 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   return true;
 }
 
-// Colour from SH in float: rgb_c = sum_k sh[k*3+c] Y_k(dir) + 0.5, clamped at 0.
-__device__ inline void sh_color(const float* sh, int degree, uint32_t i, uint32_t n, const float dir[3], float rgb[3],
+// Colour from SH in float: rgb_c = sum_k sh[k*3+c] Y_k(dir) + 0.5 (the
+// caller clamps at 0).
+template <int DEG>
+__device__ inline void sh_color(const float* sh, uint32_t i, uint32_t n, const float dir[3], float rgb[3],
                                 float Y[16]) {
-  sh_basis(degree, dir[0], dir[1], dir[2], Y);
-  const int nb = (degree + 1) * (degree + 1);
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
   float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
   for (int k = 0; k < nb; ++k)
+#pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] += sh[(size_t)(k * 3 + c) * n + i] * Y[k];
   for (int c = 0; c < 3; ++c) rgb[c] = acc[c];
 }
@@ -143,6 +145,7 @@ __device__ inline void view_dir(const float* means, uint32_t i, uint32_t n, cons
   for (int a = 0; a < 3; ++a) dir[a] = (float)(vdir[a] / vlen);
 }
 
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
     float dir[3], Y[16], rgb[3];
     double vd[3], vlen;
     view_dir(a.means, i, n, a.campos, dir, vd, vlen);
-    sh_color(a.sh, a.sh_degree, i, n, dir, rgb, Y);
+    sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
     if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) break;
     const float o = a.opac[i];
     const double A = G.conic[0], B = G.conic[1];
@@ -190,8 +193,6 @@ __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   a.tiles[i] = ntiles;
   a.rects[i] = rect;
   a.radii[i] = radius;
-  a.dkeys[i] = key;
-  a.dvals[i] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -222,11 +223,12 @@ struct PreBwdArgs {
   float* g_means2d;
 };
 
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
   const uint32_t n = a.n;
-  const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+  constexpr int nb = (DEG + 1) * (DEG + 1);
   Geometry G;
   const bool visible = a.tiles[i] != 0 && compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
   if (!visible) {
@@ -283,20 +285,24 @@ __global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs 
   float dir[3], Y[16], rgb[3];
   double vd[3], vlen;
   view_dir(a.means, i, n, a.campos, dir, vd, vlen);
-  sh_color(a.sh, a.sh_degree, i, n, dir, rgb, Y);
+  sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
   float gcol[3];
   for (int c = 0; c < 3; ++c) gcol[c] = rgb[c] < 0.0f ? 0.0f : grgb[c];
-  for (int k = 0; k < nb; ++k)
-    for (int c = 0; c < 3; ++c) a.g_sh[(size_t)(k * 3 + c) * n + i] = Y[k] * gcol[c];
-  if (nb > 1) {
-    float dY[16][3];
-    sh_basis_grad(a.sh_degree, dir[0], dir[1], dir[2], dY);
-    float gd[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 1; k < nb; ++k) {
-      float w = 0.0f;
-      for (int c = 0; c < 3; ++c) w += a.sh[(size_t)(k * 3 + c) * n + i] * gcol[c];
-      for (int e = 0; e < 3; ++e) gd[e] += w * dY[k][e];
+  float wk[16];
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    float w = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t plane = (size_t)(k * 3 + c) * n + i;
+      a.g_sh[plane] = Y[k] * gcol[c];
+      w += a.sh[plane] * gcol[c];
     }
+    wk[k] = w;
+  }
+  if constexpr (DEG > 0) {
+    float gd[3];
+    sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wk, gd);
     // d dir / d v = (I - dir dir^T) / |v|
     const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
     for (int e = 0; e < 3; ++e) gm[e] += ((double)gd[e] - (double)dir[e] * dd) / vlen;
@@ -359,10 +365,14 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* 
   a.tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
   a.rects = reinterpret_cast<uint2*>(ws + L.rects);
   a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
-  a.dkeys = reinterpret_cast<uint32_t*>(ws + L.dkeys_a);
-  a.dvals = reinterpret_cast<uint32_t*>(ws + L.dvals_a);
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
-  hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
+  ProfScope prof(s, kKPreprocess);
+  switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 
@@ -388,7 +398,13 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.g_sh = out.sh;
   a.g_means2d = out.means2d;
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
-  hipLaunchKernelGGL(preprocess_backward_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
+  ProfScope prof(s, kKPreprocessBackward);
+  switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(preprocess_backward_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(preprocess_backward_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(preprocess_backward_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(preprocess_backward_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -94,6 +94,32 @@ def cpu_baseline(scene, pose, cam, target):
                 sample="1 full view of the same workload (fwd + bwd, fp64), OMP threads = cores")
 
 
+def serving_bench(params, deg, rates, count):
+    """Resident scene; open-loop Poisson requests, each a random pose in the
+    room, resolution from {512^2, 1024^2, 1752x1168, 2048^2}, FOV U(150, 200)
+    deg.  Batched server vs serial rendering on the same trace."""
+    from paper_2409_04751_amd import server as S
+
+    srv = S.RenderServer(*params, deg, workspace_bytes=16 << 30)
+    warm = S.poisson_trace(2000.0, 24, seed=99)
+    srv.serve(warm, "batched")
+    srv.serve(warm, "serial")
+    out = dict(scene="room3m resident (3M Gaussians, SH3)", requests_per_rate=count,
+               resolutions=["512x512", "1024x1024", "1752x1168", "2048x2048"], fov_deg=[150, 200], rates={})
+    for rate in rates:
+        trace = S.poisson_trace(rate, count, seed=3)
+        res = {}
+        for mode in ("serial", "batched"):
+            srv.batches = srv.splits = 0
+            r = srv.serve(trace, mode)
+            res[mode] = {k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()}
+            log(f"serve rate={rate:g}/s {mode}: p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms "
+                f"{r['views_per_s']:.0f} views/s")
+        res["batched_over_serial_views_per_s"] = round(res["batched"]["views_per_s"] / res["serial"]["views_per_s"], 3)
+        out["rates"][f"{rate:g}"] = res
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +128,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 2000.0],
+                    help="Poisson arrival rates (requests/s) for the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the fisheye rasterizer has no "
@@ -185,6 +215,10 @@ def main() -> int:
             v["ms"] = round(v["ms"], 5)
             v["avg_ms"] = round(v["avg_ms"], 5)
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_bench([x.detach() for x in leaves], deg, args.serve_rates, args.serve_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
@@ -198,7 +232,7 @@ def main() -> int:
                config=dict(workload="room3m_fisheye1752x1168_180deg", gaussians=N, sh_degree=3, width=cam.width,
                            height=cam.height, fov_deg=180.0, views_per_step=1, visible=V, intersections=K,
                            geometry_dtype="f64"),
-               roofline=roofline, cpu_baseline=cpu, kernels=kernels)
+               roofline=roofline, cpu_baseline=cpu, kernels=kernels, serving=serving)
     print(json.dumps(out), flush=True)
     return 0
 

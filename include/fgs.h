@@ -48,6 +48,8 @@ extern "C" {
 
 #define FGS_MODEL_EQUIDISTANT 0 /* r_d = f theta (Sec. 3.2) */
 
+#define FGS_MAX_BATCH 8 /* views per fgs_render_forward_batch call */
+
 /* Forward flags */
 #define FGS_SAVE_PIXEL_STATE 1u /* also store per-pixel final transmittance and
                                    contributor count; the backward then reads
@@ -116,7 +118,7 @@ typedef struct fgs_layout {
   size_t grad2d;       /* float [9][n]: backward scratch (dL/d mu_p xy, conic A B C, opacity, rgb) */
   size_t pixel_T;      /* float [H][W]: final transmittance (FGS_SAVE_PIXEL_STATE) */
   size_t pixel_last;   /* uint32 [H][W]: 1 + list index of the last blended Gaussian */
-  size_t counters;     /* uint32 [16]: [0] K, [1] visible count, [2] forward flags */
+  size_t counters;     /* uint32 [11]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view */
 } fgs_layout;
 
 /* Library version string (static storage). */
@@ -154,6 +156,34 @@ int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes,
 int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
                        uint32_t flags, void* workspace, size_t workspace_bytes, float* out_rgb, int64_t* k_out,
                        void* stream);
+
+/*
+ * Bytes of workspace fgs_render_forward_batch needs for nviews views (host
+ * cams[nviews]: only width and height are read) and up to k_capacity
+ * intersections in total.
+ */
+int fgs_batch_workspace_bytes(int64_t n, int32_t nviews, const fgs_camera* cams, int64_t k_capacity, size_t* bytes);
+
+/*
+ * Forward render of 1..FGS_MAX_BATCH views of one resident scene in one set of
+ * launches (serving): one preprocess launch walks the Gaussians once and
+ * projects each into every view, so each Gaussian's parameters are read
+ * from HBM once per batch; the visible (view, Gaussian) entries share one
+ * depth sort, their (tile, id) pairs use view-major tile ids and share one
+ * tile sort, and one blend launch covers the tiles of all views.  Views
+ * may differ in pose, resolution, focal length and field of view.
+ *
+ * poses, cams: host [nviews]; bgs: host [nviews][3]; out_rgb: host array of
+ * nviews device pointers, view v's image [3][H_v][W_v].  k_views (host
+ * [nviews]) and k_total (host) may be NULL; they receive the intersections
+ * per view and in total, also when FGS_ERR_WORKSPACE is returned, so a
+ * server can split the batch.  Synchronises `stream` once, like
+ * fgs_render_forward.  The workspace is the batch layout
+ * (fgs_batch_workspace_bytes), not usable by fgs_render_backward.
+ */
+int fgs_render_forward_batch(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, const fgs_camera* cams,
+                             const float* bgs, void* workspace, size_t workspace_bytes, float* const* out_rgb,
+                             int64_t* k_views, int64_t* k_total, void* stream);
 
 /*
  * Backward of the same view.  Inputs must be those of the preceding

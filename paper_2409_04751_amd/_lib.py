@@ -19,6 +19,7 @@ FGS_ERR_HIP = -3
 FGS_ERR_OVERFLOW = -4
 FGS_MODEL_EQUIDISTANT = 0
 FGS_SAVE_PIXEL_STATE = 1
+FGS_MAX_BATCH = 8
 
 c_size = ctypes.c_size_t
 
@@ -77,6 +78,12 @@ SIGNATURES = {
     "fgs_render_backward": ([ctypes.POINTER(fgs_gaussians), ctypes.POINTER(fgs_pose), ctypes.POINTER(fgs_camera),
                              ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, c_size, ctypes.c_void_p,
                              ctypes.POINTER(fgs_grads), ctypes.c_void_p], ctypes.c_int),
+    "fgs_batch_workspace_bytes": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(fgs_camera), ctypes.c_int64,
+                                   ctypes.POINTER(c_size)], ctypes.c_int),
+    "fgs_render_forward_batch": ([ctypes.POINTER(fgs_gaussians), ctypes.c_int32, ctypes.POINTER(fgs_pose),
+                                  ctypes.POINTER(fgs_camera), ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, c_size,
+                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p], ctypes.c_int),
     "fgs_profile_enable": ([ctypes.c_int32], ctypes.c_int),
     "fgs_profile_read": ([ctypes.POINTER(fgs_profile)], ctypes.c_int),
 }
@@ -148,6 +155,28 @@ def fgs_render_backward(g: fgs_gaussians, pose: fgs_pose, cam: fgs_camera, bg, w
                         dL_drgb: int, grads: fgs_grads, stream: int) -> int:
     return lib().fgs_render_backward(ctypes.byref(g), ctypes.byref(pose), ctypes.byref(cam), _bg(bg), workspace,
                                      workspace_bytes, dL_drgb, ctypes.byref(grads), stream)
+
+
+def fgs_batch_workspace_bytes(n: int, cams, k_capacity: int) -> int:
+    arr = (fgs_camera * len(cams))(*cams)
+    out = c_size(0)
+    check(lib().fgs_batch_workspace_bytes(n, len(cams), arr, k_capacity, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fgs_render_forward_batch(g: fgs_gaussians, poses, cams, bgs, workspace: int, workspace_bytes: int, out_rgb,
+                             stream: int) -> tuple[int, list[int], int]:
+    """Returns (return code, K per view, K total); does not raise."""
+    nv = len(cams)
+    P = (fgs_pose * nv)(*poses)
+    C = (fgs_camera * nv)(*cams)
+    B = (ctypes.c_float * (3 * nv))(*[float(x) for bg in bgs for x in bg])
+    O = (ctypes.c_void_p * nv)(*out_rgb)
+    kv = (ctypes.c_int64 * nv)()
+    kt = ctypes.c_int64(0)
+    rc = lib().fgs_render_forward_batch(ctypes.byref(g), nv, P, C, B, workspace, workspace_bytes, O, kv,
+                                        ctypes.byref(kt), stream)
+    return rc, [int(x) for x in kv], int(kt.value)
 
 
 def fgs_profile_enable(on: bool) -> None:

@@ -31,55 +31,63 @@ int bits_for(int64_t values) {  // bits needed to represent 0 .. values-1
   return b;
 }
 
+int tiles_of(int32_t px) { return (px + kTile - 1) / kTile; }
+
 }  // namespace
 
-Layout make_layout(int64_t n, int32_t width, int32_t height, int64_t kcap) {
+Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32_t* heights, int64_t kcap) {
   Layout L;
   L.n = n;
-  L.width = width;
-  L.height = height;
-  L.tiles_x = (width + kTile - 1) / kTile;
-  L.tiles_y = (height + kTile - 1) / kTile;
+  L.nviews = nviews;
+  L.width = widths[0];
+  L.height = heights[0];
+  L.tiles_x = tiles_of(widths[0]);
+  L.tiles_y = tiles_of(heights[0]);
   L.kcap = kcap;
-  const int64_t ntiles = (int64_t)L.tiles_x * L.tiles_y;
-  const int64_t P = (int64_t)width * height;
+  for (int v = 0; v < nviews; ++v) {
+    L.total_tiles += (int64_t)tiles_of(widths[v]) * tiles_of(heights[v]);
+    L.total_pixels += (int64_t)widths[v] * heights[v];
+  }
   const size_t nn = (size_t)(n > 0 ? n : 1);
+  const size_t nv = nn * (size_t)nviews;
+  L.nv = (int64_t)n * nviews;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off = align_up(off + (bytes > 0 ? bytes : 1));
     return o;
   };
-  L.counters = take(16 * sizeof(uint32_t));
-  L.splats = take(nn * 3 * sizeof(float4));
-  L.depth_keys = take(nn * 4);
-  L.tiles = take(nn * 4);
-  L.rects = take(nn * 8);
-  L.radii = take(nn * 4);
-  L.dkeys_a = take(nn * 4);
-  L.dvals_a = take(nn * 4);
-  L.drx_a = take(nn * 4);
-  L.dry_a = take(nn * 4);
-  L.dkeys_b = take(nn * 4);
-  L.dvals_b = take(nn * 4);
-  L.drx_b = take(nn * 4);
-  L.dry_b = take(nn * 4);
-  L.offsets = take(nn * 4);
+  L.counters = take(kNumCounters * sizeof(uint32_t));
+  L.splats = take(nv * 3 * sizeof(float4));
+  L.depth_keys = take(nv * 4);
+  L.tiles = take(nv * 4);
+  L.rects = take(nv * 8);
+  L.radii = take(nv * 4);
+  L.dkeys_a = take(nv * 4);
+  L.dvals_a = take(nv * 4);
+  L.drx_a = take(nv * 4);
+  L.dry_a = take(nv * 4);
+  L.dkeys_b = take(nv * 4);
+  L.dvals_b = take(nv * 4);
+  L.drx_b = take(nv * 4);
+  L.dry_b = take(nv * 4);
+  L.offsets = take(nv * 4);
   L.grad2d = take(nn * 9 * 4);
-  L.ranges = take((size_t)ntiles * 8);
-  L.pixel_T = take((size_t)P * 4);
-  L.pixel_last = take((size_t)P * 4);
+  L.ranges = take((size_t)L.total_tiles * 8);
+  L.pixel_T = take((size_t)L.total_pixels * 4);
+  L.pixel_last = take((size_t)L.total_pixels * 4);
+  L.block_tiles = take((size_t)ceil_div((int64_t)nn, kBlock) * nviews * 4);
   const int64_t kk = kcap > 0 ? kcap : 1;
-  const int64_t nb_max = std::max(radix_blocks((int64_t)nn, 3), radix_blocks(kk, 1));
+  const int64_t nb_max = std::max(radix_blocks((int64_t)nv, 3), radix_blocks(kk, 1));
   L.hist = take((size_t)nb_max * kRadix * 4);
-  const int64_t scan_items = std::max<int64_t>({(int64_t)nn, nb_max * kRadix});
+  const int64_t scan_items = std::max<int64_t>({(int64_t)nv, nb_max * kRadix});
   L.partials = take((size_t)(ceil_div(scan_items, kItemsPerBlock) + 1) * 4);
   L.tkeys_a = take((size_t)kk * 4);
   L.tvals_a = take((size_t)kk * 4);
   L.tkeys_b = take((size_t)kk * 4);
   L.tvals_b = take((size_t)kk * 4);
   L.bytes = off;
-  L.tile_bits = bits_for(ntiles);
+  L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
   const bool in_b = L.tile_passes % 2 == 1;
   L.tile_keys_final = in_b ? L.tkeys_b : L.tkeys_a;
@@ -87,19 +95,19 @@ Layout make_layout(int64_t n, int32_t width, int32_t height, int64_t kcap) {
   return L;
 }
 
-Layout fit_layout(int64_t n, int32_t width, int32_t height, size_t bytes) {
-  Layout L0 = make_layout(n, width, height, 0);
+Layout fit_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32_t* heights, size_t bytes) {
+  Layout L0 = make_layout(n, nviews, widths, heights, 0);
   if (L0.bytes > bytes) {
     L0.kcap = -1;
     return L0;
   }
   // largest kcap with make_layout(kcap).bytes <= bytes (monotone in kcap)
-  int64_t lo = 0, hi = (int64_t)(bytes / 16) + 1;
+  int64_t lo = 0, hi = std::min<int64_t>((int64_t)(bytes / 16) + 1, 0x7FFFFFFF);
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (make_layout(n, width, height, mid).bytes <= bytes) lo = mid; else hi = mid;
+    if (make_layout(n, nviews, widths, heights, mid).bytes <= bytes) lo = mid; else hi = mid;
   }
-  return make_layout(n, width, height, lo);
+  return make_layout(n, nviews, widths, heights, lo);
 }
 
 }  // namespace fgs
@@ -108,22 +116,29 @@ using namespace fgs;
 
 namespace {
 
-int check_common(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
-  if (!g || !pose || !cam || !bg) return fail(FGS_ERR_ARG, "null struct argument");
+int check_gaussians(const fgs_gaussians* g) {
+  if (!g) return fail(FGS_ERR_ARG, "null gaussians");
   if (g->n < 0) return fail(FGS_ERR_ARG, "n < 0");
   if (g->n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 Gaussians");
   if (g->sh_degree < 0 || g->sh_degree > 3) return fail(FGS_ERR_ARG, "sh_degree must be 0..3");
   if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
     return fail(FGS_ERR_ARG, "null parameter array");
+  return FGS_OK;
+}
+
+int check_view(const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
+  if (!pose || !cam || !bg) return fail(FGS_ERR_ARG, "null pose, camera or bg");
   if (cam->width <= 0 || cam->height <= 0) return fail(FGS_ERR_ARG, "image size must be positive");
   if ((int64_t)cam->width * cam->height > ((int64_t)1 << 31)) return fail(FGS_ERR_ARG, "image too large");
-  if (((cam->width + kTile - 1) / kTile) > 0xFFFF || ((cam->height + kTile - 1) / kTile) > 0xFFFF)
+  if (tiles_of(cam->width) > 0xFFFF || tiles_of(cam->height) > 0xFFFF)
     return fail(FGS_ERR_ARG, "more than 65535 tiles along one axis");
   if (cam->model != FGS_MODEL_EQUIDISTANT) return fail(FGS_ERR_ARG, "unsupported camera model");
-  if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+  if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
+      !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
     return fail(FGS_ERR_ARG, "focal lengths must be positive and the principal point finite");
-  if (!(cam->theta_max > 0) || !(cam->theta_max < 3.14159265358979323846)) return fail(FGS_ERR_ARG, "theta_max must be in (0, pi)");
-  if (!(cam->near_dist >= 0)) return fail(FGS_ERR_ARG, "near_dist must be >= 0");
+  if (!(cam->theta_max > 0) || !(cam->theta_max < 3.14159265358979323846))
+    return fail(FGS_ERR_ARG, "theta_max must be in (0, pi)");
+  if (!(cam->near_dist >= 0) || !std::isfinite(cam->near_dist)) return fail(FGS_ERR_ARG, "near_dist must be >= 0");
   for (int k = 0; k < 9; ++k)
     if (!std::isfinite(pose->R[k])) return fail(FGS_ERR_ARG, "non-finite pose");
   for (int k = 0; k < 3; ++k)
@@ -131,10 +146,12 @@ int check_common(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera*
   return FGS_OK;
 }
 
-ViewParams make_view(const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
+ViewParams make_view(const fgs_pose* pose, const fgs_camera* cam, const float* bg, uint32_t tile_base,
+                     uint32_t pixel_base) {
   ViewParams v;
   for (int k = 0; k < 9; ++k) v.R[k] = pose->R[k];
   for (int k = 0; k < 3; ++k) v.t[k] = pose->t[k];
+  for (int c = 0; c < 3; ++c) v.campos[c] = -(v.R[0 * 3 + c] * v.t[0] + v.R[1 * 3 + c] * v.t[1] + v.R[2 * 3 + c] * v.t[2]);
   v.fx = cam->fx;
   v.fy = cam->fy;
   v.cx = cam->cx;
@@ -143,8 +160,10 @@ ViewParams make_view(const fgs_pose* pose, const fgs_camera* cam, const float* b
   v.theta_max = cam->theta_max;
   v.width = cam->width;
   v.height = cam->height;
-  v.tiles_x = (cam->width + kTile - 1) / kTile;
-  v.tiles_y = (cam->height + kTile - 1) / kTile;
+  v.tiles_x = tiles_of(cam->width);
+  v.tiles_y = tiles_of(cam->height);
+  v.tile_base = tile_base;
+  v.pixel_base = pixel_base;
   for (int k = 0; k < 3; ++k) v.bg[k] = bg[k];
   return v;
 }
@@ -174,81 +193,74 @@ void export_layout(const Layout& L, fgs_layout* out) {
   out->counters = L.counters;
 }
 
-#define HIP_TRY(expr, where)               \
-  do {                                     \
-    hipError_t e_ = (expr);                \
+#define HIP_TRY(expr, where)                          \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
-}  // namespace
-
-extern "C" {
-
-const char* fgs_version(void) { return "fgs 0.1 gfx950"; }
-
-const char* fgs_last_error(void) { return g_last_error.c_str(); }
-
-int fgs_workspace_bytes(int64_t n, int32_t width, int32_t height, int64_t k_capacity, size_t* bytes) {
-  if (!bytes || n < 0 || width <= 0 || height <= 0 || k_capacity < 0) return fail(FGS_ERR_ARG, "bad argument");
-  if (n > 0x7FFFFFFF || k_capacity > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "size beyond 2^31-1");
-  *bytes = make_layout(n, width, height, k_capacity).bytes;
-  return FGS_OK;
-}
-
-int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes, fgs_layout* out) {
-  if (!out || n < 0 || width <= 0 || height <= 0) return fail(FGS_ERR_ARG, "bad argument");
-  const Layout L = fit_layout(n, width, height, bytes);
-  if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
-  export_layout(L, out);
-  return FGS_OK;
-}
-
-int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
-                       uint32_t flags, void* workspace, size_t workspace_bytes, float* out_rgb, int64_t* k_out,
-                       void* stream) {
-  int rc = check_common(g, pose, cam, bg);
-  if (rc != FGS_OK) return rc;
-  if (!workspace || !out_rgb) return fail(FGS_ERR_ARG, "null workspace or output");
-  if (flags & ~FGS_SAVE_PIXEL_STATE) return fail(FGS_ERR_ARG, "unknown flags");
-  const Layout L = fit_layout(g->n, cam->width, cam->height, workspace_bytes);
+// Shared forward of 1..kMaxViews views: preprocess of every (view, Gaussian),
+// compaction, depth sort, tile-count scan, K read-back, duplication, tile
+// sort, ranges and one blend launch over the tiles of all views.
+int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, const fgs_camera* cams,
+                 const float* bgs, uint32_t flags, void* workspace, size_t workspace_bytes, float* const* out_rgb,
+                 int64_t* k_views, int64_t* k_total, hipStream_t s) {
+  int32_t widths[kMaxViews], heights[kMaxViews];
+  for (int v = 0; v < nviews; ++v) {
+    widths[v] = cams[v].width;
+    heights[v] = cams[v].height;
+  }
+  const Layout L = fit_layout(g->n, nviews, widths, heights, workspace_bytes);
   if (L.kcap < 0) {
-    if (k_out) *k_out = -1;
+    if (k_total) *k_total = -1;
     return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
   }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const ViewParams v = make_view(pose, cam, bg);
-  uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
-  const int64_t n = g->n;
-  const int32_t ntiles = L.tiles_x * L.tiles_y;
-
-  HIP_TRY(launch_fill_u32(counters, 0u, 16, s), "clear counters");
-  HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
-  HIP_TRY(launch_preprocess(*g, v, ws, L, s), "preprocess");
   auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  ViewBatch b;
+  b.count = nviews;
+  uint32_t tile_base = 0, pixel_base = 0;
+  BatchOut out;
+  for (int v = 0; v < kMaxViews; ++v) out.rgb[v] = nullptr;
+  for (int v = 0; v < nviews; ++v) {
+    b.v[v] = make_view(&poses[v], &cams[v], &bgs[3 * v], tile_base, pixel_base);
+    tile_base += (uint32_t)(b.v[v].tiles_x * b.v[v].tiles_y);
+    pixel_base += (uint32_t)(cams[v].width * cams[v].height);
+    out.rgb[v] = out_rgb[v];
+  }
+  const int64_t n = g->n, nv = L.nv;
+  uint32_t* counters = U(L.counters);
   uint32_t* partials = U(L.partials);
   uint32_t* hist = U(L.hist);
   const uint32_t* d_visible = counters + kCountVisible;
-  // stable compaction of the visible Gaussians (id order); offsets holds the
-  // positions until the tile-count scan reuses it
-  HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, n, kScanFlag, partials, counters + kCountVisible, U(L.offsets), s),
+
+  HIP_TRY(launch_fill_u32(counters, 0u, kNumCounters, s), "clear counters");
+  HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
+  HIP_TRY(launch_preprocess(*g, b, ws, L, s), "preprocess");
+  // stable compaction of the visible (view, Gaussian) entries; offsets holds
+  // their positions until the tile-count scan reuses it
+  HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible, U(L.offsets),
+                      s),
           "visibility scan");
-  HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects), U(L.offsets), n,
+  HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects), U(L.offsets), nv,
                          U(L.dkeys_a), U(L.dvals_a), U(L.drx_a), U(L.dry_a), s),
           "compact");
-  // depth sort of the visible Gaussians carrying (id, rect); positive float
-  // bits use 31 key bits -> 4 passes, result back in the *_a planes
+  // depth sort carrying (id, rect); positive float bits use 31 key bits ->
+  // 4 passes, result back in the *_a planes.  Views may interleave here: the
+  // tile sort below separates them again and keeps each view's depth order.
   RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
                   {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
-  HIP_TRY(launch_radix_sort(DB, d_visible, n, 31, hist, partials, s, kKDepthHist, kKDepthScatter), "depth sort");
-  HIP_TRY(launch_scan(U(L.drx_a), U(L.dry_a), d_visible, n, kScanRectArea, partials, counters + kCountK, U(L.offsets),
-                      s),
+  HIP_TRY(launch_radix_sort(DB, d_visible, nv, 31, hist, partials, s, kKDepthHist, kKDepthScatter), "depth sort");
+  HIP_TRY(launch_scan(U(L.drx_a), U(L.dry_a), d_visible, nv, kScanRectArea, partials, counters + kCountK,
+                      U(L.offsets), s),
           "tile count scan");
-  uint32_t K32 = 0;
-  HIP_TRY(hipMemcpyAsync(&K32, counters + kCountK, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read K");
+  uint32_t host_counters[kNumCounters];
+  HIP_TRY(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s), "read K");
   HIP_TRY(hipStreamSynchronize(s), "sync for K");
-  const int64_t K = K32;
-  if (k_out) *k_out = K;
+  const int64_t K = host_counters[kCountK];
+  if (k_total) *k_total = K;
+  if (k_views)  // one view: its count is the total (the per-view sums run for batches only)
+    for (int v = 0; v < nviews; ++v) k_views[v] = nviews == 1 ? K : (int64_t)host_counters[kCountViewK + v];
   if (K > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 intersections");
   if (K > L.kcap) {
     char msg[160];
@@ -256,36 +268,108 @@ int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_c
                   (long long)K);
     return fail(FGS_ERR_WORKSPACE, msg);
   }
-  HIP_TRY(launch_duplicate(U(L.dvals_a), U(L.drx_a), U(L.dry_a), U(L.offsets), d_visible, n, L.tiles_x, U(L.tkeys_a),
-                           U(L.tvals_a), s),
+  HIP_TRY(launch_duplicate(U(L.dvals_a), U(L.drx_a), U(L.dry_a), U(L.offsets), d_visible, nv, K, b, n, L.tile_bits,
+                           hist, U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
-  HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter), "tile sort");
-  const uint32_t* keys = U(L.tile_keys_final);
-  const uint32_t* ids = U(L.tile_ids_final);
+  HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, true),
+          "tile sort");
   uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);
-  HIP_TRY(launch_ranges(keys, K, ranges, ntiles, s), "ranges");
-  HIP_TRY(launch_blend_forward(v, ranges, ids, reinterpret_cast<const float4*>(ws + L.splats), out_rgb,
-                               reinterpret_cast<float*>(ws + L.pixel_T), reinterpret_cast<uint32_t*>(ws + L.pixel_last),
+  HIP_TRY(launch_ranges(U(L.tile_keys_final), K, ranges, (int32_t)L.total_tiles, s), "ranges");
+  HIP_TRY(launch_blend_forward(b, L.total_tiles, ranges, U(L.tile_ids_final),
+                               reinterpret_cast<const float4*>(ws + L.splats), out,
+                               reinterpret_cast<float*>(ws + L.pixel_T), U(L.pixel_last),
                                (flags & FGS_SAVE_PIXEL_STATE) != 0, s),
           "blend forward");
   return FGS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+const char* fgs_version(void) { return "fgs 0.2 gfx950"; }
+
+const char* fgs_last_error(void) { return g_last_error.c_str(); }
+
+int fgs_workspace_bytes(int64_t n, int32_t width, int32_t height, int64_t k_capacity, size_t* bytes) {
+  if (!bytes || n < 0 || width <= 0 || height <= 0 || k_capacity < 0) return fail(FGS_ERR_ARG, "bad argument");
+  if (n > 0x7FFFFFFF || k_capacity > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "size beyond 2^31-1");
+  *bytes = make_layout(n, 1, &width, &height, k_capacity).bytes;
+  return FGS_OK;
+}
+
+int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes, fgs_layout* out) {
+  if (!out || n < 0 || width <= 0 || height <= 0) return fail(FGS_ERR_ARG, "bad argument");
+  const Layout L = fit_layout(n, 1, &width, &height, bytes);
+  if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
+  export_layout(L, out);
+  return FGS_OK;
+}
+
+int fgs_batch_workspace_bytes(int64_t n, int32_t nviews, const fgs_camera* cams, int64_t k_capacity,
+                              size_t* bytes) {
+  if (!bytes || !cams || n < 0 || nviews < 1 || nviews > kMaxViews || k_capacity < 0)
+    return fail(FGS_ERR_ARG, "bad argument");
+  if ((int64_t)n * nviews > 0x7FFFFFFF || k_capacity > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "size beyond 2^31-1");
+  int32_t w[kMaxViews], h[kMaxViews];
+  for (int v = 0; v < nviews; ++v) {
+    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(FGS_ERR_ARG, "image size must be positive");
+    w[v] = cams[v].width;
+    h[v] = cams[v].height;
+  }
+  *bytes = make_layout(n, nviews, w, h, k_capacity).bytes;
+  return FGS_OK;
+}
+
+int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                       uint32_t flags, void* workspace, size_t workspace_bytes, float* out_rgb, int64_t* k_out,
+                       void* stream) {
+  int rc = check_gaussians(g);
+  if (rc == FGS_OK) rc = check_view(pose, cam, bg);
+  if (rc != FGS_OK) return rc;
+  if (!workspace || !out_rgb) return fail(FGS_ERR_ARG, "null workspace or output");
+  if (flags & ~FGS_SAVE_PIXEL_STATE) return fail(FGS_ERR_ARG, "unknown flags");
+  float* outs[1] = {out_rgb};
+  return forward_impl(g, 1, pose, cam, bg, flags, workspace, workspace_bytes, outs, nullptr, k_out,
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
+int fgs_render_forward_batch(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, const fgs_camera* cams,
+                             const float* bgs, void* workspace, size_t workspace_bytes, float* const* out_rgb,
+                             int64_t* k_views, int64_t* k_total, void* stream) {
+  int rc = check_gaussians(g);
+  if (rc != FGS_OK) return rc;
+  if (nviews < 1 || nviews > kMaxViews) return fail(FGS_ERR_ARG, "nviews must be 1..FGS_MAX_BATCH");
+  if (!poses || !cams || !bgs || !out_rgb || !workspace) return fail(FGS_ERR_ARG, "null argument");
+  if ((int64_t)g->n * nviews > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "n * nviews beyond 2^31-1");
+  int64_t tiles = 0;
+  for (int v = 0; v < nviews; ++v) {
+    rc = check_view(&poses[v], &cams[v], &bgs[3 * v]);
+    if (rc != FGS_OK) return rc;
+    if (!out_rgb[v]) return fail(FGS_ERR_ARG, "null output image");
+    tiles += (int64_t)tiles_of(cams[v].width) * tiles_of(cams[v].height);
+  }
+  if (tiles > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "too many tiles in the batch");
+  return forward_impl(g, nviews, poses, cams, bgs, 0u, workspace, workspace_bytes, out_rgb, k_views, k_total,
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
 int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
                         void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
                         void* stream) {
-  int rc = check_common(g, pose, cam, bg);
+  int rc = check_gaussians(g);
+  if (rc == FGS_OK) rc = check_view(pose, cam, bg);
   if (rc != FGS_OK) return rc;
   if (!workspace || !dL_drgb || !grads) return fail(FGS_ERR_ARG, "null workspace, dL_drgb or grads");
   if (g->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->sh))
     return fail(FGS_ERR_ARG, "null gradient array");
-  const Layout L = fit_layout(g->n, cam->width, cam->height, workspace_bytes);
+  const Layout L = fit_layout(g->n, 1, &cam->width, &cam->height, workspace_bytes);
   if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
   if (g->n == 0) return FGS_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const ViewParams v = make_view(pose, cam, bg);
+  const ViewParams v = make_view(pose, cam, bg, 0u, 0u);
   float* grad2d = reinterpret_cast<float*>(ws + L.grad2d);
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * g->n, s), "clear grad2d");
   HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges),

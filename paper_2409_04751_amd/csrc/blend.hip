@@ -31,12 +31,11 @@ struct BlendArgs {
   const uint2* ranges;
   const uint32_t* ids;
   const float4* splats;
-  int32_t width, height, tiles_x;
-  float bg[3];
-  float* out;
   float* pixel_T;
   uint32_t* pixel_last;
   int save;
+  BatchOut out;
+  ViewBatch batch;
 };
 
 // Pixel of this thread inside its tile: wave w owns quadrant (w & 1, w >> 1).
@@ -71,19 +70,25 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
   return __builtin_fmaf(a.z * t, t, (b.x * dy) * dy);
 }
 
+// One block per tile of every view of the batch (tiles are numbered view by
+// view; the view of a block is found from the views' first tile ids).
 __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
   __shared__ float4 sa[kBlock];
   __shared__ float4 sb[kBlock];
   __shared__ float2 sc[kBlock];
-  const int tile = blockIdx.x;
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const uint32_t gtile = blockIdx.x;
+  int vi = 0;
+  while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
+  const ViewParams& vp = a.batch.v[vi];
+  const int tile = (int)(gtile - vp.tile_base);
+  const int tx = tile % vp.tiles_x, ty = tile / vp.tiles_x;
   int i, j;
   pixel_of_thread(i, j);
   const int px = tx * kTile + i, py = ty * kTile + j;
-  const bool inside = px < a.width && py < a.height;
+  const bool inside = px < vp.width && py < vp.height;
   const float fi = (float)i, fj = (float)j;
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
-  const uint2 r = a.ranges[tile];
+  const uint2 r = a.ranges[gtile];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   uint32_t last = 0;
   bool done = !inside;
@@ -116,13 +121,14 @@ __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
     }
   }
   if (inside) {
-    const size_t hw = (size_t)a.width * a.height, p = (size_t)py * a.width + px;
-    a.out[p] = __builtin_fmaf(T, a.bg[0], C0);
-    a.out[hw + p] = __builtin_fmaf(T, a.bg[1], C1);
-    a.out[2 * hw + p] = __builtin_fmaf(T, a.bg[2], C2);
+    const size_t hw = (size_t)vp.width * vp.height, p = (size_t)py * vp.width + px;
+    float* out = a.out.rgb[vi];
+    out[p] = __builtin_fmaf(T, vp.bg[0], C0);
+    out[hw + p] = __builtin_fmaf(T, vp.bg[1], C1);
+    out[2 * hw + p] = __builtin_fmaf(T, vp.bg[2], C2);
     if (a.save) {
-      a.pixel_T[p] = T;
-      a.pixel_last[p] = last;
+      a.pixel_T[vp.pixel_base + p] = T;
+      a.pixel_last[vp.pixel_base + p] = last;
     }
   }
 }
@@ -327,23 +333,21 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
 
 }  // namespace
 
-hipError_t launch_blend_forward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
-                                float* out, float* pixel_T, uint32_t* pixel_last, bool save, hipStream_t s) {
+hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
+                                const float4* splats, const BatchOut& out, float* pixel_T, uint32_t* pixel_last,
+                                bool save, hipStream_t s) {
+  if (total_tiles <= 0) return hipSuccess;
   BlendArgs a;
   a.ranges = ranges;
   a.ids = ids;
   a.splats = splats;
-  a.width = v.width;
-  a.height = v.height;
-  a.tiles_x = v.tiles_x;
-  for (int c = 0; c < 3; ++c) a.bg[c] = v.bg[c];
-  a.out = out;
   a.pixel_T = pixel_T;
   a.pixel_last = pixel_last;
   a.save = save ? 1 : 0;
-  const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  a.out = out;
+  a.batch = b;
   ProfScope prof(s, kKBlendForward);
-  hipLaunchKernelGGL(blend_forward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)total_tiles), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -68,27 +68,34 @@ class ProfScope {
   int slot_;
 };
 
-// Counters slots in the workspace.
-enum Counter { kCountK = 0, kCountVisible = 1, kCountFlags = 2 };
+constexpr int kMaxViews = FGS_MAX_BATCH;
+
+// Counters slots in the workspace (uint32).
+enum Counter { kCountK = 0, kCountVisible = 1, kCountFlags = 2, kCountViewK = 3, kNumCounters = 3 + kMaxViews };
 
 // Workspace layout (host computation, shared by the API and the launchers).
+// Per-(view, Gaussian) arrays have n * nviews entries, view-major; the
+// per-tile and per-pixel arrays concatenate the views.
 struct Layout {
   int64_t n = 0;
-  int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0;
+  int32_t nviews = 1;
+  int64_t nv = 0;  // n * nviews
+  int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0;  // view 0
+  int64_t total_tiles = 0, total_pixels = 0;
   int64_t kcap = 0;
   size_t bytes = 0;
   size_t splats, depth_keys, tiles, rects, radii;
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
-  size_t hist, partials;
+  size_t hist, partials, block_tiles;
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
   int tile_bits = 0, tile_passes = 0;
   size_t tile_keys_final, tile_ids_final;
 };
 
-Layout make_layout(int64_t n, int32_t width, int32_t height, int64_t kcap);
+Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32_t* heights, int64_t kcap);
 // Largest kcap whose layout fits in `bytes`; kcap < 0 if even kcap = 0 does not fit.
-Layout fit_layout(int64_t n, int32_t width, int32_t height, size_t bytes);
+Layout fit_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32_t* heights, size_t bytes);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -96,17 +103,30 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct ViewParams {
   double R[9];
   double t[3];
+  double campos[3];  // -R^T t
   double fx, fy, cx, cy;
   double near_dist, theta_max;
   int32_t width, height, tiles_x, tiles_y;
+  uint32_t tile_base;   // first global tile id of the view
+  uint32_t pixel_base;  // first pixel of the view in the per-pixel arrays
   float bg[3];
+};
+
+// Up to kMaxViews views rendered by one set of launches (passed by value).
+struct ViewBatch {
+  int32_t count;
+  ViewParams v[kMaxViews];
+};
+
+struct BatchOut {
+  float* rgb[kMaxViews];  // [3][H_v][W_v] per view
 };
 
 // ---- launchers (each returns hipSuccess or the first HIP error) ----------
 
 // Preprocess: writes splats, depth_keys, tiles, rects, radii, and seeds the
 // depth sort with (key, id) in dkeys_a / dvals_a.
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* ws, const Layout& L,
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* ws, const Layout& L,
                              hipStream_t s);
 
 // Exclusive scan of u32 values read as `mode` says; the item count is
@@ -118,8 +138,11 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
 // Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
 // bits [0, bits), same item-count convention as launch_scan.  The result is
 // in the *_a buffers after an even number of passes, else in *_b.
+// If first_hist_ready, the digit histogram of pass 0 is already in hist
+// (digit-major, one column per radix block).
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
-                             uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id);
+                             uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
+                             bool first_hist_ready = false);
 int radix_passes(int bits);
 int64_t radix_blocks(int64_t max_count, int payload);
 
@@ -129,17 +152,21 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
                           int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, hipStream_t s);
 
 // One (tile, id) pair per covered tile of each depth-ordered visible
-// Gaussian (ids, rect planes rx / ry), at the exclusive-scan offsets.
+// Gaussian (ids, rect planes rx / ry), at the exclusive-scan offsets; K
+// pairs in total.  Also writes the first-pass digit histogram of the tile
+// sort (tile_bits key bits) into hist.
+// Ids are view-major (view * n + Gaussian); the pair's key is the view's
+// tile_base plus the tile index inside the view.
 hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
-                            const uint32_t* d_count, int64_t max_count, int32_t tiles_x, uint32_t* out_keys,
-                            uint32_t* out_vals, hipStream_t s);
+                            const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
+                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 
-hipError_t launch_blend_forward(const ViewParams& v, const uint2* ranges, const uint32_t* ids,
-                                const float4* splats, float* out, float* pixel_T, uint32_t* pixel_last,
+hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
+                                const float4* splats, const BatchOut& out, float* pixel_T, uint32_t* pixel_last,
                                 bool save, hipStream_t s);
 
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids,

@@ -27,13 +27,14 @@ struct PreArgs {
   const float* sh;
   uint32_t n;
   int sh_degree;
-  ViewParams v;
-  double campos[3];
+  // outputs, entry view * n + i
   float4* splats;
   uint32_t* depth_keys;
   uint32_t* tiles;
   uint2* rects;
   int32_t* radii;
+  uint32_t* block_tiles;  // [view][block] tiles touched (multi-view only)
+  ViewBatch batch;
 };
 
 struct Geometry {
@@ -145,54 +146,97 @@ __device__ inline void view_dir(const float* means, uint32_t i, uint32_t n, cons
   for (int a = 0; a < 3; ++a) dir[a] = (float)(vdir[a] / vlen);
 }
 
-template <int DEG>
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// block_tiles[v * nblocks + b] -> out[v]: one block per view.
+__global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block_tiles, uint32_t nblocks,
+                                                           uint32_t* out) {
+  __shared__ uint32_t s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  uint32_t acc = 0;
+  for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) acc += block_tiles[(size_t)blockIdx.x * nblocks + b];
+  acc = wave_sum_u32(acc);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, acc);
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = s_sum;
+}
+
+// One thread per Gaussian, looping over the views of the batch: the
+// parameters are read from HBM once (the compiler keeps the loop-invariant
+// loads in registers).  MULTI = false is the one-view variant, whose
+// registers stay low enough for high occupancy.
+template <int DEG, bool MULTI>
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
+  const bool in_range = i < a.n;
   const uint32_t n = a.n;
-  uint32_t key = 0xFFFFFFFFu, ntiles = 0;
-  uint2 rect = make_uint2(0, 0);
-  int32_t radius = 0;
-  float4 s0 = make_float4(0, 0, 0, 0), s1 = make_float4(0, 0, 0, 0), s2 = make_float4(0, 0, 0, 0);
-  Geometry G;
-  do {
-    if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, false, G)) break;
-    const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
-    const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
-    double rad = ceil(3.0 * sqrt(lam));
-    if (rad > kMaxRadius) rad = kMaxRadius;
-    const double gx = a.v.tiles_x, gy = a.v.tiles_y;
-    const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
-    const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile), vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
-    const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
-    const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
-    const uint32_t area = (x1 - x0) * (y1 - y0);
-    if (area == 0) break;
-    float dir[3], Y[16], rgb[3];
-    double vd[3], vlen;
-    view_dir(a.means, i, n, a.campos, dir, vd, vlen);
-    sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
-    if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) break;
-    const float o = a.opac[i];
-    const double A = G.conic[0], B = G.conic[1];
-    const float hx = (float)G.mu[0], hy = (float)G.mu[1];
-    s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-    s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
-                     (float)(-log2(255.0 * (double)o)));
-    s2 = make_float4(o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
-    const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
-    key = __float_as_uint((float)dist);
-    ntiles = area;
-    rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
-    radius = (int32_t)rad;
-  } while (false);
-  a.splats[3 * (size_t)i + 0] = s0;
-  a.splats[3 * (size_t)i + 1] = s1;
-  a.splats[3 * (size_t)i + 2] = s2;
-  a.depth_keys[i] = key;
-  a.tiles[i] = ntiles;
-  a.rects[i] = rect;
-  a.radii[i] = radius;
+  const int nviews = MULTI ? a.batch.count : 1;
+  for (int vi = 0; vi < nviews; ++vi) {
+    const ViewParams& vp = a.batch.v[vi];
+    uint32_t key = 0xFFFFFFFFu, ntiles = 0;
+    uint2 rect = make_uint2(0, 0);
+    int32_t radius = 0;
+    float4 s0 = make_float4(0, 0, 0, 0), s1 = make_float4(0, 0, 0, 0), s2 = make_float4(0, 0, 0, 0);
+    Geometry G;
+    do {
+      if (!in_range) break;
+      if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
+      const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
+      const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
+      double rad = ceil(3.0 * sqrt(lam));
+      if (rad > kMaxRadius) rad = kMaxRadius;
+      const double gx = vp.tiles_x, gy = vp.tiles_y;
+      const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
+      const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile),
+                   vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
+      const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
+      const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
+      const uint32_t area = (x1 - x0) * (y1 - y0);
+      if (area == 0) break;
+      float dir[3], Y[16], rgb[3];
+      double vd[3], vlen;
+      view_dir(a.means, i, n, vp.campos, dir, vd, vlen);
+      sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
+      if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) break;
+      const float o = a.opac[i];
+      const double A = G.conic[0], B = G.conic[1];
+      const float hx = (float)G.mu[0], hy = (float)G.mu[1];
+      s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+      s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
+                       (float)(-log2(255.0 * (double)o)));
+      s2 = make_float4(o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+      const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
+      key = __float_as_uint((float)dist);
+      ntiles = area;
+      rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+      radius = (int32_t)rad;
+    } while (false);
+    if (in_range) {
+      const size_t e = (size_t)vi * n + i;
+      a.splats[3 * e + 0] = s0;
+      a.splats[3 * e + 1] = s1;
+      a.splats[3 * e + 2] = s2;
+      a.depth_keys[e] = key;
+      a.tiles[e] = ntiles;
+      a.rects[e] = rect;
+      a.radii[e] = radius;
+    }
+    if constexpr (MULTI) {
+      // per-view tile total of this block (a plain store per block, reduced
+      // per view afterwards: no contended atomics on one address)
+      __shared__ uint32_t s_sum;
+      if (threadIdx.x == 0) s_sum = 0;
+      __syncthreads();
+      const uint32_t wsum = wave_sum_u32(ntiles);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, wsum);
+      __syncthreads();
+      if (threadIdx.x == 0) a.block_tiles[(size_t)vi * gridDim.x + blockIdx.x] = s_sum;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,7 +256,6 @@ struct PreBwdArgs {
   uint32_t n;
   int sh_degree;
   ViewParams v;
-  double campos[3];
   const uint32_t* tiles;
   const float* grad2d;  // [9][n]
   float* g_means;
@@ -284,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs 
   // colour
   float dir[3], Y[16], rgb[3];
   double vd[3], vlen;
-  view_dir(a.means, i, n, a.campos, dir, vd, vlen);
+  view_dir(a.means, i, n, a.v.campos, dir, vd, vlen);
   sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
   float gcol[3];
   for (int c = 0; c < 3; ++c) gcol[c] = rgb[c] < 0.0f ? 0.0f : grgb[c];
@@ -343,12 +386,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs 
 
 }  // namespace
 
-static void fill_view(PreArgs& a, const ViewParams& v) {
-  a.v = v;
-  for (int c = 0; c < 3; ++c) a.campos[c] = -(v.R[0 * 3 + c] * v.t[0] + v.R[1 * 3 + c] * v.t[1] + v.R[2 * 3 + c] * v.t[2]);
-}
-
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* ws, const Layout& L,
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* ws, const Layout& L,
                              hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   PreArgs a;
@@ -359,7 +397,8 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* 
   a.sh = g.sh;
   a.n = (uint32_t)g.n;
   a.sh_degree = g.sh_degree;
-  fill_view(a, v);
+  a.batch = b;
+  a.block_tiles = reinterpret_cast<uint32_t*>(ws + L.block_tiles);
   a.splats = reinterpret_cast<float4*>(ws + L.splats);
   a.depth_keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
   a.tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
@@ -367,11 +406,24 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewParams& v, char* 
   a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
   ProfScope prof(s, kKPreprocess);
+  const bool multi = b.count > 1;
+#define FGS_PRE_LAUNCH(D)                                                                  \
+  if (multi)                                                                               \
+    hipLaunchKernelGGL((preprocess_kernel<D, true>), dim3(blocks), dim3(kBlock), 0, s, a); \
+  else                                                                                     \
+    hipLaunchKernelGGL((preprocess_kernel<D, false>), dim3(blocks), dim3(kBlock), 0, s, a);
   switch (g.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(preprocess_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(preprocess_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(preprocess_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    case 0: FGS_PRE_LAUNCH(0) break;
+    case 1: FGS_PRE_LAUNCH(1) break;
+    case 2: FGS_PRE_LAUNCH(2) break;
+    default: FGS_PRE_LAUNCH(3) break;
+  }
+#undef FGS_PRE_LAUNCH
+  if (multi) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(view_sums_kernel, dim3(b.count), dim3(kBlock), 0, s, a.block_tiles, blocks,
+                       reinterpret_cast<uint32_t*>(ws + L.counters) + kCountViewK);
   }
   return hipGetLastError();
 }
@@ -388,7 +440,6 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.n = (uint32_t)g.n;
   a.sh_degree = g.sh_degree;
   a.v = v;
-  for (int c = 0; c < 3; ++c) a.campos[c] = -(v.R[0 * 3 + c] * v.t[0] + v.R[1 * 3 + c] * v.t[1] + v.R[2 * 3 + c] * v.t[2]);
   a.tiles = reinterpret_cast<const uint32_t*>(ws + L.tiles);
   a.grad2d = reinterpret_cast<const float*>(ws + L.grad2d);
   a.g_means = out.means;

@@ -266,61 +266,132 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* tiles, 
 }
 
 // ---- duplication: one pair per (Gaussian, covered tile) --------------------
-// Block b handles depth-ordered Gaussians [b*256, b*256+256) and emits their
-// pairs cooperatively: each output slot finds its Gaussian by binary search
-// over the block's 256 offsets in LDS, so a Gaussian covering thousands of
-// tiles does not serialise one thread, and consecutive lanes write
-// consecutive addresses.
-__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
-                                                           const uint32_t* offsets, const uint32_t* d_count,
-                                                           uint32_t max_count, uint32_t tiles_x, uint32_t* out_keys,
-                                                           uint32_t* out_vals) {
-  __shared__ uint32_t s_off[kBlock + 1];
-  __shared__ uint32_t s_id[kBlock];
-  __shared__ uint32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock];
-  __shared__ uint32_t s_end;
-  const uint32_t count = item_count(d_count, max_count);
-  const uint32_t first = blockIdx.x * kBlock;
-  if (first >= count) return;  // uniform per block
-  const uint32_t j = first + threadIdx.x;
-  const uint32_t last = min(count - first, (uint32_t)kBlock) - 1;
-  if (j < count) {
-    const uint32_t a = rx[j], b = ry[j];
-    const uint32_t x0 = a & 0xFFFFu, y0 = a >> 16, x1 = b & 0xFFFFu, y1 = b >> 16;
-    s_off[threadIdx.x] = offsets[j];
-    s_id[threadIdx.x] = ids[j];
-    s_x0[threadIdx.x] = x0;
-    s_y0[threadIdx.x] = y0;
-    s_w[threadIdx.x] = x1 - x0;
-    if (threadIdx.x == last) s_end = offsets[j] + (x1 - x0) * (y1 - y0);
-  }
-  __syncthreads();
-  if (threadIdx.x > last) s_off[threadIdx.x] = s_end;
-  if (threadIdx.x == 0) s_off[kBlock] = s_end;
-  __syncthreads();
-  const uint32_t start = s_off[0], end = s_end;
-  for (uint32_t o = start + threadIdx.x; o < end; o += kBlock) {
-    // largest k with s_off[k] <= o (every compacted Gaussian has >= 1 tile)
-    int lo = 0, hi = kBlock;  // invariant s_off[lo] <= o < s_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= o) lo = mid; else hi = mid;
-    }
-    const uint32_t local = o - s_off[lo];
-    const uint32_t w = s_w[lo];
-    const uint32_t row = local / w;
-    const uint32_t ty = s_y0[lo] + row, tx = s_x0[lo] + (local - row * w);
-    out_keys[o] = ty * tiles_x + tx;
-    out_vals[o] = s_id[lo];
-  }
+// Balanced by output: block b owns output slots [b*4096, b*4096 + 4096) -- the
+// same slots as radix block b of the tile sort -- whatever Gaussians they
+// belong to, so the near, large splats at the front of the depth order do not
+// pile up in a few blocks.  Thread t walks the 16 consecutive slots
+// 16t .. 16t+15 starting from a binary search for its first Gaussian; the
+// block stages its (tile, id) pairs in LDS and writes them out coalesced.
+// It also counts the first digit of the tile sort for its slots, which is
+// exactly that sort's first histogram.
+constexpr int kDupItems = kBlock * kIptPayload1;  // 4096
+
+__device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
+
+struct TileMap {
+  int32_t count;                     // views
+  uint32_t n;                        // Gaussians per view (ids are view * n + Gaussian)
+  uint32_t tile_base[kMaxViews];
+  uint32_t tiles_x[kMaxViews];
+};
+
+__device__ inline void view_of(const TileMap& m, uint32_t id, uint32_t& base, uint32_t& tx) {
+  const uint32_t v = m.count > 1 ? id / m.n : 0u;
+  base = m.tile_base[v];
+  tx = m.tiles_x[v];
 }
 
-__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* keys, uint32_t K, uint2* ranges) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= K) return;
-  const uint32_t t = keys[j];
-  if (j == 0 || keys[j - 1] != t) ranges[t].x = j;
-  if (j == K - 1 || keys[j + 1] != t) ranges[t].y = j + 1;
+__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
+                                                           const uint32_t* offsets, const uint32_t* d_count,
+                                                           uint32_t max_count, uint32_t K, TileMap map,
+                                                           int digit_bits, uint32_t nblocks, uint32_t* hist,
+                                                           uint32_t* out_keys, uint32_t* out_vals) {
+  __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
+  __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
+  __shared__ uint32_t s_hist[kRadix];
+  __shared__ uint32_t s_first;
+  const uint32_t V = item_count(d_count, max_count);
+  const uint32_t o_begin = blockIdx.x * kDupItems;
+  const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
+  const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
+  if (threadIdx.x == 0) {
+    // largest j with offsets[j] <= o_begin
+    uint32_t lo = 0, hi = V;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (offsets[mid] <= o_begin) lo = mid; else hi = mid;
+    }
+    s_first = lo;
+  }
+  __syncthreads();
+  uint32_t o = o_begin + threadIdx.x * kIptPayload1;
+  if (o < o_end) {
+    // this thread's Gaussian: at most kDupItems Gaussians past the block's first
+    uint32_t lo = s_first, hi = min(V, s_first + (uint32_t)kDupItems + 1u);
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (offsets[mid] <= o) lo = mid; else hi = mid;
+    }
+    uint32_t j = lo;
+    uint32_t next = j + 1 < V ? offsets[j + 1] : K;
+    uint32_t a = rx[j], b = ry[j], g = ids[j];
+    uint32_t x0 = a & 0xFFFFu, y0 = a >> 16, w = (b & 0xFFFFu) - x0;
+    uint32_t tbase, tiles_x;
+    view_of(map, g, tbase, tiles_x);
+    const uint32_t local = o - offsets[j];
+    uint32_t row = local / w, col = local - row * w;
+    for (int k = 0; k < kIptPayload1 && o < o_end; ++k, ++o) {
+      if (o == next) {
+        ++j;
+        next = j + 1 < V ? offsets[j + 1] : K;
+        a = rx[j];
+        b = ry[j];
+        g = ids[j];
+        x0 = a & 0xFFFFu;
+        y0 = a >> 16;
+        w = (b & 0xFFFFu) - x0;
+        view_of(map, g, tbase, tiles_x);
+        row = 0;
+        col = 0;
+      }
+      const uint32_t key = tbase + (y0 + row) * tiles_x + (x0 + col);
+      const uint32_t e = o - o_begin;
+      s_keys[pad_index(e)] = key;
+      s_vals[pad_index(e)] = g;
+      atomicAdd(&s_hist[key & dmask], 1u);
+      if (++col == w) {
+        col = 0;
+        ++row;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t cnt = o_end - o_begin;
+  for (uint32_t e = threadIdx.x; e < cnt; e += kBlock) {
+    out_keys[o_begin + e] = s_keys[pad_index(e)];
+    out_vals[o_begin + e] = s_vals[pad_index(e)];
+  }
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[d * nblocks + blockIdx.x] = s_hist[d];
+}
+
+// ranges[t].x = first index whose key >= t (so ranges[t].y = ranges[t+1].x):
+// one wave per boundary, a 64-ary search of the sorted keys.
+__global__ __launch_bounds__(kBlock) void ranges_kernel(const uint32_t* keys, uint32_t K, uint32_t ntiles,
+                                                        uint2* ranges) {
+  const uint32_t t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);  // boundary: first key >= t
+  const uint32_t lane = threadIdx.x & 63u;
+  if (t > ntiles) return;  // uniform per wave
+  uint32_t lo = 0, hi = K;  // answer in [lo, hi]
+  while (hi - lo > 0) {
+    const uint32_t span = hi - lo;
+    const uint32_t step = (span + 63u) / 64u;
+    const uint32_t idx = lo + lane * step;
+    const bool below = idx < hi && keys[idx] < t;  // probes are increasing in lane
+    const uint64_t m = __ballot(below);
+    const uint32_t nb = (uint32_t)__builtin_popcountll(m);  // probes below t form a prefix
+    if (nb == 0) {
+      hi = lo;
+    } else {
+      const uint32_t last_below = lo + (nb - 1) * step;
+      lo = last_below + 1;
+      hi = min(hi, last_below + step);
+    }
+  }
+  if (lane == 0) {
+    if (t < ntiles) ranges[t].x = lo;
+    if (t > 0) ranges[t - 1].y = lo;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t count) {
@@ -330,7 +401,8 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, uint32_t 
 
 template <int P, int IPT>
 hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
-                           uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id) {
+                           uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
+                           bool first_hist_ready) {
   const int passes = radix_passes(bits);
   const uint32_t nb = (uint32_t)ceil_div(max_count, (int64_t)kBlock * IPT);
   uint32_t* ki = B.keys_a;
@@ -344,7 +416,7 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
   for (int p = 0; p < passes; ++p) {
     const int remaining = bits - shift;
     const int pb = (remaining + (passes - p) - 1) / (passes - p);  // balanced digit widths
-    {
+    if (p > 0 || !first_hist_ready) {
       ProfScope prof(s, hist_id);
       hipLaunchKernelGGL((radix_hist_kernel<IPT>), dim3(nb), dim3(kBlock), 0, s, ki, d_count, (uint32_t)max_count,
                          shift, pb, nb, hist);
@@ -420,11 +492,14 @@ int64_t radix_blocks(int64_t max_count, int payload) {
 }
 
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
-                             uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id) {
+                             uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
+                             bool first_hist_ready) {
   if (max_count <= 0 || radix_passes(bits) == 0) return hipSuccess;
   if (B.payload == 1)
-    return radix_sort_impl<1, kIptPayload1>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id);
-  return radix_sort_impl<3, kIptPayload3>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id);
+    return radix_sort_impl<1, kIptPayload1>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
+                                            first_hist_ready);
+  return radix_sort_impl<3, kIptPayload3>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
+                                          first_hist_ready);
 }
 
 hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
@@ -437,21 +512,31 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
 }
 
 hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
-                            const uint32_t* d_count, int64_t max_count, int32_t tiles_x, uint32_t* out_keys,
-                            uint32_t* out_vals, hipStream_t s) {
-  if (max_count <= 0) return hipSuccess;
+                            const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
+                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s) {
+  if (max_count <= 0 || K <= 0) return hipSuccess;
+  const int passes = radix_passes(tile_bits);
+  const int first_bits = passes > 0 ? (tile_bits + passes - 1) / passes : 0;  // as launch_radix_sort
+  const uint32_t nb = (uint32_t)ceil_div(K, kDupItems);
   ProfScope prof(s, kKDuplicate);
-  hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)ceil_div(max_count, kBlock)), dim3(kBlock), 0, s, ids, rx, ry,
-                     offsets, d_count, (uint32_t)max_count, (uint32_t)tiles_x, out_keys, out_vals);
+  TileMap map;
+  map.count = b.count;
+  map.n = (uint32_t)n;
+  for (int v = 0; v < kMaxViews; ++v) {
+    map.tile_base[v] = v < b.count ? b.v[v].tile_base : 0u;
+    map.tiles_x[v] = v < b.count ? (uint32_t)b.v[v].tiles_x : 1u;
+  }
+  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, ids, rx, ry, offsets, d_count,
+                     (uint32_t)max_count, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
   return hipGetLastError();
 }
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s) {
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)ntiles, s);
-  if (e != hipSuccess || K <= 0) return e;
+  if (K <= 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)ntiles, s);
+  const int waves_per_block = kBlock / 64;
   ProfScope prof(s, kKRanges);
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)ceil_div(K, kBlock)), dim3(kBlock), 0, s, sorted_keys,
-                     (uint32_t)K, ranges);
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)ceil_div((int64_t)ntiles + 1, waves_per_block)), dim3(kBlock), 0, s,
+                     sorted_keys, (uint32_t)K, (uint32_t)ntiles, ranges);
   return hipGetLastError();
 }
 

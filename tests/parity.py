@@ -100,7 +100,13 @@ def compare_tile_lists(st, bins, pre):
     else:
         np.testing.assert_array_equal(keys_g, keys_o)
         np.testing.assert_array_equal(ids_g, ids_o)
-        np.testing.assert_array_equal(st["ranges"], bins["ranges"])
+        # an empty tile's start is arbitrary (the oracle writes 0, the GPU
+        # its insertion point): compare lengths everywhere, starts where
+        # the tile has entries
+        rg, ro = st["ranges"].astype(np.int64), bins["ranges"].astype(np.int64)
+        np.testing.assert_array_equal(rg[:, 1] - rg[:, 0], ro[:, 1] - ro[:, 0])
+        nz = ro[:, 1] > ro[:, 0]
+        np.testing.assert_array_equal(rg[nz], ro[nz])
 
 
 def image_tolerance_check(img_gpu, ora, tol=1e-4):

@@ -37,7 +37,9 @@ def log(*a):
 def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | None:
     """Algorithmic HBM bytes of ONE launch of `name` (byte model)."""
     if name == "preprocess":
-        return 44.0 * N + 4.0 * S * V + 76.0 * N
+        return 52.0 * N + 44.0 * V
+    if name == "color":
+        return 4.0 * N + (4.0 * S + 32.0) * V
     if name == "depth_sort_scatter":
         return 16.0 * N
     if name == "depth_sort_hist":
@@ -50,9 +52,19 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * K
     if name == "ranges":
         return 4.0 * K
+    if name == "sh_backward":
+        return 4.0 * N + (24.0 + 4.0 * S) * V + (12.0 + 4.0 * S) * N
     if name == "preprocess_backward":
-        return (44.0 + 4.0 * S + 40.0) * V + (44.0 + 4.0 * S) * N
+        return 4.0 * N + 80.0 * V + 44.0 * N
     return None
+
+
+def path_bytes(N: int, V: int, K: int, P: int, S: int) -> float:
+    """Algorithmic HBM bytes of one whole fwd+bwd view: every array the tile
+    method needs, read or written the fewest times it must be (the sort as one
+    read + write of the K pairs; extra radix passes are overhead):
+    52 N + (12 S + 316) V + 124 K + 44 P."""
+    return 52.0 * N + (12.0 * S + 316.0) * V + 124.0 * K + 44.0 * P
 
 
 def traffic_for(kernel: str):
@@ -132,7 +144,13 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 2000.0],
                     help="Poisson arrival rates (requests/s) for the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=300, help="requests per rate")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (rocprofv3 counter calibration) and exit")
+    ap.add_argument("--source-sha", action="store_true", help="print the hash of the kernel sources and exit")
     args = ap.parse_args()
+    if args.source_sha:
+        print(source_sha())
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the fisheye rasterizer has no "
               "multi-GPU path in this build", file=sys.stderr)
@@ -147,6 +165,14 @@ def main() -> int:
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration << 18, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB")
+        return 0
     t = time.perf_counter()
     scene = synth.room_scene(args.n, 0, 0.01, 3)
     cam = synth.fisheye_camera(1752, 1168, 180.0)
@@ -208,6 +234,9 @@ def main() -> int:
         else:
             roofline = dict(kernel=dom, bound="alu", achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                             frac=None, traffic=traffic_for(dom), avg_launch_ms=round(d["avg_ms"], 5))
+        pb = path_bytes(N, V, K, P, S)
+        roofline["path"] = dict(bytes_per_view=pb, achieved=round(pb / (ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                                unit="GB/s", frac=round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
         for k, v in kernels.items():
             bb = kernel_bytes(k, N, V, K, P, S)
             if bb is not None:

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
   __shared__ float4 sa[kBlock];
   __shared__ float4 sb[kBlock];
   __shared__ float2 sc[kBlock];
-  const uint32_t gtile = blockIdx.x;
+  const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x);
   int vi = 0;
   while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
   const ViewParams& vp = a.batch.v[vi];
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
   __shared__ uint32_t sid[kBlock];
   __shared__ float acc[9][kBlock];
   __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
+  const int tile = (int)xcd_chunk(blockIdx.x, gridDim.x);
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   int i, j;
   pixel_of_thread(i, j);

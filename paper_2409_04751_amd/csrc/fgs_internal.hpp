@@ -14,10 +14,23 @@ constexpr int kTile = 16;          // 16x16 pixel tiles (Sec. 3.1 "Rendering")
 constexpr int kBlock = 256;        // threads per block = pixels per tile
 constexpr int kItemsPerThread = 16;
 constexpr int kItemsPerBlock = kBlock * kItemsPerThread;  // radix sort / scan tile
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 9;  // widest digit: a 17-bit batch tile id still sorts in 2 passes
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kIptPayload1 = 16;  // radix items per thread with one payload word
 constexpr int kIptPayload3 = 8;   // ... with three payload words (LDS staging size)
+
+// The hardware hands the blocks of a launch to the 8 XCDs round-robin (block
+// b to XCD b % 8), and every XCD has an L2 of its own.  xcd_chunk maps a
+// hardware block to a logical block such that each XCD gets one contiguous
+// range of logical blocks; neighbouring logical blocks (adjacent output runs
+// of a radix scatter, adjacent tiles that gather the same splats) then meet
+// in one L2 instead of eight.  A bijection on [0, nb) for any nb.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_chunk(uint32_t b, uint32_t nb) {
+  const uint32_t x = b % kXcds, k = b / kXcds;
+  const uint32_t q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
 
 // What a device-wide scan reads.
 enum ScanMode {
@@ -50,6 +63,8 @@ enum KernelId {
   kKBlendForward,
   kKBlendBackward,
   kKPreprocessBackward,
+  kKShBackward,
+  kKColor,
   kKNumKernels
 };
 const char* kernel_name(int id);

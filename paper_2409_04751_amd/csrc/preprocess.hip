@@ -124,19 +124,26 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   return true;
 }
 
-// Colour from SH in float: rgb_c = sum_k sh[k*3+c] Y_k(dir) + 0.5 (the
+// The 3 (DEG+1)^2 SH coefficients of Gaussian i, plane k*3+c, into registers.
+template <int DEG>
+__device__ inline void load_sh(const float* __restrict__ sh, uint32_t i, uint32_t n, float c[48]) {
+  constexpr int nc = 3 * (DEG + 1) * (DEG + 1);
+#pragma unroll
+  for (int k = 0; k < nc; ++k) c[k] = sh[(size_t)k * n + i];
+}
+
+// Colour from SH in float: rgb_c = sum_k c[k*3+c] Y_k(dir) + 0.5 (the
 // caller clamps at 0).
 template <int DEG>
-__device__ inline void sh_color(const float* sh, uint32_t i, uint32_t n, const float dir[3], float rgb[3],
-                                float Y[16]) {
+__device__ inline void sh_color(const float c[48], const float dir[3], float rgb[3], float Y[16]) {
   constexpr int nb = (DEG + 1) * (DEG + 1);
   sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
   float acc[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
   for (int k = 0; k < nb; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] += sh[(size_t)(k * 3 + c) * n + i] * Y[k];
-  for (int c = 0; c < 3; ++c) rgb[c] = acc[c];
+    for (int ch = 0; ch < 3; ++ch) acc[ch] += c[k * 3 + ch] * Y[k];
+  for (int ch = 0; ch < 3; ++ch) rgb[ch] = acc[ch];
 }
 
 __device__ inline void view_dir(const float* means, uint32_t i, uint32_t n, const double campos[3], float dir[3],
@@ -165,77 +172,94 @@ __global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block
   if (threadIdx.x == 0) out[blockIdx.x] = s_sum;
 }
 
-// One thread per Gaussian, looping over the views of the batch: the
-// parameters are read from HBM once (the compiler keeps the loop-invariant
-// loads in registers).  MULTI = false is the one-view variant, whose
-// registers stay low enough for high occupancy.
-template <int DEG, bool MULTI>
+// Both forward kernels run one thread per (view, Gaussian) entry on a grid of
+// nviews x blocks-per-view blocks.  The xcd_chunk order puts the views of one
+// Gaussian block on one XCD at about the same time, so the parameters come
+// from HBM once per batch and from that XCD's L2 for the other views, while
+// each thread stays as lean as a single-view one.
+__device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i) {
+  const uint32_t logical = xcd_chunk(blockIdx.x, gridDim.x);
+  vi = logical % nviews;
+  i = (logical / nviews) * kBlock + threadIdx.x;
+}
+
+// Geometry: cull, project, conic, radius, tile rect, depth key.  Culled
+// entries write only their tile count (0) and an all-ones depth key.
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  const bool in_range = i < a.n;
+  uint32_t vi, i;
+  entry_of_block((uint32_t)a.batch.count, vi, i);
+  if (i >= a.n) return;
   const uint32_t n = a.n;
-  const int nviews = MULTI ? a.batch.count : 1;
-  for (int vi = 0; vi < nviews; ++vi) {
-    const ViewParams& vp = a.batch.v[vi];
-    uint32_t key = 0xFFFFFFFFu, ntiles = 0;
-    uint2 rect = make_uint2(0, 0);
-    int32_t radius = 0;
-    float4 s0 = make_float4(0, 0, 0, 0), s1 = make_float4(0, 0, 0, 0), s2 = make_float4(0, 0, 0, 0);
-    Geometry G;
-    do {
-      if (!in_range) break;
-      if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
-      const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
-      const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
-      double rad = ceil(3.0 * sqrt(lam));
-      if (rad > kMaxRadius) rad = kMaxRadius;
-      const double gx = vp.tiles_x, gy = vp.tiles_y;
-      const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
-      const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile),
-                   vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
-      const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
-      const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
-      const uint32_t area = (x1 - x0) * (y1 - y0);
-      if (area == 0) break;
-      float dir[3], Y[16], rgb[3];
-      double vd[3], vlen;
-      view_dir(a.means, i, n, vp.campos, dir, vd, vlen);
-      sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
-      if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) break;
-      const float o = a.opac[i];
-      const double A = G.conic[0], B = G.conic[1];
-      const float hx = (float)G.mu[0], hy = (float)G.mu[1];
-      s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-      s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
-                       (float)(-log2(255.0 * (double)o)));
-      s2 = make_float4(o, fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
-      const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
-      key = __float_as_uint((float)dist);
-      ntiles = area;
-      rect = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
-      radius = (int32_t)rad;
-    } while (false);
-    if (in_range) {
-      const size_t e = (size_t)vi * n + i;
-      a.splats[3 * e + 0] = s0;
-      a.splats[3 * e + 1] = s1;
-      a.splats[3 * e + 2] = s2;
-      a.depth_keys[e] = key;
-      a.tiles[e] = ntiles;
-      a.rects[e] = rect;
-      a.radii[e] = radius;
+  const ViewParams& vp = a.batch.v[vi];
+  const size_t e = (size_t)vi * n + i;
+  uint32_t key = 0xFFFFFFFFu, ntiles = 0;
+  Geometry G;
+  do {
+    if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
+    const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
+    const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
+    double rad = ceil(3.0 * sqrt(lam));
+    if (rad > kMaxRadius) rad = kMaxRadius;
+    const double gx = vp.tiles_x, gy = vp.tiles_y;
+    const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
+    const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile),
+                 vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
+    const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
+    const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
+    const uint32_t area = (x1 - x0) * (y1 - y0);
+    if (area == 0) break;
+    const float o = a.opac[i];
+    const double A = G.conic[0], B = G.conic[1];
+    const float hx = (float)G.mu[0], hy = (float)G.mu[1];
+    a.splats[3 * e + 0] = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+    a.splats[3 * e + 1] = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A),
+                                      (float)(-0.5 * kLog2e / (G.det * A)), (float)(-log2(255.0 * (double)o)));
+    a.rects[e] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+    a.radii[e] = (int32_t)rad;
+    const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
+    key = __float_as_uint((float)dist);
+    ntiles = area;
+  } while (false);
+  a.depth_keys[e] = key;
+  a.tiles[e] = ntiles;
+}
+
+// SH colour of every entry the geometry kernel kept.  An entry whose colour
+// is not finite is culled here, before the scans read the tile counts.  With
+// several views each block also leaves its tile total in
+// block_tiles[view][block] (a plain store per block, summed per view
+// afterwards: no contended atomics).
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void color_kernel(PreArgs a) {
+  uint32_t vi, i;
+  entry_of_block((uint32_t)a.batch.count, vi, i);
+  const uint32_t n = a.n;
+  const size_t e = (size_t)vi * n + i;
+  uint32_t ntiles = i < n ? a.tiles[e] : 0u;
+  if (ntiles != 0) {
+    float c[48];
+    load_sh<DEG>(a.sh, i, n, c);
+    float dir[3], Y[16], rgb[3];
+    double vd[3], vlen;
+    view_dir(a.means, i, n, a.batch.v[vi].campos, dir, vd, vlen);
+    sh_color<DEG>(c, dir, rgb, Y);
+    if (isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2])) {
+      a.splats[3 * e + 2] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+    } else {
+      a.tiles[e] = 0;
+      a.depth_keys[e] = 0xFFFFFFFFu;
+      ntiles = 0;
     }
-    if constexpr (MULTI) {
-      // per-view tile total of this block (a plain store per block, reduced
-      // per view afterwards: no contended atomics on one address)
-      __shared__ uint32_t s_sum;
-      if (threadIdx.x == 0) s_sum = 0;
-      __syncthreads();
-      const uint32_t wsum = wave_sum_u32(ntiles);
-      if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, wsum);
-      __syncthreads();
-      if (threadIdx.x == 0) a.block_tiles[(size_t)vi * gridDim.x + blockIdx.x] = s_sum;
-    }
+  }
+  if (a.batch.count > 1) {  // uniform
+    __shared__ uint32_t s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    const uint32_t wsum = wave_sum_u32(ntiles);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, wsum);
+    __syncthreads();
+    // thread 0 holds the block's first Gaussian, so i / kBlock is the block of the view
+    if (threadIdx.x == 0) a.block_tiles[(size_t)vi * (gridDim.x / a.batch.count) + i / kBlock] = s_sum;
   }
 }
 
@@ -266,26 +290,72 @@ struct PreBwdArgs {
   float* g_means2d;
 };
 
+// Colour part of the backward, one thread per Gaussian: dL/dSH and the term
+// of dL/dmu that flows through the view direction of the SH evaluation
+// (written to g_means; the geometry kernel adds its own term).  Streams the
+// 4S bytes of coefficients in and 4S bytes of gradient out at low register
+// count, apart from the fp64 geometry.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs a) {
+__global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
   const uint32_t n = a.n;
   constexpr int nb = (DEG + 1) * (DEG + 1);
+  if (a.tiles[i] == 0) {
+    for (int k = 0; k < 3 * nb; ++k) a.g_sh[(size_t)k * n + i] = 0.0f;
+    for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = 0.0f;
+    return;
+  }
+  const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
+  float c[48];
+  load_sh<DEG>(a.sh, i, n, c);
+  float dir[3], Y[16], rgb[3];
+  double vd[3], vlen;
+  view_dir(a.means, i, n, a.v.campos, dir, vd, vlen);
+  sh_color<DEG>(c, dir, rgb, Y);
+  float gcol[3];
+  for (int ch = 0; ch < 3; ++ch) gcol[ch] = rgb[ch] < 0.0f ? 0.0f : grgb[ch];
+  float wk[16];
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    float w = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      a.g_sh[(size_t)(k * 3 + ch) * n + i] = Y[k] * gcol[ch];
+      w += c[k * 3 + ch] * gcol[ch];
+    }
+    wk[k] = w;
+  }
+  double gm[3] = {0.0, 0.0, 0.0};
+  if constexpr (DEG > 0) {
+    float gd[3];
+    sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wk, gd);
+    // d dir / d v = (I - dir dir^T) / |v|
+    const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
+    for (int e = 0; e < 3; ++e) gm[e] = ((double)gd[e] - (double)dir[e] * dd) / vlen;
+  }
+  for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)gm[c];
+}
+
+// Geometry part of the backward (Sec. 4.3): from dL/d(mu_p, conic, opacity)
+// to dL/d(mu, s, q, o) through the fisheye Jacobian, in fp64.  Runs after
+// sh_backward_kernel and adds to the direction term it left in g_means.
+__global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const uint32_t n = a.n;
   Geometry G;
   const bool visible = a.tiles[i] != 0 && compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
   if (!visible) {
     for (int c = 0; c < 3; ++c) { a.g_means[c * n + i] = 0.0f; a.g_scales[c * n + i] = 0.0f; }
     for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = 0.0f;
     a.g_opac[i] = 0.0f;
-    for (int k = 0; k < 3 * nb; ++k) a.g_sh[(size_t)k * n + i] = 0.0f;
     if (a.g_means2d) { a.g_means2d[i] = 0.0f; a.g_means2d[n + i] = 0.0f; }
     return;
   }
   const double gmu[2] = {a.grad2d[0 * (size_t)n + i], a.grad2d[1 * (size_t)n + i]};
   const double gA = a.grad2d[2 * (size_t)n + i], gB = a.grad2d[3 * (size_t)n + i], gC = a.grad2d[4 * (size_t)n + i];
   const float go = a.grad2d[5 * (size_t)n + i];
-  const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
   // H = dL/dSigma' = -Q Gs Q with Gs = [[gA, gB/2], [gB/2, gC]]
   const double Q00 = G.conic[0], Q01 = G.conic[1], Q11 = G.conic[2];
   const double G00 = gA, G01 = 0.5 * gB, G11 = gC;
@@ -324,33 +394,7 @@ __global__ __launch_bounds__(kBlock) void preprocess_backward_kernel(PreBwdArgs 
   double gm[3];
   for (int c = 0; c < 3; ++c)
     gm[c] = a.v.R[0 * 3 + c] * gpc[0] + a.v.R[1 * 3 + c] * gpc[1] + a.v.R[2 * 3 + c] * gpc[2];
-  // colour
-  float dir[3], Y[16], rgb[3];
-  double vd[3], vlen;
-  view_dir(a.means, i, n, a.v.campos, dir, vd, vlen);
-  sh_color<DEG>(a.sh, i, n, dir, rgb, Y);
-  float gcol[3];
-  for (int c = 0; c < 3; ++c) gcol[c] = rgb[c] < 0.0f ? 0.0f : grgb[c];
-  float wk[16];
-#pragma unroll
-  for (int k = 0; k < nb; ++k) {
-    float w = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t plane = (size_t)(k * 3 + c) * n + i;
-      a.g_sh[plane] = Y[k] * gcol[c];
-      w += a.sh[plane] * gcol[c];
-    }
-    wk[k] = w;
-  }
-  if constexpr (DEG > 0) {
-    float gd[3];
-    sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wk, gd);
-    // d dir / d v = (I - dir dir^T) / |v|
-    const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
-    for (int e = 0; e < 3; ++e) gm[e] += ((double)gd[e] - (double)dir[e] * dd) / vlen;
-  }
-  for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)gm[c];
+  for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)(gm[c] + (double)a.g_means[c * n + i]);
   // Sigma = M M^T, M = R S: dL/dM = 2 dS M
   double M[9];
   for (int r = 0; r < 3; ++r)
@@ -405,13 +449,14 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* w
   a.rects = reinterpret_cast<uint2*>(ws + L.rects);
   a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
-  ProfScope prof(s, kKPreprocess);
   const bool multi = b.count > 1;
-#define FGS_PRE_LAUNCH(D)                                                                  \
-  if (multi)                                                                               \
-    hipLaunchKernelGGL((preprocess_kernel<D, true>), dim3(blocks), dim3(kBlock), 0, s, a); \
-  else                                                                                     \
-    hipLaunchKernelGGL((preprocess_kernel<D, false>), dim3(blocks), dim3(kBlock), 0, s, a);
+  const dim3 grid(blocks * (unsigned)b.count);
+  {
+    ProfScope prof(s, kKPreprocess);
+    hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kBlock), 0, s, a);
+  }
+  ProfScope prof(s, kKColor);
+#define FGS_PRE_LAUNCH(D) hipLaunchKernelGGL((color_kernel<D>), grid, dim3(kBlock), 0, s, a);
   switch (g.sh_degree) {
     case 0: FGS_PRE_LAUNCH(0) break;
     case 1: FGS_PRE_LAUNCH(1) break;
@@ -449,13 +494,17 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.g_sh = out.sh;
   a.g_means2d = out.means2d;
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
-  ProfScope prof(s, kKPreprocessBackward);
-  switch (g.sh_degree) {
-    case 0: hipLaunchKernelGGL(preprocess_backward_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(preprocess_backward_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(preprocess_backward_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(preprocess_backward_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+  {
+    ProfScope prof(s, kKShBackward);
+    switch (g.sh_degree) {
+      case 0: hipLaunchKernelGGL(sh_backward_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+      case 1: hipLaunchKernelGGL(sh_backward_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+      case 2: hipLaunchKernelGGL(sh_backward_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+      default: hipLaunchKernelGGL(sh_backward_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
   }
+  ProfScope prof(s, kKPreprocessBackward);
+  hipLaunchKernelGGL(geometry_backward_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

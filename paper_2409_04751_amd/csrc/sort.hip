@@ -158,16 +158,22 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) h[d] = 0;
   __syncthreads();
   const uint32_t base = blockIdx.x * (kBlock * IPT);
-  for (int k = 0; k < IPT; ++k) {
+  uint32_t key[IPT];
+  for (int k = 0; k < IPT; ++k) {  // all loads in flight before the first atomic
     const uint32_t idx = base + k * kBlock + threadIdx.x;
-    if (idx < count) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    key[k] = idx < count ? keys[idx] : 0xFFFFFFFFu;
+  }
+  for (int k = 0; k < IPT; ++k) {
+    if (base + k * kBlock + threadIdx.x < count) atomicAdd(&h[(key[k] >> shift) & mask], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[d * nblocks + blockIdx.x] = h[d];
 }
 
 // Stable scatter of one pass; P u32 payload words per key.
-template <int P, int IPT>
+// RB: the widest digit this instantiation handles (its LDS tables are 1 << RB
+// long, so narrow digits keep the footprint, and the occupancy, of their width)
+template <int P, int IPT, int RB>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* keys_in, ValPtrs<P> vin,
                                                                uint32_t* keys_out, ValPtrs<P> vout,
                                                                const uint32_t* d_count, uint32_t max_count, int shift,
@@ -176,30 +182,42 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
   constexpr int kItems = kBlock * IPT;
   constexpr int kPerWave = kItems / kWaves;
   constexpr int kIters = kPerWave / 64;
-  __shared__ uint32_t wave_count[kWaves][kRadix];
-  __shared__ uint32_t local_start[kRadix];
-  __shared__ uint32_t global_start[kRadix];
+  constexpr uint32_t kR = 1u << RB;
+  static_assert(kR <= 2 * kBlock, "two digits per thread");
+  static_assert(kItems <= 65535, "per-wave counts and prefixes fit 16 bits");
+  // 16-bit per-wave counters and one start table (local start while staging,
+  // then global minus local start while writing) keep a 9-bit digit at the
+  // occupancy of an 8-bit one
+  __shared__ uint16_t wave_count[kWaves][kR];
+  __shared__ uint32_t start[kR];
   __shared__ uint32_t stage_keys[kItems];
   __shared__ uint32_t stage_vals[P][kItems];
   __shared__ uint32_t smem[kWaves + 1];
 
   const uint32_t count = item_count(d_count, max_count);
-  const uint32_t block_base = blockIdx.x * kItems;
+  const uint32_t chunk = xcd_chunk(blockIdx.x, nblocks);
+  const uint32_t block_base = chunk * kItems;
   if (block_base >= count) return;  // uniform per block
   const uint32_t radix = 1u << bits, mask = radix - 1u;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t d = threadIdx.x; d < kRadix; d += kBlock) {
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
     for (int w = 0; w < kWaves; ++w) wave_count[w][d] = 0;
   }
   __syncthreads();
 
   const uint32_t wave_base = block_base + wave * kPerWave;
   uint32_t my_key[kIters], my_rank[kIters], my_val[kIters][P];
+  // every load of the tile is issued before the first one is used
   for (int it = 0; it < kIters; ++it) {
     const uint32_t idx = wave_base + it * 64 + lane;
     const bool valid = idx < count;
-    const uint32_t key = valid ? keys_in[idx] : 0u;
+    my_key[it] = valid ? keys_in[idx] : 0u;
     for (int q = 0; q < P; ++q) my_val[it][q] = valid ? vin.p[q][idx] : 0u;
+  }
+  for (int it = 0; it < kIters; ++it) {
+    const uint32_t idx = wave_base + it * 64 + lane;
+    const bool valid = idx < count;
+    const uint32_t key = my_key[it];
     const uint32_t digit = (key >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -212,40 +230,48 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
       rank = before + popc_below(peers);
       // the highest peer lane publishes the new count
       const uint32_t last_lane = 63u - (uint32_t)__builtin_clzll(peers);
-      if (lane == last_lane) wave_count[wave][digit] = before + (uint32_t)__builtin_popcountll(peers);
+      if (lane == last_lane) wave_count[wave][digit] = (uint16_t)(before + (uint32_t)__builtin_popcountll(peers));
     }
-    my_key[it] = key;
     my_rank[it] = rank;
   }
   __syncthreads();
-  // per digit: exclusive prefix over waves, block count, local and global starts
-  uint32_t block_count = 0;
-  if (threadIdx.x < radix) {
-    const uint32_t d = threadIdx.x;
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = wave_count[w][d];
-      wave_count[w][d] = block_count;
-      block_count += c;
+  // per digit: exclusive prefix over waves, block count, local and global
+  // starts; thread t owns digits 2t and 2t+1
+  uint32_t dcount[2] = {0u, 0u}, gstart[2] = {0u, 0u};
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t d = 2u * threadIdx.x + q;
+    if (d < radix) {
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wave_count[w][d];
+        wave_count[w][d] = (uint16_t)dcount[q];
+        dcount[q] += c;
+      }
+      gstart[q] = scanned_hist[d * nblocks + chunk];
     }
-    global_start[d] = scanned_hist[d * nblocks + blockIdx.x];
   }
   uint32_t total;
-  const uint32_t ls = block_exclusive_scan(block_count, smem, total);
-  if (threadIdx.x < radix) local_start[threadIdx.x] = ls;
+  const uint32_t ls = block_exclusive_scan(dcount[0] + dcount[1], smem, total);
+  const uint32_t lstart[2] = {ls, ls + dcount[0]};
+  for (int q = 0; q < 2; ++q)
+    if (2u * threadIdx.x + q < radix) start[2u * threadIdx.x + q] = lstart[q];
   __syncthreads();
   for (int it = 0; it < kIters; ++it) {
     if (my_rank[it] == 0xFFFFFFFFu) continue;
     const uint32_t digit = (my_key[it] >> shift) & mask;
-    const uint32_t pos = local_start[digit] + wave_count[wave][digit] + my_rank[it];
+    const uint32_t pos = start[digit] + wave_count[wave][digit] + my_rank[it];
     stage_keys[pos] = my_key[it];
     for (int q = 0; q < P; ++q) stage_vals[q][pos] = my_val[it][q];
   }
+  __syncthreads();
+  // item e of the staged block goes to global_start + (e - local_start)
+  for (int q = 0; q < 2; ++q)
+    if (2u * threadIdx.x + q < radix) start[2u * threadIdx.x + q] = gstart[q] - lstart[q];
   __syncthreads();
   const uint32_t nvalid = min((uint32_t)kItems, count - block_base);
   for (uint32_t e = threadIdx.x; e < nvalid; e += kBlock) {
     const uint32_t key = stage_keys[e];
     const uint32_t digit = (key >> shift) & mask;
-    const uint32_t dst = global_start[digit] + (e - local_start[digit]);
+    const uint32_t dst = start[digit] + e;
     keys_out[dst] = key;
     for (int q = 0; q < P; ++q) vout.p[q][dst] = stage_vals[q][e];
   }
@@ -425,8 +451,15 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
     if (e != hipSuccess) return e;
     {
       ProfScope prof(s, scatter_id);
-      hipLaunchKernelGGL((radix_scatter_kernel<P, IPT>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
-                         (uint32_t)max_count, shift, pb, nb, hist);
+      if (pb <= 7)
+        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 7>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
+                           (uint32_t)max_count, shift, pb, nb, hist);
+      else if (pb == 8)
+        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 8>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
+                           (uint32_t)max_count, shift, pb, nb, hist);
+      else
+        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, kRadixBits>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo,
+                           d_count, (uint32_t)max_count, shift, pb, nb, hist);
     }
     shift += pb;
     uint32_t* t = ki;

@@ -1,0 +1,110 @@
+"""Summaries of rocprofv3 CSV output (kernel stats and PMC counters).
+
+    python -m paper_2409_04751_amd.rocprof_summary stats KERNEL_STATS.csv
+    python -m paper_2409_04751_amd.rocprof_summary traffic \
+        --kernel radix_scatter_kernel<1 --name tile_sort_scatter \
+        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
+        --copy-bytes 1073741824 --out profiles/traffic_tile_sort_scatter.json
+
+`traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two
+separate `rocprofv3 --pmc` runs) into HBM bytes per launch of one kernel.
+Each counter is scaled by what it reads for a plain device copy of a known
+size: the factor is (copy bytes / 1024) / counter value for the copy kernel,
+so a counter that samples only part of the memory channels, or counts in
+other units, is corrected by the same ratio.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import os
+import sys
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_stats(path: str) -> list[dict]:
+    """Rows of a rocprofv3 `*_kernel_stats.csv`, heaviest first."""
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append(dict(name=r["Name"], calls=int(r["Calls"]), total_ns=float(r["TotalDurationNs"]),
+                             avg_ns=float(r["AverageNs"]), pct=float(r["Percentage"])))
+    rows.sort(key=lambda r: -r["total_ns"])
+    return rows
+
+
+def counter_means(path: str, kernel_substr: str, counter: str) -> tuple[float, int]:
+    """Mean value of `counter` per dispatch over kernels whose name contains
+    `kernel_substr`; returns (mean, dispatches)."""
+    per_dispatch: dict[str, float] = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter or kernel_substr not in r["Kernel_Name"]:
+                continue
+            d = r["Dispatch_Id"]
+            per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
+    if not per_dispatch:
+        raise SystemExit(f"no {counter} rows for a kernel matching {kernel_substr!r} in {path}")
+    return sum(per_dispatch.values()) / len(per_dispatch), len(per_dispatch)
+
+
+def traffic(args) -> dict:
+    copy_kib = args.copy_bytes / 1024.0
+    cf, _ = counter_means(args.copy_fetch, COPY_KERNEL, "FETCH_SIZE")
+    cw, _ = counter_means(args.copy_write, COPY_KERNEL, "WRITE_SIZE")
+    fetch_factor = copy_kib / cf
+    write_factor = copy_kib / cw
+    fk, nf = counter_means(args.fetch, args.kernel, "FETCH_SIZE")
+    wk, nw = counter_means(args.write, args.kernel, "WRITE_SIZE")
+    read_b = fk * 1024.0 * fetch_factor
+    write_b = wk * 1024.0 * write_factor
+    rec = dict(kernel=args.name, kernel_match=args.kernel, dispatches=dict(fetch=nf, write=nw),
+               fetch_kib_raw=round(fk, 1), write_kib_raw=round(wk, 1),
+               copy_calibration=dict(bytes=args.copy_bytes, fetch_kib=round(cf, 1), write_kib=round(cw, 1),
+                                     fetch_factor=round(fetch_factor, 4), write_factor=round(write_factor, 4)),
+               read_bytes_per_launch=round(read_b), write_bytes_per_launch=round(write_b),
+               bytes_per_launch=round(read_b + write_b))
+    if args.source_sha:
+        rec["source_sha"] = args.source_sha
+    if args.command:
+        rec["command"] = args.command
+    return rec
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--top", type=int, default=30)
+    t = sub.add_parser("traffic")
+    for k in ("kernel", "name", "fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--source-sha", default=None)
+    t.add_argument("--command", default=None)
+    t.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        rows = kernel_stats(args.csv)
+        total = sum(r["total_ns"] for r in rows)
+        print(f"{'kernel':<70} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'pct':>6}")
+        for r in rows[:args.top]:
+            print(f"{r['name'][:70]:<70} {r['calls']:>6} {r['total_ns'] / 1e6:>10.3f} {r['avg_ns'] / 1e3:>10.2f} "
+                  f"{r['pct']:>6.2f}")
+        print(f"{'total':<70} {'':>6} {total / 1e6:>10.3f}")
+        return 0
+    rec = traffic(args)
+    text = json.dumps(rec, indent=1)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

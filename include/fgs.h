@@ -103,9 +103,9 @@ typedef struct fgs_layout {
   int32_t width, height, tiles_x, tiles_y;
   int64_t k_capacity;  /* intersections the workspace can hold */
   size_t bytes;        /* bytes the layout uses (<= workspace size) */
-  size_t splats;       /* float4 [n][3]: (mu_x hi, mu_y hi, mu_x lo, mu_y lo),
-                          (-A/2 log2 e, B/A, -(C - B^2/A)/2 log2 e, log2(1/(255 o))),
-                          (o, r, g, b) */
+  size_t splats;       /* float4 [n][2]: (mu_x hi, mu_y hi, mu_x lo, mu_y lo),
+                          (-A/2 log2 e, B/A, -(C - B^2/A)/2 log2 e, log2(1/(255 o))) */
+  size_t colors;       /* float4 [n]: (o, r, g, b) */
   size_t depth_keys;   /* uint32 [n]: float bits of |mu_c|, 0xFFFFFFFF if culled */
   size_t tiles;        /* uint32 [n]: tiles touched (0 if culled) */
   size_t rects;        /* uint32 [n][2]: x0 | y0 << 16, x1 | y1 << 16 (half-open) */

@@ -48,7 +48,7 @@ class fgs_grads(ctypes.Structure):
 class fgs_layout(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("k_capacity", ctypes.c_int64),
-                ("bytes", c_size), ("splats", c_size), ("depth_keys", c_size), ("tiles", c_size), ("rects", c_size),
+                ("bytes", c_size), ("splats", c_size), ("colors", c_size), ("depth_keys", c_size), ("tiles", c_size), ("rects", c_size),
                 ("radii", c_size), ("depth_order", c_size), ("offsets", c_size), ("tile_keys", c_size),
                 ("tile_ids", c_size), ("ranges", c_size), ("grad2d", c_size), ("pixel_T", c_size),
                 ("pixel_last", c_size), ("counters", c_size)]

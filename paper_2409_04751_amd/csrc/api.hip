@@ -58,7 +58,8 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
     return o;
   };
   L.counters = take(kNumCounters * sizeof(uint32_t));
-  L.splats = take(nv * 3 * sizeof(float4));
+  L.splats = take(nv * 2 * sizeof(float4));
+  L.colors = take(nv * sizeof(float4));
   L.depth_keys = take(nv * 4);
   L.tiles = take(nv * 4);
   L.rects = take(nv * 8);
@@ -178,6 +179,7 @@ void export_layout(const Layout& L, fgs_layout* out) {
   out->k_capacity = L.kcap;
   out->bytes = L.bytes;
   out->splats = L.splats;
+  out->colors = L.colors;
   out->depth_keys = L.depth_keys;
   out->tiles = L.tiles;
   out->rects = L.rects;
@@ -277,7 +279,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);
   HIP_TRY(launch_ranges(U(L.tile_keys_final), K, ranges, (int32_t)L.total_tiles, s), "ranges");
   HIP_TRY(launch_blend_forward(b, L.total_tiles, ranges, U(L.tile_ids_final),
-                               reinterpret_cast<const float4*>(ws + L.splats), out,
+                               reinterpret_cast<const float4*>(ws + L.splats),
+                               reinterpret_cast<const float4*>(ws + L.colors), out,
                                reinterpret_cast<float*>(ws + L.pixel_T), U(L.pixel_last),
                                (flags & FGS_SAVE_PIXEL_STATE) != 0, s),
           "blend forward");
@@ -374,7 +377,8 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * g->n, s), "clear grad2d");
   HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges),
                                 reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final),
-                                reinterpret_cast<const float4*>(ws + L.splats), dL_drgb,
+                                reinterpret_cast<const float4*>(ws + L.splats),
+                                reinterpret_cast<const float4*>(ws + L.colors), dL_drgb,
                                 reinterpret_cast<const float*>(ws + L.pixel_T),
                                 reinterpret_cast<const uint32_t*>(ws + L.pixel_last),
                                 reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, g->n, s),

@@ -31,6 +31,7 @@ struct BlendArgs {
   const uint2* ranges;
   const uint32_t* ids;
   const float4* splats;
+  const float4* colors;
   float* pixel_T;
   uint32_t* pixel_last;
   int save;
@@ -51,11 +52,11 @@ struct Staged {
   float2 c;  // g, b
 };
 
-__device__ inline void stage_splat(const float4* splats, uint32_t g, float x0, float y0, float4& a, float4& b,
-                                   float2& c) {
-  const float4 p = splats[3 * (size_t)g + 0];
-  const float4 q = splats[3 * (size_t)g + 1];
-  const float4 r = splats[3 * (size_t)g + 2];
+__device__ inline void stage_splat(const float4* splats, const float4* colors, uint32_t g, float x0, float y0,
+                                   float4& a, float4& b, float2& c) {
+  const float4 p = splats[2 * (size_t)g + 0];
+  const float4 q = splats[2 * (size_t)g + 1];
+  const float4 r = colors[g];
   a = make_float4((p.x - x0) + p.z, (p.y - y0) + p.w, q.x, q.y);
   b = make_float4(q.z, q.w, r.x, r.y);
   c = make_float2(r.z, r.w);
@@ -70,12 +71,80 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
   return __builtin_fmaf(a.z * t, t, (b.x * dy) * dy);
 }
 
+// Quadrants of the tile (wave w owns the 8x8 pixel block (w & 1, w >> 1))
+// that can hold a pixel at which the splat is not skipped.  Such a pixel has
+// |A'| t^2 + |D'| dy^2 <= P = -q2min with t = dx + beta dy: an ellipse with
+// half extents ry = sqrt(P / |D'|) in y and rx = sqrt(P (1/|A'| + beta^2/|D'|))
+// in x.  The box is widened by 1% + 1/16 px, so the float evaluation of the
+// per-pixel test cannot pass outside it; a non-finite extent, or P so small
+// that the per-pixel terms could underflow, keeps every quadrant, and P < 0
+// (opacity below 1/255) keeps none, as the per-pixel test would.  Lists of
+// the entries per quadrant let each wave skip splats that cannot reach its
+// 64 pixels; the tile lists themselves are unchanged.
+__device__ inline uint32_t quadrant_mask(const float4& a, const float4& b) {
+  const float P = -b.y;
+  if (!(P > 1e-6f)) return P >= 0.0f ? 0xFu : 0u;
+  // t = dx + beta dy loses ~1e-7 (1 + |beta|) px to rounding: past |beta| =
+  // 1e3 that could approach the margin, so such slivers keep every quadrant
+  if (!(fabsf(a.w) <= 1e3f)) return 0xFu;
+  const float iA = 1.0f / fabsf(a.z), iD = 1.0f / fabsf(b.x);
+  constexpr float kBig = 1e30f;
+  float ry = sqrtf(P * iD), rx = sqrtf(P * __builtin_fmaf(a.w * a.w, iD, iA));
+  ry = ry <= kBig ? __builtin_fmaf(ry, 1.01f, 0.0625f) : kBig;
+  rx = rx <= kBig ? __builtin_fmaf(rx, 1.01f, 0.0625f) : kBig;
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float qx0 = (float)((q & 1) * 8), qy0 = (float)((q >> 1) * 8);
+    if (a.x + rx >= qx0 && a.x - rx <= qx0 + 7.0f && a.y + ry >= qy0 && a.y - ry <= qy0 + 7.0f) m |= 1u << q;
+  }
+  return m;
+}
+
+// Per-quadrant lists of the staged entries, in entry order.
+struct QuadLists {
+  uint8_t idx[4][kBlock];
+  uint32_t wcount[4][4];  // [staging wave][quadrant]
+};
+
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Called by all threads after thread t staged entry t with quadrant mask m
+// (0 for no entry); returns the length of the calling wave's list.  Contains
+// the barriers that publish the staged records too.
+__device__ inline int build_quad_lists(uint32_t m, QuadLists& Q) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t bal[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bal[q] = __ballot((m >> q) & 1u);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Q.wcount[wave][q] = (uint32_t)__builtin_popcountll(bal[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if ((m >> q) & 1u) {
+      uint32_t off = 0;
+      for (uint32_t w = 0; w < wave; ++w) off += Q.wcount[w][q];
+      Q.idx[q][off + lanes_below(bal[q])] = (uint8_t)threadIdx.x;
+    }
+  }
+  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave] + Q.wcount[2][wave] + Q.wcount[3][wave]);
+  __syncthreads();
+  return n;
+}
+
 // One block per tile of every view of the batch (tiles are numbered view by
 // view; the view of a block is found from the views' first tile ids).
 __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
   __shared__ float4 sa[kBlock];
   __shared__ float4 sb[kBlock];
   __shared__ float2 sc[kBlock];
+  __shared__ QuadLists Q;
+  const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x);
   int vi = 0;
   while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
@@ -95,11 +164,20 @@ __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
   for (uint32_t base = r.x; base < r.y; base += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t k = base + threadIdx.x;
-    if (k < r.y) stage_splat(a.splats, a.ids[k], x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, r.y - base);
+    uint32_t m = 0;
+    if (k < r.y) {
+      float4 ta, tb;
+      float2 tc;
+      stage_splat(a.splats, a.colors, a.ids[k], x0, y0, ta, tb, tc);
+      sa[threadIdx.x] = ta;
+      sb[threadIdx.x] = tb;
+      sc[threadIdx.x] = tc;
+      m = quadrant_mask(ta, tb);
+    }
+    const int cnt = build_quad_lists(m, Q);
     if (!done) {
-      for (int e = 0; e < cnt; ++e) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
         const float4 ga = sa[e], gb = sb[e];
         float dx, dy, t;
         const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
@@ -138,6 +216,7 @@ struct BlendBwdArgs {
   const uint2* ranges;
   const uint32_t* ids;
   const float4* splats;
+  const float4* colors;
   int32_t width, height, tiles_x;
   float bg[3];
   const float* dL;
@@ -199,6 +278,8 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
   __shared__ uint32_t sid[kBlock];
   __shared__ float acc[9][kBlock];
   __shared__ uint32_t s_maxlast;
+  __shared__ QuadLists Q;
+  const uint32_t wave = threadIdx.x >> 6;
   const int tile = (int)xcd_chunk(blockIdx.x, gridDim.x);
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   int i, j;
@@ -225,11 +306,19 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
     for (uint32_t base = r.x; base < r.y; base += kBlock) {
       if (__syncthreads_count(!done) == 0) break;
       const uint32_t k = base + threadIdx.x;
-      if (k < r.y) stage_splat(a.splats, a.ids[k], x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
-      __syncthreads();
-      const int cnt = (int)min((uint32_t)kBlock, r.y - base);
+      uint32_t m = 0;
+      if (k < r.y) {
+        float4 ta, tb;
+        float2 tc;
+        stage_splat(a.splats, a.colors, a.ids[k], x0, y0, ta, tb, tc);
+        sa[threadIdx.x] = ta;
+        sb[threadIdx.x] = tb;
+        m = quadrant_mask(ta, tb);
+      }
+      const int cnt = build_quad_lists(m, Q);
       if (!done) {
-        for (int e = 0; e < cnt; ++e) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
           const float4 ga = sa[e], gb = sb[e];
           float dx, dy, t;
           const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
@@ -249,6 +338,9 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
   atomicMax(&s_maxlast, last);
+  uint32_t wlast = last;  // this wave's largest last contributor
+  for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, d, 64));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);
   __syncthreads();
   const uint32_t maxlast = s_maxlast;
 
@@ -269,15 +361,24 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
   for (int end = (int)maxlast; end > 0; end -= kBlock) {
     const int beg = max(end - kBlock, 0);
     __syncthreads();
+    uint32_t m = 0;
     if (beg + (int)threadIdx.x < end) {
       const uint32_t g = a.ids[r.x + beg + threadIdx.x];
       sid[threadIdx.x] = g;
-      stage_splat(a.splats, g, x0, y0, sa[threadIdx.x], sb[threadIdx.x], sc[threadIdx.x]);
+      float4 ta, tb;
+      float2 tc;
+      stage_splat(a.splats, a.colors, g, x0, y0, ta, tb, tc);
+      sa[threadIdx.x] = ta;
+      sb[threadIdx.x] = tb;
+      sc[threadIdx.x] = tc;
+      m = quadrant_mask(ta, tb);
     }
     for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
-    __syncthreads();
-    for (int e = end - 1; e >= beg; --e) {
-      const int idx = e - beg;
+    const int cnt = build_quad_lists(m, Q);
+    for (int jj = cnt - 1; jj >= 0; --jj) {
+      const int idx = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
+      const int e = beg + idx;
+      if ((uint32_t)e >= wlast) continue;  // past every pixel of this wave
       float v[9];
       for (int k = 0; k < 9; ++k) v[k] = 0.0f;
       bool contrib = false;
@@ -334,13 +435,15 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
 }  // namespace
 
 hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
-                                const float4* splats, const BatchOut& out, float* pixel_T, uint32_t* pixel_last,
+                                const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
+                                uint32_t* pixel_last,
                                 bool save, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
   BlendArgs a;
   a.ranges = ranges;
   a.ids = ids;
   a.splats = splats;
+  a.colors = colors;
   a.pixel_T = pixel_T;
   a.pixel_last = pixel_last;
   a.save = save ? 1 : 0;
@@ -352,12 +455,14 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
 }
 
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
+                                 const float4* colors,
                                  const float* dL_dimg, const float* pixel_T, const uint32_t* pixel_last,
                                  const uint32_t* counters, float* grad2d, int64_t n, hipStream_t s) {
   BlendBwdArgs a;
   a.ranges = ranges;
   a.ids = ids;
   a.splats = splats;
+  a.colors = colors;
   a.width = v.width;
   a.height = v.height;
   a.tiles_x = v.tiles_x;

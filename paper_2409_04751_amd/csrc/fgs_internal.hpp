@@ -99,7 +99,7 @@ struct Layout {
   int64_t total_tiles = 0, total_pixels = 0;
   int64_t kcap = 0;
   size_t bytes = 0;
-  size_t splats, depth_keys, tiles, rects, radii;
+  size_t splats, colors, depth_keys, tiles, rects, radii;
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
   size_t hist, partials, block_tiles;
@@ -181,11 +181,13 @@ hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 
 hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
-                                const float4* splats, const BatchOut& out, float* pixel_T, uint32_t* pixel_last,
+                                const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
+                                uint32_t* pixel_last,
                                 bool save, hipStream_t s);
 
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids,
-                                 const float4* splats, const float* dL_dimg, const float* pixel_T,
+                                 const float4* splats, const float4* colors, const float* dL_dimg,
+                                 const float* pixel_T,
                                  const uint32_t* pixel_last, const uint32_t* counters, float* grad2d, int64_t n,
                                  hipStream_t s);
 

@@ -28,7 +28,8 @@ struct PreArgs {
   uint32_t n;
   int sh_degree;
   // outputs, entry view * n + i
-  float4* splats;
+  float4* splats;  // [entry][2]: position, conic
+  float4* colors;  // [entry]: opacity, rgb
   uint32_t* depth_keys;
   uint32_t* tiles;
   uint2* rects;
@@ -211,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
     const float o = a.opac[i];
     const double A = G.conic[0], B = G.conic[1];
     const float hx = (float)G.mu[0], hy = (float)G.mu[1];
-    a.splats[3 * e + 0] = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-    a.splats[3 * e + 1] = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A),
+    a.splats[2 * e + 0] = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+    a.splats[2 * e + 1] = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A),
                                       (float)(-0.5 * kLog2e / (G.det * A)), (float)(-log2(255.0 * (double)o)));
     a.rects[e] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
     a.radii[e] = (int32_t)rad;
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void color_kernel(PreArgs a) {
     view_dir(a.means, i, n, a.batch.v[vi].campos, dir, vd, vlen);
     sh_color<DEG>(c, dir, rgb, Y);
     if (isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2])) {
-      a.splats[3 * e + 2] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+      a.colors[e] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
     } else {
       a.tiles[e] = 0;
       a.depth_keys[e] = 0xFFFFFFFFu;
@@ -301,11 +302,9 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   if (i >= a.n) return;
   const uint32_t n = a.n;
   constexpr int nb = (DEG + 1) * (DEG + 1);
-  if (a.tiles[i] == 0) {
-    for (int k = 0; k < 3 * nb; ++k) a.g_sh[(size_t)k * n + i] = 0.0f;
-    for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = 0.0f;
-    return;
-  }
+  // one path for every lane (culled lanes compute and select zeros), so each
+  // plane is written by one full-wave store
+  const bool vis = a.tiles[i] != 0;
   const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
   float c[48];
   load_sh<DEG>(a.sh, i, n, c);
@@ -314,14 +313,14 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   view_dir(a.means, i, n, a.v.campos, dir, vd, vlen);
   sh_color<DEG>(c, dir, rgb, Y);
   float gcol[3];
-  for (int ch = 0; ch < 3; ++ch) gcol[ch] = rgb[ch] < 0.0f ? 0.0f : grgb[ch];
+  for (int ch = 0; ch < 3; ++ch) gcol[ch] = (vis && !(rgb[ch] < 0.0f)) ? grgb[ch] : 0.0f;
   float wk[16];
 #pragma unroll
   for (int k = 0; k < nb; ++k) {
     float w = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      a.g_sh[(size_t)(k * 3 + ch) * n + i] = Y[k] * gcol[ch];
+      a.g_sh[(size_t)(k * 3 + ch) * n + i] = vis ? Y[k] * gcol[ch] : 0.0f;
       w += c[k * 3 + ch] * gcol[ch];
     }
     wk[k] = w;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
     const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
     for (int e = 0; e < 3; ++e) gm[e] = ((double)gd[e] - (double)dir[e] * dd) / vlen;
   }
-  for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)gm[c];
+  for (int ch = 0; ch < 3; ++ch) a.g_means[ch * n + i] = vis ? (float)gm[ch] : 0.0f;
 }
 
 // Geometry part of the backward (Sec. 4.3): from dL/d(mu_p, conic, opacity)
@@ -444,6 +443,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* w
   a.batch = b;
   a.block_tiles = reinterpret_cast<uint32_t*>(ws + L.block_tiles);
   a.splats = reinterpret_cast<float4*>(ws + L.splats);
+  a.colors = reinterpret_cast<float4*>(ws + L.colors);
   a.depth_keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
   a.tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
   a.rects = reinterpret_cast<uint2*>(ws + L.rects);

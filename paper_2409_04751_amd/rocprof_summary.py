@@ -2,12 +2,13 @@
 
     python -m paper_2409_04751_amd.rocprof_summary stats KERNEL_STATS.csv
     python -m paper_2409_04751_amd.rocprof_summary traffic \
-        --kernel radix_scatter_kernel<1 --name tile_sort_scatter \
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
-        --copy-bytes 1073741824 --out profiles/traffic_tile_sort_scatter.json
+        --copy-bytes 1073741824 --out profiles/traffic_<workload>.json
+    python -m paper_2409_04751_amd.rocprof_summary counters C.csv --counters SQ_WAVES ...
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two
-separate `rocprofv3 --pmc` runs) into HBM bytes per launch of one kernel.
+separate `rocprofv3 --pmc` runs) into HBM bytes per launch of each library
+kernel.
 Each counter is scaled by what it reads for a plain device copy of a known
 size: the factor is (copy bytes / 1024) / counter value for the copy kernel,
 so a counter that samples only part of the memory channels, or counts in
@@ -50,27 +51,63 @@ def counter_means(path: str, kernel_substr: str, counter: str) -> tuple[float, i
     return sum(per_dispatch.values()) / len(per_dispatch), len(per_dispatch)
 
 
+# profiler kernel names of the library's kernels, as they appear (demangled)
+# in rocprofv3 output, keyed by the names the library's event profiler uses
+KERNELS = {
+    "preprocess": "::preprocess_kernel(",
+    "color": "::color_kernel<",
+    "compact": "::compact_kernel(",
+    "depth_sort_scatter": "::radix_scatter_kernel<3,",
+    "duplicate": "::duplicate_kernel(",
+    "tile_sort_hist": "::radix_hist_kernel<16>",
+    "tile_sort_scatter": "::radix_scatter_kernel<1,",
+    "ranges": "::ranges_kernel(",
+    "blend_forward": "::blend_forward_kernel(",
+    "blend_backward": "::blend_backward_kernel(",
+    "sh_backward": "::sh_backward_kernel<",
+    "preprocess_backward": "::geometry_backward_kernel(",
+}
+
+
 def traffic(args) -> dict:
+    """HBM bytes per launch of each library kernel, calibrated by the copy."""
     copy_kib = args.copy_bytes / 1024.0
     cf, _ = counter_means(args.copy_fetch, COPY_KERNEL, "FETCH_SIZE")
     cw, _ = counter_means(args.copy_write, COPY_KERNEL, "WRITE_SIZE")
     fetch_factor = copy_kib / cf
     write_factor = copy_kib / cw
-    fk, nf = counter_means(args.fetch, args.kernel, "FETCH_SIZE")
-    wk, nw = counter_means(args.write, args.kernel, "WRITE_SIZE")
-    read_b = fk * 1024.0 * fetch_factor
-    write_b = wk * 1024.0 * write_factor
-    rec = dict(kernel=args.name, kernel_match=args.kernel, dispatches=dict(fetch=nf, write=nw),
-               fetch_kib_raw=round(fk, 1), write_kib_raw=round(wk, 1),
+    kernels = {}
+    for name, sub in KERNELS.items():
+        try:
+            fk, nf = counter_means(args.fetch, sub, "FETCH_SIZE")
+            wk, nw = counter_means(args.write, sub, "WRITE_SIZE")
+        except SystemExit:
+            continue
+        read_b = fk * 1024.0 * fetch_factor
+        write_b = wk * 1024.0 * write_factor
+        kernels[name] = dict(dispatches=nf, fetch_kib_raw=round(fk, 1), write_kib_raw=round(wk, 1),
+                             read_bytes_per_launch=round(read_b), write_bytes_per_launch=round(write_b),
+                             bytes_per_launch=round(read_b + write_b))
+    rec = dict(workload=args.workload, command=args.command, source_sha=args.source_sha,
                copy_calibration=dict(bytes=args.copy_bytes, fetch_kib=round(cf, 1), write_kib=round(cw, 1),
                                      fetch_factor=round(fetch_factor, 4), write_factor=round(write_factor, 4)),
-               read_bytes_per_launch=round(read_b), write_bytes_per_launch=round(write_b),
-               bytes_per_launch=round(read_b + write_b))
-    if args.source_sha:
-        rec["source_sha"] = args.source_sha
-    if args.command:
-        rec["command"] = args.command
+               kernels=kernels)
     return rec
+
+
+def counter_table(path: str, counters: list[str]) -> dict:
+    """Mean per dispatch of each counter for each library kernel."""
+    out = {}
+    for name, sub in KERNELS.items():
+        row = {}
+        for c in counters:
+            try:
+                row[c], row["dispatches"] = counter_means(path, sub, c)
+            except SystemExit:
+                pass
+        if row:
+            out[name] = row
+    return out
 
 
 def main(argv=None) -> int:
@@ -80,12 +117,16 @@ def main(argv=None) -> int:
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=30)
     t = sub.add_parser("traffic")
-    for k in ("kernel", "name", "fetch", "write", "copy_fetch", "copy_write"):
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--workload", default="")
     t.add_argument("--source-sha", default=None)
     t.add_argument("--command", default=None)
     t.add_argument("--out", default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--counters", nargs="+", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         rows = kernel_stats(args.csv)
@@ -95,6 +136,9 @@ def main(argv=None) -> int:
             print(f"{r['name'][:70]:<70} {r['calls']:>6} {r['total_ns'] / 1e6:>10.3f} {r['avg_ns'] / 1e3:>10.2f} "
                   f"{r['pct']:>6.2f}")
         print(f"{'total':<70} {'':>6} {total / 1e6:>10.3f}")
+        return 0
+    if args.cmd == "counters":
+        print(json.dumps(counter_table(args.csv, args.counters), indent=1))
         return 0
     rec = traffic(args)
     text = json.dumps(rec, indent=1)

@@ -39,7 +39,8 @@ def read_state(ws, n, cam, K):
     lay = ws.layout(n, cam.width, cam.height)
     u32 = lambda off, cnt: ws.view(off, cnt, torch.int32).cpu().numpy().view(np.uint32)
     ntiles = lay.tiles_x * lay.tiles_y
-    splats = ws.view(lay.splats, 12 * n, torch.float32).cpu().numpy().reshape(n, 3, 4).astype(np.float64)
+    splats = ws.view(lay.splats, 8 * n, torch.float32).cpu().numpy().reshape(n, 2, 4).astype(np.float64)
+    colors = ws.view(lay.colors, 4 * n, torch.float32).cpu().numpy().reshape(n, 4).astype(np.float64)
     mu = splats[:, 0, 0:2] + splats[:, 0, 2:4]
     Ap, beta, Dp, q2min = splats[:, 1, 0], splats[:, 1, 1], splats[:, 1, 2], splats[:, 1, 3]
     A = Ap / (-0.5 * LOG2E)
@@ -49,7 +50,7 @@ def read_state(ws, n, cam, K):
     rects = u32(lay.rects, 2 * n).reshape(n, 2)
     rect = np.stack([rects[:, 0] & 0xFFFF, rects[:, 0] >> 16, rects[:, 1] & 0xFFFF, rects[:, 1] >> 16], axis=1)
     return dict(
-        mu_p=mu, conic=np.stack([A, B, C], axis=1), opacity=splats[:, 2, 0], rgb=splats[:, 2, 1:4], q2min=q2min,
+        mu_p=mu, conic=np.stack([A, B, C], axis=1), opacity=colors[:, 0], rgb=colors[:, 1:4], q2min=q2min,
         depth_bits=u32(lay.depth_keys, n), tiles=u32(lay.tiles, n), rect=rect.astype(np.int32),
         radius=ws.view(lay.radii, n, torch.int32).cpu().numpy(), depth_order=u32(lay.depth_order, n),
         tile_keys=u32(lay.tile_keys, K) if K else np.zeros(0, np.uint32),

@@ -46,7 +46,7 @@ def test_version_and_workspace_arithmetic():
     lay = L.fgs_workspace_layout(1000, 256, 256, b1)
     assert lay.k_capacity >= 10000 and lay.bytes <= b1
     assert lay.tiles_x == 16 and lay.tiles_y == 16
-    offs = [lay.splats, lay.depth_keys, lay.tiles, lay.rects, lay.radii, lay.depth_order, lay.offsets,
+    offs = [lay.splats, lay.colors, lay.depth_keys, lay.tiles, lay.rects, lay.radii, lay.depth_order, lay.offsets,
             lay.tile_keys, lay.tile_ids, lay.ranges, lay.grad2d, lay.pixel_T, lay.pixel_last, lay.counters]
     assert all(o % 256 == 0 for o in offs)
     assert len(set(offs)) == len(offs)

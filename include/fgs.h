@@ -118,7 +118,9 @@ typedef struct fgs_layout {
   size_t grad2d;       /* float [9][n]: backward scratch (dL/d mu_p xy, conic A B C, opacity, rgb) */
   size_t pixel_T;      /* float [H][W]: final transmittance (FGS_SAVE_PIXEL_STATE) */
   size_t pixel_last;   /* uint32 [H][W]: 1 + list index of the last blended Gaussian */
-  size_t counters;     /* uint32 [11]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view */
+  size_t counters;     /* uint32 [16]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view,
+                          [11] / [12] smallest / largest depth key of a visible entry,
+                          [14..15] K as a uint64 */
 } fgs_layout;
 
 /* Library version string (static storage). */

@@ -80,7 +80,9 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.block_tiles = take((size_t)ceil_div((int64_t)nn, kBlock) * nviews * 4);
   const int64_t kk = kcap > 0 ? kcap : 1;
   const int64_t nb_max = std::max(radix_blocks((int64_t)nv, 3), radix_blocks(kk, 1));
-  L.hist = take((size_t)nb_max * kRadix * 4);
+  // radix histograms; before the depth sort also the compaction's per-block
+  // stats (one uint4 per 256 entries)
+  L.hist = take(std::max((size_t)nb_max * kRadix * 4, (size_t)ceil_div((int64_t)nv, kBlock) * 16));
   const int64_t scan_items = std::max<int64_t>({(int64_t)nv, nb_max * kRadix});
   L.partials = take((size_t)(ceil_div(scan_items, kItemsPerBlock) + 1) * 4);
   L.tkeys_a = take((size_t)kk * 4);
@@ -234,43 +236,59 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint32_t* counters = U(L.counters);
   uint32_t* partials = U(L.partials);
   uint32_t* hist = U(L.hist);
-  const uint32_t* d_visible = counters + kCountVisible;
 
   HIP_TRY(launch_fill_u32(counters, 0u, kNumCounters, s), "clear counters");
   HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
   HIP_TRY(launch_preprocess(*g, b, ws, L, s), "preprocess");
   // stable compaction of the visible (view, Gaussian) entries; offsets holds
-  // their positions until the tile-count scan reuses it
+  // their positions until the tile-count scan reuses it.  The compaction
+  // also sums K and finds the depth-key range, so one read-back gives every
+  // later stage its exact size.
   HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible, U(L.offsets),
                       s),
           "visibility scan");
   HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects), U(L.offsets), nv,
-                         U(L.dkeys_a), U(L.dvals_a), U(L.drx_a), U(L.dry_a), s),
+                         U(L.dkeys_a), U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters,
+                         reinterpret_cast<uint4*>(hist), s),
           "compact");
-  // depth sort carrying (id, rect); positive float bits use 31 key bits ->
-  // 4 passes, result back in the *_a planes.  Views may interleave here: the
-  // tile sort below separates them again and keeps each view's depth order.
-  RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
-                  {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
-  HIP_TRY(launch_radix_sort(DB, d_visible, nv, 31, hist, partials, s, kKDepthHist, kKDepthScatter), "depth sort");
-  HIP_TRY(launch_scan(U(L.drx_a), U(L.dry_a), d_visible, nv, kScanRectArea, partials, counters + kCountK,
-                      U(L.offsets), s),
-          "tile count scan");
   uint32_t host_counters[kNumCounters];
-  HIP_TRY(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s), "read K");
-  HIP_TRY(hipStreamSynchronize(s), "sync for K");
-  const int64_t K = host_counters[kCountK];
-  if (k_total) *k_total = K;
+  HIP_TRY(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s), "read counts");
+  HIP_TRY(hipStreamSynchronize(s), "sync for counts");
+  const int64_t V = host_counters[kCountVisible];
+  uint64_t K64;
+  std::memcpy(&K64, &host_counters[kCountK64], sizeof(K64));
+  if (k_total) *k_total = K64 > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)K64;
   if (k_views)  // one view: its count is the total (the per-view sums run for batches only)
-    for (int v = 0; v < nviews; ++v) k_views[v] = nviews == 1 ? K : (int64_t)host_counters[kCountViewK + v];
-  if (K > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 intersections");
+    for (int v = 0; v < nviews; ++v) k_views[v] = nviews == 1 ? (int64_t)K64 : (int64_t)host_counters[kCountViewK + v];
+  if (K64 > 0x7FFFFFFFull) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 intersections");
+  const int64_t K = (int64_t)K64;
   if (K > L.kcap) {
     char msg[160];
     std::snprintf(msg, sizeof(msg), "workspace holds %lld intersections, %lld needed", (long long)L.kcap,
                   (long long)K);
     return fail(FGS_ERR_WORKSPACE, msg);
   }
-  HIP_TRY(launch_duplicate(U(L.dvals_a), U(L.drx_a), U(L.dry_a), U(L.offsets), d_visible, nv, K, b, n, L.tile_bits,
+  // depth sort of the V visible entries carrying (id, rect); digits over
+  // key - min key, so only the bits in which the visible depths differ are
+  // sorted (26 of 31 for depths 0.2-12 m: 3 passes).  Views may interleave here: the tile
+  // sort below separates them again and keeps each view's depth order.
+  const uint32_t kmin = host_counters[kCountKeyMin], kmax = host_counters[kCountKeyMax];
+  const int depth_bits = V > 1 ? bits_for((int64_t)(kmax - kmin) + 1) : 0;
+  RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
+                  {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
+  HIP_TRY(launch_radix_sort(DB, nullptr, V, depth_bits, hist, partials, s, kKDepthHist, kKDepthScatter, false, kmin),
+          "depth sort");
+  // an odd number of passes leaves the order in the *_b planes; the id plane
+  // is copied back so the layout's depth_order always holds it
+  const bool odd = radix_passes(depth_bits) % 2 == 1;
+  uint32_t* d_ids = odd ? U(L.dvals_b) : U(L.dvals_a);
+  uint32_t* d_rx = odd ? U(L.drx_b) : U(L.drx_a);
+  uint32_t* d_ry = odd ? U(L.dry_b) : U(L.dry_a);
+  if (odd && V > 0)
+    HIP_TRY(hipMemcpyAsync(U(L.dvals_a), d_ids, (size_t)V * 4, hipMemcpyDeviceToDevice, s), "depth order");
+  HIP_TRY(launch_scan(d_rx, d_ry, nullptr, V, kScanRectArea, partials, counters + kCountK, U(L.offsets), s),
+          "tile count scan");
+  HIP_TRY(launch_duplicate(d_ids, d_rx, d_ry, U(L.offsets), nullptr, V, K, b, n, L.tile_bits,
                            hist, U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};

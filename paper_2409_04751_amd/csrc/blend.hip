@@ -274,7 +274,7 @@ __device__ inline float row_reduce_scatter9(const float v[9], bool b3, bool b2, 
 __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ float4 sa[kBlock];
   __shared__ float4 sb[kBlock];
-  __shared__ float2 sc[kBlock];
+  __shared__ float4 sc[kBlock];  // g, b, and the conic's A, D in natural units
   __shared__ uint32_t sid[kBlock];
   __shared__ float acc[9][kBlock];
   __shared__ uint32_t s_maxlast;
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
       stage_splat(a.splats, a.colors, g, x0, y0, ta, tb, tc);
       sa[threadIdx.x] = ta;
       sb[threadIdx.x] = tb;
-      sc[threadIdx.x] = tc;
+      sc[threadIdx.x] = make_float4(tc.x, tc.y, kNegTwoLn2 * ta.z, kNegTwoLn2 * tb.x);
       m = quadrant_mask(ta, tb);
     }
     for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
@@ -379,47 +379,43 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
       const int idx = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
       const int e = beg + idx;
       if ((uint32_t)e >= wlast) continue;  // past every pixel of this wave
+      const float4 ga = sa[idx], gb = sb[idx];
+      float dx, dy, t;
+      const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
+      const bool pass = (uint32_t)e < last && q2 >= gb.y;
+      if (__ballot(pass) == 0ull) continue;  // wave-uniform
+      // one path for every lane: a lane the splat does not reach gets
+      // alpha = 0, which leaves Tc and the colour behind unchanged and
+      // zeroes its gradient terms, so the DPP exchange needs no branches
+      const float4 gc = sc[idx];  // g, b, A, D (natural scale)
+      const float eq = __builtin_amdgcn_exp2f(q2);
+      const float raw = gb.z * eq;
+      const float alpha = pass ? fminf(kAlphaMax, raw) : 0.0f;
+      const float om = 1.0f - alpha;
+      const float Ti = pass ? Tc * __builtin_amdgcn_rcpf(om) : Tc;
+      const float w = alpha * Ti;
       float v[9];
-      for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-      bool contrib = false;
-      if ((uint32_t)e < last) {
-        const float4 ga = sa[idx], gb = sb[idx];
-        float dx, dy, t;
-        const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
-        if (q2 >= gb.y) {
-          contrib = true;
-          const float eq = __builtin_amdgcn_exp2f(q2);
-          const float raw = gb.z * eq;
-          const float alpha = fminf(kAlphaMax, raw);
-          const float Ti = Tc * __builtin_amdgcn_rcpf(1.0f - alpha);
-          const float w = alpha * Ti;
-          const float2 gc = sc[idx];
-          v[6] = w * G0;
-          v[7] = w * G1;
-          v[8] = w * G2;
-          const float dLda = Ti * ((gb.w - B0) * G0 + (gc.x - B1) * G1 + (gc.y - B2) * G2);
-          B0 = alpha * gb.w + (1.0f - alpha) * B0;
-          B1 = alpha * gc.x + (1.0f - alpha) * B1;
-          B2 = alpha * gc.y + (1.0f - alpha) * B2;
-          Tc = Ti;
-          if (raw < kAlphaMax) {
-            const float dLdq = dLda * alpha;
-            v[5] = dLda * eq;
-            const float A = kNegTwoLn2 * ga.z, D = kNegTwoLn2 * gb.x;
-            const float At = A * t;
-            v[0] = -dLdq * At;
-            v[1] = -dLdq * (ga.w * At + D * dy);
-            v[2] = -0.5f * dLdq * dx * dx;
-            v[3] = -dLdq * dx * dy;
-            v[4] = -0.5f * dLdq * dy * dy;
-          }
-        }
-      }
-      if (__ballot(contrib) != 0ull) {
-        // wave-uniform: every lane takes part in the DPP exchanges
-        const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
-        if (rvalid) atomicAdd(&acc[rval][idx], part);
-      }
+      v[6] = w * G0;
+      v[7] = w * G1;
+      v[8] = w * G2;
+      const float dLda = Ti * ((gb.w - B0) * G0 + (gc.x - B1) * G1 + (gc.y - B2) * G2);
+      B0 = alpha * gb.w + om * B0;
+      B1 = alpha * gc.x + om * B1;
+      B2 = alpha * gc.y + om * B2;
+      Tc = Ti;
+      const bool live = pass && raw < kAlphaMax;  // the clamp passes no gradient
+      const float dLdq = live ? dLda * alpha : 0.0f;
+      v[5] = live ? dLda * eq : 0.0f;
+      const float At = gc.z * t;
+      v[0] = -dLdq * At;
+      v[1] = -dLdq * (ga.w * At + gc.w * dy);
+      const float h = -0.5f * dLdq, hdx = h * dx;
+      v[2] = hdx * dx;
+      v[3] = (hdx + hdx) * dy;
+      v[4] = (h * dy) * dy;
+      // wave-uniform: every lane takes part in the DPP exchanges
+      const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
+      if (rvalid) atomicAdd(&acc[rval][idx], part);
     }
     __syncthreads();
     if ((int)threadIdx.x < end - beg) {

@@ -86,7 +86,19 @@ class ProfScope {
 constexpr int kMaxViews = FGS_MAX_BATCH;
 
 // Counters slots in the workspace (uint32).
-enum Counter { kCountK = 0, kCountVisible = 1, kCountFlags = 2, kCountViewK = 3, kNumCounters = 3 + kMaxViews };
+// Device counters at the start of the workspace (u32 slots).  K64 is a u64
+// at slots 14-15 (8-byte aligned).
+enum Counter {
+  kCountK = 0,
+  kCountVisible = 1,
+  kCountFlags = 2,
+  kCountViewK = 3,
+  kCountKeyMin = 3 + kMaxViews,  // smallest depth key of a visible entry
+  kCountKeyMax = 4 + kMaxViews,  // largest
+  kCountK64 = 14,                // sum of the visible entries' tile counts
+  kNumCounters = 16
+};
+static_assert(kCountKeyMax < kCountK64, "counter slots overlap");
 
 // Workspace layout (host computation, shared by the API and the launchers).
 // Per-(view, Gaussian) arrays have n * nviews entries, view-major; the
@@ -155,16 +167,22 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
 // in the *_a buffers after an even number of passes, else in *_b.
 // If first_hist_ready, the digit histogram of pass 0 is already in hist
 // (digit-major, one column per radix block).
+// Digits are taken from key - key_bias (every key must be >= key_bias); the
+// keys themselves are moved unchanged.
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                             bool first_hist_ready = false);
+                             bool first_hist_ready = false, uint32_t key_bias = 0);
 int radix_passes(int bits);
 int64_t radix_blocks(int64_t max_count, int payload);
 
 // Visible Gaussians (tiles > 0) in id order: key, id and rect planes at
-// position pos[i] (exclusive scan of the visibility flags).
+// position pos[i] (exclusive scan of the visibility flags).  Also stores
+// the visible entries' total tile count in counters[kCountK64] (u64) and
+// their depth-key range in counters[kCountKeyMin / kCountKeyMax], through
+// block_stats (one uint4 per 256 entries, scratch).
 hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
-                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, hipStream_t s);
+                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters,
+                          uint4* block_stats, hipStream_t s);
 
 // One (tile, id) pair per covered tile of each depth-ordered visible
 // Gaussian (ids, rect planes rx / ry), at the exclusive-scan offsets; K

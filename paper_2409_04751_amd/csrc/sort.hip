@@ -150,8 +150,8 @@ struct ValPtrs {
 // IPT items per thread; one block covers kBlock * IPT consecutive items.
 template <int IPT>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys, const uint32_t* d_count,
-                                                            uint32_t max_count, int shift, int bits, uint32_t nblocks,
-                                                            uint32_t* hist) {
+                                                            uint32_t max_count, uint32_t key_bias, int shift, int bits,
+                                                            uint32_t nblocks, uint32_t* hist) {
   __shared__ uint32_t h[kRadix];
   const uint32_t count = item_count(d_count, max_count);
   const uint32_t radix = 1u << bits, mask = radix - 1u;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys
     key[k] = idx < count ? keys[idx] : 0xFFFFFFFFu;
   }
   for (int k = 0; k < IPT; ++k) {
-    if (base + k * kBlock + threadIdx.x < count) atomicAdd(&h[(key[k] >> shift) & mask], 1u);
+    if (base + k * kBlock + threadIdx.x < count) atomicAdd(&h[((key[k] - key_bias) >> shift) & mask], 1u);
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[d * nblocks + blockIdx.x] = h[d];
@@ -176,8 +176,8 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys
 template <int P, int IPT, int RB>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* keys_in, ValPtrs<P> vin,
                                                                uint32_t* keys_out, ValPtrs<P> vout,
-                                                               const uint32_t* d_count, uint32_t max_count, int shift,
-                                                               int bits, uint32_t nblocks,
+                                                               const uint32_t* d_count, uint32_t max_count,
+                                                               uint32_t key_bias, int shift, int bits, uint32_t nblocks,
                                                                const uint32_t* scanned_hist) {
   constexpr int kItems = kBlock * IPT;
   constexpr int kPerWave = kItems / kWaves;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
     const uint32_t idx = wave_base + it * 64 + lane;
     const bool valid = idx < count;
     const uint32_t key = my_key[it];
-    const uint32_t digit = (key >> shift) & mask;
+    const uint32_t digit = ((key - key_bias) >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const uint64_t bal = __ballot((digit >> b) & 1u);
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
   __syncthreads();
   for (int it = 0; it < kIters; ++it) {
     if (my_rank[it] == 0xFFFFFFFFu) continue;
-    const uint32_t digit = (my_key[it] >> shift) & mask;
+    const uint32_t digit = ((my_key[it] - key_bias) >> shift) & mask;
     const uint32_t pos = start[digit] + wave_count[wave][digit] + my_rank[it];
     stage_keys[pos] = my_key[it];
     for (int q = 0; q < P; ++q) stage_vals[q][pos] = my_val[it][q];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
   const uint32_t nvalid = min((uint32_t)kItems, count - block_base);
   for (uint32_t e = threadIdx.x; e < nvalid; e += kBlock) {
     const uint32_t key = stage_keys[e];
-    const uint32_t digit = (key >> shift) & mask;
+    const uint32_t digit = ((key - key_bias) >> shift) & mask;
     const uint32_t dst = start[digit] + e;
     keys_out[dst] = key;
     for (int q = 0; q < P; ++q) vout.p[q][dst] = stage_vals[q][e];
@@ -278,17 +278,87 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
 }
 
 // ---- compaction of the visible Gaussians (stable, id order) ----------------
+// Also reduces, per block, the tile counts (u64) and the depth-key range of
+// the visible entries into block_stats[b] = (sum lo, sum hi, min, max); a
+// single-block pass folds them afterwards (thousands of blocks on three
+// addresses would serialise as global atomics).
 __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* tiles, const uint32_t* depth_keys,
                                                          const uint2* rects, const uint32_t* pos, uint32_t n,
-                                                         uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry) {
+                                                         uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry,
+                                                         uint4* block_stats) {
+  __shared__ unsigned long long s_k;
+  __shared__ uint32_t s_min, s_max;
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n || tiles[i] == 0) return;
-  const uint32_t p = pos[i];
-  const uint2 r = rects[i];
-  keys[p] = depth_keys[i];
-  ids[p] = i;
-  rx[p] = r.x;
-  ry[p] = r.y;
+  if (threadIdx.x == 0) {
+    s_k = 0;
+    s_min = 0xFFFFFFFFu;
+    s_max = 0u;
+  }
+  __syncthreads();
+  const uint32_t nt = i < n ? tiles[i] : 0u;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, ksum = 0u;
+  if (nt != 0) {
+    const uint32_t p = pos[i];
+    const uint2 r = rects[i];
+    const uint32_t key = depth_keys[i];
+    keys[p] = key;
+    ids[p] = i;
+    rx[p] = r.x;
+    ry[p] = r.y;
+    kmin = kmax = key;
+    ksum = nt;
+  }
+  unsigned long long k64 = ksum;  // a u32 per entry: block sums fit 64 bits
+  for (int d = 32; d >= 1; d >>= 1) {
+    k64 += __shfl_xor(k64, d, 64);
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0 && k64 != 0) {
+    atomicAdd(&s_k, k64);
+    atomicMin(&s_min, kmin);
+    atomicMax(&s_max, kmax);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) block_stats[blockIdx.x] = make_uint4((uint32_t)s_k, (uint32_t)(s_k >> 32), s_min, s_max);
+}
+
+constexpr int kStatsThreads = 1024;
+__global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4* block_stats, uint32_t nblocks,
+                                                                     uint32_t* counters) {
+  __shared__ unsigned long long s_k;
+  __shared__ uint32_t s_min, s_max;
+  if (threadIdx.x == 0) {
+    s_k = 0;
+    s_min = 0xFFFFFFFFu;
+    s_max = 0u;
+  }
+  __syncthreads();
+  unsigned long long k64 = 0;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+  for (uint32_t b = threadIdx.x; b < nblocks; b += kStatsThreads) {
+    const uint4 st = block_stats[b];
+    k64 += (unsigned long long)st.x | ((unsigned long long)st.y << 32);
+    kmin = min(kmin, st.z);
+    kmax = max(kmax, st.w);
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    k64 += __shfl_xor(k64, d, 64);
+    kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
+    kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&s_k, k64);
+    atomicMin(&s_min, kmin);
+    atomicMax(&s_max, kmax);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counters[kCountK64] = (uint32_t)s_k;
+    counters[kCountK64 + 1] = (uint32_t)(s_k >> 32);
+    counters[kCountKeyMin] = s_min;
+    counters[kCountKeyMax] = s_max;
+  }
 }
 
 // ---- duplication: one pair per (Gaussian, covered tile) --------------------
@@ -428,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, uint32_t 
 template <int P, int IPT>
 hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                            uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                           bool first_hist_ready) {
+                           bool first_hist_ready, uint32_t key_bias) {
   const int passes = radix_passes(bits);
   const uint32_t nb = (uint32_t)ceil_div(max_count, (int64_t)kBlock * IPT);
   uint32_t* ki = B.keys_a;
@@ -445,7 +515,7 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
     if (p > 0 || !first_hist_ready) {
       ProfScope prof(s, hist_id);
       hipLaunchKernelGGL((radix_hist_kernel<IPT>), dim3(nb), dim3(kBlock), 0, s, ki, d_count, (uint32_t)max_count,
-                         shift, pb, nb, hist);
+                         key_bias, shift, pb, nb, hist);
     }
     hipError_t e = launch_scan(hist, nullptr, nullptr, (int64_t)nb << pb, kScanPlain, partials, nullptr, hist, s);
     if (e != hipSuccess) return e;
@@ -453,13 +523,13 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
       ProfScope prof(s, scatter_id);
       if (pb <= 7)
         hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 7>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
-                           (uint32_t)max_count, shift, pb, nb, hist);
+                           (uint32_t)max_count, key_bias, shift, pb, nb, hist);
       else if (pb == 8)
         hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 8>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
-                           (uint32_t)max_count, shift, pb, nb, hist);
+                           (uint32_t)max_count, key_bias, shift, pb, nb, hist);
       else
         hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, kRadixBits>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo,
-                           d_count, (uint32_t)max_count, shift, pb, nb, hist);
+                           d_count, (uint32_t)max_count, key_bias, shift, pb, nb, hist);
     }
     shift += pb;
     uint32_t* t = ki;
@@ -526,21 +596,24 @@ int64_t radix_blocks(int64_t max_count, int payload) {
 
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                             bool first_hist_ready) {
+                             bool first_hist_ready, uint32_t key_bias) {
   if (max_count <= 0 || radix_passes(bits) == 0) return hipSuccess;
   if (B.payload == 1)
     return radix_sort_impl<1, kIptPayload1>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
-                                            first_hist_ready);
+                                            first_hist_ready, key_bias);
   return radix_sort_impl<3, kIptPayload3>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
-                                          first_hist_ready);
+                                          first_hist_ready, key_bias);
 }
 
 hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
-                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, hipStream_t s) {
+                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters,
+                          uint4* block_stats, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   ProfScope prof(s, kKCompact);
-  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s, tiles, depth_keys, rects,
-                     pos, (uint32_t)n, keys, ids, rx, ry);
+  const unsigned blocks = (unsigned)ceil_div(n, kBlock);
+  hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, s, tiles, depth_keys, rects, pos, (uint32_t)n,
+                     keys, ids, rx, ry, block_stats);
+  hipLaunchKernelGGL(stats_reduce_kernel, dim3(1), dim3(kStatsThreads), 0, s, block_stats, blocks, counters);
   return hipGetLastError();
 }
 

@@ -236,10 +236,13 @@ __global__ __launch_bounds__(kBlock) void color_kernel(PreArgs a) {
   entry_of_block((uint32_t)a.batch.count, vi, i);
   const uint32_t n = a.n;
   const size_t e = (size_t)vi * n + i;
-  uint32_t ntiles = i < n ? a.tiles[e] : 0u;
+  const bool in_range = i < n;
+  uint32_t ntiles = in_range ? a.tiles[e] : 0u;
+  // the coefficients and the mean are loaded without waiting for the
+  // visibility (a wave with any visible lane fetches all of their lines)
+  float c[48];
+  if (in_range) load_sh<DEG>(a.sh, i, n, c);
   if (ntiles != 0) {
-    float c[48];
-    load_sh<DEG>(a.sh, i, n, c);
     float dir[3], Y[16], rgb[3];
     double vd[3], vlen;
     view_dir(a.means, i, n, a.batch.v[vi].campos, dir, vd, vlen);

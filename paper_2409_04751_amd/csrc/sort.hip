@@ -118,27 +118,83 @@ __global__ __launch_bounds__(kBlock) void scan_top_kernel(uint32_t* partials, ui
   if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
+// Up to this many partials, each apply block sums the partials of the blocks
+// before it itself (no separate scan of the partials); beyond it, a
+// one-block scan of the partials runs in between.
+constexpr uint32_t kMaxFusedPartials = 2048;
+
+// Items idx .. idx+15 of the scan input (idx a multiple of 16).
 template <int MODE>
+__device__ inline void load16(const ScanIn& in, uint32_t idx, uint32_t count, uint32_t vals[16]) {
+  if (idx + 16u <= count) {
+    const uint4* a4 = reinterpret_cast<const uint4*>(in.a + idx);
+    uint32_t av[16];
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = a4[q];
+      av[4 * q] = v.x;
+      av[4 * q + 1] = v.y;
+      av[4 * q + 2] = v.z;
+      av[4 * q + 3] = v.w;
+    }
+    if (MODE == kScanRectArea) {
+      const uint4* b4 = reinterpret_cast<const uint4*>(in.b + idx);
+      for (int q = 0; q < 4; ++q) {
+        const uint4 v = b4[q];
+        const uint32_t bv[4] = {v.x, v.y, v.z, v.w};
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t aa = av[4 * q + r], bb = bv[r];
+          vals[4 * q + r] = ((bb & 0xFFFFu) - (aa & 0xFFFFu)) * ((bb >> 16) - (aa >> 16));
+        }
+      }
+    } else {
+      for (int k = 0; k < 16; ++k) vals[k] = MODE == kScanFlag ? (av[k] != 0u ? 1u : 0u) : av[k];
+    }
+  } else {
+    for (int k = 0; k < 16; ++k) vals[k] = idx + k < count ? scan_value<MODE>(in, idx + k) : 0u;
+  }
+}
+
+// FUSED: partials holds the block sums and each block adds up those before
+// it; otherwise partials already holds their exclusive scan.  The last block
+// writes the grand total (FUSED only).
+template <int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(ScanIn in, uint32_t* out, const uint32_t* d_count,
-                                                            uint32_t max_count, const uint32_t* partials) {
+                                                            uint32_t max_count, const uint32_t* partials,
+                                                            uint32_t* total_out) {
+  static_assert(kItemsPerThread == 16, "load16");
   __shared__ uint32_t smem[kWaves + 1];
   const uint32_t count = item_count(d_count, max_count);
+  uint32_t block_off;
+  if (FUSED) {
+    uint32_t acc = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) acc += partials[b];
+    uint32_t tot;
+    block_exclusive_scan(acc, smem, tot);
+    block_off = tot;
+  } else {
+    block_off = partials[blockIdx.x];
+  }
   // thread t owns items base + t*16 .. +15 (blocked), so the scan is one pass
   const uint32_t base = blockIdx.x * kItemsPerBlock + threadIdx.x * kItemsPerThread;
   uint32_t vals[kItemsPerThread];
+  load16<MODE>(in, base, count, vals);
   uint32_t sum = 0;
-  for (int k = 0; k < kItemsPerThread; ++k) {
-    const uint32_t idx = base + k;
-    vals[k] = idx < count ? scan_value<MODE>(in, idx) : 0u;
-    sum += vals[k];
-  }
+  for (int k = 0; k < kItemsPerThread; ++k) sum += vals[k];
   uint32_t total;
-  uint32_t off = block_exclusive_scan(sum, smem, total) + partials[blockIdx.x];
+  uint32_t off = block_exclusive_scan(sum, smem, total) + block_off;
+  uint32_t res[kItemsPerThread];
   for (int k = 0; k < kItemsPerThread; ++k) {
-    const uint32_t idx = base + k;
-    if (idx < count) out[idx] = off;
+    res[k] = off;
     off += vals[k];
   }
+  if (base + 16u <= count) {
+    uint4* o4 = reinterpret_cast<uint4*>(out + base);
+    for (int q = 0; q < 4; ++q) o4[q] = make_uint4(res[4 * q], res[4 * q + 1], res[4 * q + 2], res[4 * q + 3]);
+  } else {
+    for (int k = 0; k < kItemsPerThread; ++k)
+      if (base + k < count) out[base + k] = res[k];
+  }
+  if (FUSED && total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = block_off + total;
 }
 
 // ---- radix sort ------------------------------------------------------------
@@ -387,6 +443,23 @@ __device__ inline void view_of(const TileMap& m, uint32_t id, uint32_t& base, ui
   tx = m.tiles_x[v];
 }
 
+// Largest j in [lo, hi) with a[j] <= x, for non-decreasing a with
+// a[lo] <= x; called by a whole wave, which probes 64 evenly spaced
+// positions per round (the probes at or below x form a prefix).
+__device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
+  const uint32_t lane = lane_id();
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63u) / 64u;
+    const uint32_t idx = lo + lane * step;
+    const uint64_t m = __ballot(idx < hi && a[idx] <= x);
+    const uint32_t nle = (uint32_t)__builtin_popcountll(m);  // >= 1: a[lo] <= x
+    const uint32_t nlo = lo + (nle - 1u) * step;
+    hi = min(hi, lo + nle * step);
+    lo = nlo;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
                                                            const uint32_t* offsets, const uint32_t* d_count,
                                                            uint32_t max_count, uint32_t K, TileMap map,
@@ -394,43 +467,50 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, 
                                                            uint32_t* out_keys, uint32_t* out_vals) {
   __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
   __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
+  __shared__ uint32_t s_off[kDupItems];  // offsets of the Gaussians that own this block's slots
   __shared__ uint32_t s_hist[kRadix];
-  __shared__ uint32_t s_first;
+  __shared__ uint32_t s_first, s_count;
   const uint32_t V = item_count(d_count, max_count);
   const uint32_t o_begin = blockIdx.x * kDupItems;
   const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
   const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
-  if (threadIdx.x == 0) {
-    // largest j with offsets[j] <= o_begin
-    uint32_t lo = 0, hi = V;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (offsets[mid] <= o_begin) lo = mid; else hi = mid;
+  if (threadIdx.x < 64) {
+    // the Gaussians owning slots [o_begin, o_end): first .. last, at most
+    // kDupItems of them (every visible Gaussian owns at least one slot)
+    const uint32_t first = wave_search_le(offsets, 0u, V, o_begin);
+    const uint32_t last = wave_search_le(offsets, first, min(V, first + (uint32_t)kDupItems), o_end - 1u);
+    if (threadIdx.x == 0) {
+      s_first = first;
+      s_count = last - first + 1u;
     }
-    s_first = lo;
   }
+  __syncthreads();
+  const uint32_t first = s_first, m = s_count;
+  for (uint32_t t = threadIdx.x; t < m; t += kBlock) s_off[t] = offsets[first + t];
   __syncthreads();
   uint32_t o = o_begin + threadIdx.x * kIptPayload1;
   if (o < o_end) {
-    // this thread's Gaussian: at most kDupItems Gaussians past the block's first
-    uint32_t lo = s_first, hi = min(V, s_first + (uint32_t)kDupItems + 1u);
+    // this thread's first Gaussian: largest local index with s_off <= o
+    uint32_t lo = 0, hi = m;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (offsets[mid] <= o) lo = mid; else hi = mid;
+      if (s_off[mid] <= o) lo = mid; else hi = mid;
     }
-    uint32_t j = lo;
-    uint32_t next = j + 1 < V ? offsets[j + 1] : K;
+    uint32_t local = lo;
+    uint32_t j = first + local;
+    uint32_t next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
     uint32_t a = rx[j], b = ry[j], g = ids[j];
     uint32_t x0 = a & 0xFFFFu, y0 = a >> 16, w = (b & 0xFFFFu) - x0;
     uint32_t tbase, tiles_x;
     view_of(map, g, tbase, tiles_x);
-    const uint32_t local = o - offsets[j];
-    uint32_t row = local / w, col = local - row * w;
+    const uint32_t lcl = o - s_off[local];
+    uint32_t row = lcl / w, col = lcl - row * w;
     for (int k = 0; k < kIptPayload1 && o < o_end; ++k, ++o) {
       if (o == next) {
+        ++local;
         ++j;
-        next = j + 1 < V ? offsets[j + 1] : K;
+        next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
         a = rx[j];
         b = ry[j];
         g = ids[j];
@@ -571,20 +651,21 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
       hipLaunchKernelGGL(scan_partials_kernel<kScanPlain>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
                          (uint32_t)max_count, partials);
   }
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBlock), 0, s, partials, nb, total);
+  const bool fused = nb <= kMaxFusedPartials;
+  if (!fused) hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBlock), 0, s, partials, nb, total);
+#define FGS_APPLY(M)                                                                                            \
+  if (fused)                                                                                                     \
+    hipLaunchKernelGGL((scan_apply_kernel<M, true>), dim3(nb), dim3(kBlock), 0, s, in, out, d_count,            \
+                       (uint32_t)max_count, partials, total);                                                    \
+  else                                                                                                           \
+    hipLaunchKernelGGL((scan_apply_kernel<M, false>), dim3(nb), dim3(kBlock), 0, s, in, out, d_count,           \
+                       (uint32_t)max_count, partials, total);
   switch (mode) {
-    case kScanFlag:
-      hipLaunchKernelGGL(scan_apply_kernel<kScanFlag>, dim3(nb), dim3(kBlock), 0, s, in, out, d_count,
-                         (uint32_t)max_count, partials);
-      break;
-    case kScanRectArea:
-      hipLaunchKernelGGL(scan_apply_kernel<kScanRectArea>, dim3(nb), dim3(kBlock), 0, s, in, out, d_count,
-                         (uint32_t)max_count, partials);
-      break;
-    default:
-      hipLaunchKernelGGL(scan_apply_kernel<kScanPlain>, dim3(nb), dim3(kBlock), 0, s, in, out, d_count,
-                         (uint32_t)max_count, partials);
+    case kScanFlag: FGS_APPLY(kScanFlag) break;
+    case kScanRectArea: FGS_APPLY(kScanRectArea) break;
+    default: FGS_APPLY(kScanPlain) break;
   }
+#undef FGS_APPLY
   return hipGetLastError();
 }
 

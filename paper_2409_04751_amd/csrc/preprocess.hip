@@ -179,7 +179,9 @@ __global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block
 // from HBM once per batch and from that XCD's L2 for the other views, while
 // each thread stays as lean as a single-view one.
 __device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i) {
-  const uint32_t logical = xcd_chunk(blockIdx.x, gridDim.x);
+  // one view: plain order, so that all XCDs stream neighbouring lines of each
+  // plane (eight separate streams per plane lose DRAM row locality)
+  const uint32_t logical = nviews > 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
   vi = logical % nviews;
   i = (logical / nviews) * kBlock + threadIdx.x;
 }

@@ -132,6 +132,68 @@ def serving_bench(params, deg, rates, count):
     return out
 
 
+def serving_train_bench(n: int, rate: float, count: int, train_seconds: float):
+    """Serving while training (resident n-Gaussian SH-3 room scene, Adam):
+    mixed-resolution Poisson requests at `rate` served batched, with fwd+bwd
+    training views of 1752x1168 at 180 deg (4 per step, random poses) in the
+    gaps; beside it, the same trace served without training and training
+    alone for `train_seconds`."""
+    import numpy as np
+    import torch
+
+    from paper_2409_04751_amd import render as R
+    from paper_2409_04751_amd import server as S
+    from paper_2409_04751_amd import synth
+
+    dev = torch.device("cuda", 0)
+    scene = synth.room_scene(n, 5, 0.01, 3)
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    leaves = [f(a).requires_grad_(True) for a in (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
+    opt = torch.optim.Adam(leaves, lr=1e-4)
+    cam = synth.fisheye_camera(1752, 1168, 180.0)
+    poses = synth.random_poses(64, 7, tuple(x + 1.0 for x in synth.ROOM_LO), tuple(x - 1.0 for x in synth.ROOM_HI))
+    targets = [f(synth.target_image(cam.width, cam.height, 100 + k)) for k in range(4)]
+    ws = R.Workspace(dev)
+
+    def train_view(k):
+        img = R.rasterize(*leaves, 3, poses[k % len(poses)], cam, (0.0, 0.0, 0.0), ws)
+        loss = (img - targets[k % 4]).abs().mean()
+        loss.backward()
+
+    def optimizer_step():
+        opt.step()
+        opt.zero_grad(set_to_none=False)
+
+    srv = S.RenderServer(*[x.detach() for x in leaves], 3, workspace_bytes=16 << 30)
+    warm = S.poisson_trace(rate, 16, seed=98)
+    srv.serve(warm, "batched")
+    for k in range(4):
+        train_view(k)
+    optimizer_step()
+    torch.cuda.synchronize()
+    trace = S.poisson_trace(rate, count, seed=11)
+    srv.batches = srv.splits = 0
+    alone = srv.serve(trace, "batched")
+    srv.batches = srv.splits = 0
+    mixed = srv.serve_with_training(trace, train_view, optimizer_step, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < train_seconds:
+        for k in range(4):
+            train_view(k)
+        optimizer_step()
+        torch.cuda.synchronize()
+        steps += 1
+    train_only = steps / (time.perf_counter() - t0)
+    r = lambda d: {k: round(v, 3) if isinstance(v, float) else v for k, v in d.items()}
+    log(f"serve+train: p99 {mixed['p99_ms']:.2f} ms (serve only {alone['p99_ms']:.2f}), "
+        f"{mixed['train_steps_per_s']:.1f} train steps/s (train only {train_only:.1f})")
+    return dict(scene=f"room {n} Gaussians, SH3, resident, Adam lr 1e-4", rate=rate, requests=count,
+                train_view="1752x1168 fisheye 180 deg, 4 views per step", serve_only=r(alone), serve_and_train=r(mixed),
+                train_only_steps_per_s=round(train_only, 3))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,9 +203,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 2000.0],
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0],
                     help="Poisson arrival rates (requests/s) for the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=300, help="requests per rate")
+    ap.add_argument("--serve-train", action="store_true",
+                    help="also measure serving while training a 6M-Gaussian scene")
+    ap.add_argument("--serve-train-n", type=int, default=6_000_000)
+    ap.add_argument("--serve-train-rate", type=float, default=200.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (rocprofv3 counter calibration) and exit")
     ap.add_argument("--source-sha", action="store_true", help="print the hash of the kernel sources and exit")
@@ -256,6 +322,10 @@ def main() -> int:
     if not args.no_serve:
         serving = serving_bench([x.detach() for x in leaves], deg, args.serve_rates, args.serve_requests)
 
+    serve_train = None
+    if args.serve_train:
+        serve_train = serving_train_bench(args.serve_train_n, args.serve_train_rate, args.serve_requests, 3.0)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
@@ -270,7 +340,8 @@ def main() -> int:
                            height=cam.height, fov_deg=180.0, views_per_step=1, visible=V, intersections=K,
                            geometry_dtype="f64"),
                roofline=roofline, cpu_baseline=cpu, kernels=kernels,
-               ms_per_step_event_profiled=round(ms_profiled, 4) if ms_profiled else None, serving=serving)
+               ms_per_step_event_profiled=round(ms_profiled, 4) if ms_profiled else None, serving=serving,
+               serving_with_training=serve_train)
     print(json.dumps(out), flush=True)
     return 0
 

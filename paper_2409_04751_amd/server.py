@@ -12,6 +12,10 @@ batch does not fit, it is split and the rest deferred.
 `serve()` replays an open-loop arrival trace on the wall clock and reports
 per-request latency (completion - arrival), p50 / p99 and views/s, for the
 batched server or for serial one-request-at-a-time rendering.
+`serve_with_training()` does the same while training the resident scene in
+the gaps: whenever no request is queued, one training view (forward +
+backward) runs, and every few views an optimizer step ends a training step;
+it reports the served latency together with training steps/s.
 """
 from __future__ import annotations
 
@@ -136,6 +140,47 @@ class RenderServer:
         return img
 
     # -- open-loop replay ----------------------------------------------------
+    def serve_with_training(self, trace: list[Request], train_view, optimizer_step, views_per_step: int = 4) -> dict:
+        """Batched serving of `trace` with training in the gaps.  Requests
+        have priority; when the queue is empty, `train_view(k)` runs the k-th
+        training view (forward + backward) and after every `views_per_step`
+        views `optimizer_step()` updates the parameters in place (the server
+        renders the same tensors, so requests see the scene as trained so far)."""
+        pending: collections.deque = collections.deque()
+        lat = np.zeros(len(trace))
+        nxt = done = views = steps = 0
+        stream = torch.cuda.current_stream(self.device)
+        t0 = time.perf_counter()
+        while done < len(trace):
+            now = time.perf_counter() - t0
+            while nxt < len(trace) and trace[nxt].arrival <= now:
+                pending.append(trace[nxt])
+                nxt += 1
+            if not pending:
+                train_view(views)
+                views += 1
+                if views % views_per_step == 0:
+                    optimizer_step()
+                    steps += 1
+                stream.synchronize()
+                continue
+            batch = self.admit(pending)
+            imgs, deferred = self.render_batch(batch)
+            for r in reversed(deferred):
+                pending.appendleft(r)
+            batch = batch[:len(imgs)]
+            stream.synchronize()
+            t_done = time.perf_counter() - t0
+            for r in batch:
+                lat[r.rid] = t_done - r.arrival
+            done += len(batch)
+        span = time.perf_counter() - t0
+        return dict(mode="batched+training", requests=len(trace), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                    p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                    views_per_s=len(trace) / span, span_s=span, offered_rate=len(trace) / trace[-1].arrival,
+                    train_views=views, train_steps=steps, train_steps_per_s=steps / span, batches=self.batches,
+                    splits=self.splits)
+
     def serve(self, trace: list[Request], mode: str = "batched", keep_images: bool = False) -> dict:
         assert mode in ("batched", "serial")
         pending: collections.deque = collections.deque()

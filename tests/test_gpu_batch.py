@@ -124,3 +124,29 @@ def test_server_splits_a_batch_that_overflows():
     for r in trace:
         assert small.k_seen[r.rid] == serial.k_seen[r.rid]
         assert torch.equal(got[r.rid], ref[r.rid]), r.rid
+
+
+def test_batch_of_large_views_equals_single_views():
+    """Three views of the 3M-Gaussian room: 9M (view, Gaussian) entries, so
+    the visibility scan takes its unfused path (more than 2048 partial sums)
+    and the tile ids of the batch need 15+ bits."""
+    scene = synth.room_scene(3_000_000, 0, 0.01, 3)
+    gs = to_gpu(scene)
+    trace = S.poisson_trace(1000.0, 3, seed=21, resolutions=((512, 512), (1024, 1024), (1752, 1168)),
+                            fov_range=(150.0, 200.0))
+    views = [(r.pose, r.cam, (0.0, 0.1, 0.2)) for r in trace]
+    g = R.gaussians_struct(*_params(gs))
+    cams = [R.camera_struct(c) for _, c, _ in views]
+    outs = [torch.empty((3, c.height, c.width), device="cuda") for _, c, _ in views]
+    refs = [gpu_forward(gs, p, c, b) for p, c, b in views]
+    ws = R.Workspace()
+    ws.ensure(L.fgs_batch_workspace_bytes(g.n, cams, sum(k for _, _, k in refs) + 4096))
+    rc, kv, kt = L.fgs_render_forward_batch(g, [R.pose_struct(p) for p, _, _ in views], cams, [b for _, _, b in views],
+                                            ws.ptr, ws.nbytes, [o.data_ptr() for o in outs],
+                                            R._stream_handle(outs[0].device))
+    L.check(rc)
+    torch.cuda.synchronize()
+    assert kt == sum(kv)
+    for (img, _, K), out, k in zip(refs, outs, kv):
+        assert K == k
+        assert torch.equal(out, img)

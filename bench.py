@@ -206,8 +206,8 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0],
                     help="Poisson arrival rates (requests/s) for the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=300, help="requests per rate")
-    ap.add_argument("--serve-train", action="store_true",
-                    help="also measure serving while training a 6M-Gaussian scene")
+    ap.add_argument("--no-serve-train", action="store_true",
+                    help="skip the measurement of serving while training a 6M-Gaussian scene")
     ap.add_argument("--serve-train-n", type=int, default=6_000_000)
     ap.add_argument("--serve-train-rate", type=float, default=200.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -323,7 +323,7 @@ def main() -> int:
         serving = serving_bench([x.detach() for x in leaves], deg, args.serve_rates, args.serve_requests)
 
     serve_train = None
-    if args.serve_train:
+    if not args.no_serve and not args.no_serve_train:
         serve_train = serving_train_bench(args.serve_train_n, args.serve_train_rate, args.serve_requests, 3.0)
 
     cpu = None

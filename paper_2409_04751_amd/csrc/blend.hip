@@ -71,33 +71,58 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
   return __builtin_fmaf(a.z * t, t, (b.x * dy) * dy);
 }
 
-// Quadrants of the tile (wave w owns the 8x8 pixel block (w & 1, w >> 1))
-// that can hold a pixel at which the splat is not skipped.  Such a pixel has
+// Which parts of a tile can hold a pixel at which the splat is not skipped
+// (the forward's waves own 8x8 quadrants, the backward's 16x8 halves).  Such
+// a pixel has
 // |A'| t^2 + |D'| dy^2 <= P = -q2min with t = dx + beta dy: an ellipse with
 // half extents ry = sqrt(P / |D'|) in y and rx = sqrt(P (1/|A'| + beta^2/|D'|))
 // in x.  The box is widened by 1% + 1/16 px, so the float evaluation of the
 // per-pixel test cannot pass outside it; a non-finite extent, or P so small
-// that the per-pixel terms could underflow, keeps every quadrant, and P < 0
+// that the per-pixel terms could underflow, keeps every pixel, and P < 0
 // (opacity below 1/255) keeps none, as the per-pixel test would.  Lists of
-// the entries per quadrant let each wave skip splats that cannot reach its
-// 64 pixels; the tile lists themselves are unchanged.
-__device__ inline uint32_t quadrant_mask(const float4& a, const float4& b) {
+// the entries per part let each wave skip splats that cannot reach its
+// pixels; the tile lists themselves are unchanged.
+//
+// splat_box gives the half extents (rx, ry) of that box and returns 0 if no
+// pixel can pass, 1 for a box, 2 if every pixel must be kept.
+__device__ inline int splat_box(const float4& a, const float4& b, float& rx, float& ry) {
   const float P = -b.y;
-  if (!(P > 1e-6f)) return P >= 0.0f ? 0xFu : 0u;
+  if (!(P > 1e-6f)) return P >= 0.0f ? 2 : 0;
   // t = dx + beta dy loses ~1e-7 (1 + |beta|) px to rounding: past |beta| =
   // 1e3 that could approach the margin, so such slivers keep every quadrant
-  if (!(fabsf(a.w) <= 1e3f)) return 0xFu;
+  if (!(fabsf(a.w) <= 1e3f)) return 2;
   const float iA = 1.0f / fabsf(a.z), iD = 1.0f / fabsf(b.x);
   constexpr float kBig = 1e30f;
-  float ry = sqrtf(P * iD), rx = sqrtf(P * __builtin_fmaf(a.w * a.w, iD, iA));
+  ry = sqrtf(P * iD);
+  rx = sqrtf(P * __builtin_fmaf(a.w * a.w, iD, iA));
   ry = ry <= kBig ? __builtin_fmaf(ry, 1.01f, 0.0625f) : kBig;
   rx = rx <= kBig ? __builtin_fmaf(rx, 1.01f, 0.0625f) : kBig;
+  return 1;
+}
+
+// Bit q + 2 r set if the box meets pixels [8q, 8q+7] x [8r, 8r+7] of the tile.
+__device__ inline uint32_t quadrant_mask(const float4& a, const float4& b) {
+  float rx, ry;
+  const int k = splat_box(a, b, rx, ry);
+  if (k != 1) return k == 2 ? 0xFu : 0u;
   uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float qx0 = (float)((q & 1) * 8), qy0 = (float)((q >> 1) * 8);
     if (a.x + rx >= qx0 && a.x - rx <= qx0 + 7.0f && a.y + ry >= qy0 && a.y - ry <= qy0 + 7.0f) m |= 1u << q;
   }
+  return m;
+}
+
+// Bit h set if the box meets pixel rows [8h, 8h+7] of the tile.
+__device__ inline uint32_t half_mask(const float4& a, const float4& b) {
+  float rx, ry;
+  const int k = splat_box(a, b, rx, ry);
+  if (k != 1) return k == 2 ? 0x3u : 0u;
+  if (!(a.x + rx >= 0.0f && a.x - rx <= 15.0f)) return 0u;
+  uint32_t m = 0;
+  if (a.y + ry >= 0.0f && a.y - ry <= 7.0f) m |= 1u;
+  if (a.y + ry >= 8.0f && a.y - ry <= 15.0f) m |= 2u;
   return m;
 }
 
@@ -271,40 +296,131 @@ __device__ inline float row_reduce_scatter9(const float v[9], bool b3, bool b2, 
   return keep + dpp<kDppQuadXor1>(send);
 }
 
-__global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) {
-  __shared__ float4 sa[kBlock];
-  __shared__ float4 sb[kBlock];
-  __shared__ float4 sc[kBlock];  // g, b, and the conic's A, D in natural units
-  __shared__ uint32_t sid[kBlock];
-  __shared__ float acc[9][kBlock];
+// The backward runs two waves per tile, and each lane owns two pixels of its
+// wave's 16x8 half: (l & 15, 8w + (l >> 4)) and the pixel 4 rows below.  Every
+// LDS read of a staged splat and every DPP reduction then serves two pixels
+// (the reverse sweep is bound by LDS bandwidth and VALU issue together).
+constexpr int kBwdThreads = 128;
+constexpr int kBwdChunk = kBwdThreads;
+
+struct HalfLists {
+  uint8_t idx[2][kBwdChunk];
+  uint32_t wcount[2][2];  // [staging wave][half]
+};
+
+// As build_quad_lists, for the two halves and two waves of a backward block.
+__device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t bal0 = __ballot(m & 1u), bal1 = __ballot((m >> 1) & 1u);
+  if (lane == 0) {
+    Q.wcount[wave][0] = (uint32_t)__builtin_popcountll(bal0);
+    Q.wcount[wave][1] = (uint32_t)__builtin_popcountll(bal1);
+  }
+  __syncthreads();
+  if (m & 1u) Q.idx[0][(wave ? Q.wcount[0][0] : 0u) + lanes_below(bal0)] = (uint8_t)threadIdx.x;
+  if (m & 2u) Q.idx[1][(wave ? Q.wcount[0][1] : 0u) + lanes_below(bal1)] = (uint8_t)threadIdx.x;
+  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave]);
+  __syncthreads();
+  return n;
+}
+
+// State of one pixel in the backward.
+struct BwdPixel {
+  float fi, fj;        // tile-relative position
+  bool inside;
+  size_t p;            // index in the image
+  float T;             // final transmittance, then transmittance in front of the current splat
+  uint32_t last;       // 1 + list index of its last blended splat
+  float G0, G1, G2;    // dL/dC
+  float B0, B1, B2;    // colour behind the current splat
+};
+
+// Front-to-back step of the re-sweep, with the forward's arithmetic.
+__device__ inline void resweep_step(BwdPixel& px, bool& done, const float4& ga, const float4& gb, uint32_t index) {
+  float dx, dy, t;
+  const float q2 = exponent2(ga, gb, px.fi, px.fj, dx, dy, t);
+  if (done || !(q2 >= gb.y)) return;
+  const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
+  const float tn = px.T * (1.0f - alpha);
+  if (tn < kTmin) {
+    done = true;
+    return;
+  }
+  px.T = tn;
+  px.last = index + 1u;
+}
+
+// Reverse step for one pixel, adding its 9 gradient terms to v.  One path
+// for every lane: a pixel the splat does not reach takes alpha = 0, which
+// leaves its transmittance and colour-behind exactly unchanged and adds
+// zeros, so the DPP exchange needs no branches.
+__device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx, float dy, float t, const float4& ga,
+                                    const float4& gb, const float2& gc, float v[9]) {
+  const float eq = __builtin_amdgcn_exp2f(q2);
+  const float raw = gb.z * eq;
+  const float alpha = pass ? fminf(kAlphaMax, raw) : 0.0f;
+  const float om = 1.0f - alpha;
+  const float Ti = pass ? px.T * __builtin_amdgcn_rcpf(om) : px.T;
+  const float w = alpha * Ti;
+  v[6] += w * px.G0;
+  v[7] += w * px.G1;
+  v[8] += w * px.G2;
+  const float dLda = Ti * ((gb.w - px.B0) * px.G0 + (gc.x - px.B1) * px.G1 + (gc.y - px.B2) * px.G2);
+  px.B0 = alpha * gb.w + om * px.B0;
+  px.B1 = alpha * gc.x + om * px.B1;
+  px.B2 = alpha * gc.y + om * px.B2;
+  px.T = Ti;
+  const bool live = pass && raw < kAlphaMax;  // the clamp passes no gradient
+  const float dLdq = live ? dLda * alpha : 0.0f;
+  v[5] += live ? dLda * eq : 0.0f;
+  const float A = kNegTwoLn2 * ga.z, D = kNegTwoLn2 * gb.x;  // natural-scale conic terms
+  const float At = A * t;
+  v[0] += -dLdq * At;
+  v[1] += -dLdq * (ga.w * At + D * dy);
+  const float h = -0.5f * dLdq, hdx = h * dx;
+  v[2] += hdx * dx;
+  v[3] += (hdx + hdx) * dy;
+  v[4] += (h * dy) * dy;
+}
+
+__global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArgs a) {
+  __shared__ float4 sa[kBwdChunk];
+  __shared__ float4 sb[kBwdChunk];
+  __shared__ float2 sc[kBwdChunk];
+  __shared__ uint32_t sid[kBwdChunk];
+  __shared__ float acc[9][kBwdChunk];
   __shared__ uint32_t s_maxlast;
-  __shared__ QuadLists Q;
-  const uint32_t wave = threadIdx.x >> 6;
+  __shared__ HalfLists Q;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const int tile = (int)xcd_chunk(blockIdx.x, gridDim.x);
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  int i, j;
-  pixel_of_thread(i, j);
-  const int px = tx * kTile + i, py = ty * kTile + j;
-  const bool inside = px < a.width && py < a.height;
-  const float fi = (float)i, fj = (float)j;
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 r = a.ranges[tile];
-  const size_t hw = (size_t)a.width * a.height, p = (size_t)py * a.width + px;
+  const size_t hw = (size_t)a.width * a.height;
   const bool saved = (a.counters[kCountFlags] & FGS_SAVE_PIXEL_STATE) != 0;
+  BwdPixel P[2];
+  for (int q = 0; q < 2; ++q) {
+    const int i = (int)(lane & 15u), j = (int)(8u * wave + (lane >> 4) + 4u * q);
+    const int px = tx * kTile + i, py = ty * kTile + j;
+    P[q].fi = (float)i;
+    P[q].fj = (float)j;
+    P[q].inside = px < a.width && py < a.height;
+    P[q].p = (size_t)py * a.width + px;
+    P[q].T = 1.0f;
+    P[q].last = 0;
+  }
 
   // ---- final transmittance and last contributor of each pixel ----
-  float T = 1.0f;
-  uint32_t last = 0;
   if (saved) {
-    if (inside) {
-      T = a.pixel_T[p];
-      last = a.pixel_last[p];
-    }
+    for (int q = 0; q < 2; ++q)
+      if (P[q].inside) {
+        P[q].T = a.pixel_T[P[q].p];
+        P[q].last = a.pixel_last[P[q].p];
+      }
   } else {
-    // front-to-back re-sweep with the forward's arithmetic (no colour)
-    bool done = !inside;
-    for (uint32_t base = r.x; base < r.y; base += kBlock) {
-      if (__syncthreads_count(!done) == 0) break;
+    bool done0 = !P[0].inside, done1 = !P[1].inside;
+    for (uint32_t base = r.x; base < r.y; base += kBwdChunk) {
+      if (__syncthreads_count(!(done0 && done1)) == 0) break;
       const uint32_t k = base + threadIdx.x;
       uint32_t m = 0;
       if (k < r.y) {
@@ -313,53 +429,49 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
         stage_splat(a.splats, a.colors, a.ids[k], x0, y0, ta, tb, tc);
         sa[threadIdx.x] = ta;
         sb[threadIdx.x] = tb;
-        m = quadrant_mask(ta, tb);
+        m = half_mask(ta, tb);
       }
-      const int cnt = build_quad_lists(m, Q);
-      if (!done) {
+      const int cnt = build_half_lists(m, Q);
+      if (!(done0 && done1)) {
         for (int jj = 0; jj < cnt; ++jj) {
           const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
           const float4 ga = sa[e], gb = sb[e];
-          float dx, dy, t;
-          const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
-          if (!(q2 >= gb.y)) continue;
-          const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
-          const float tn = T * (1.0f - alpha);
-          if (tn < kTmin) {
-            done = true;
-            break;
-          }
-          T = tn;
-          last = base - r.x + (uint32_t)e + 1u;
+          const uint32_t index = base - r.x + (uint32_t)e;
+          resweep_step(P[0], done0, ga, gb, index);
+          resweep_step(P[1], done1, ga, gb, index);
+          if (done0 && done1) break;
         }
       }
     }
   }
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
-  atomicMax(&s_maxlast, last);
-  uint32_t wlast = last;  // this wave's largest last contributor
+  uint32_t wlast = max(P[0].last, P[1].last);  // this wave's largest last contributor
   for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, d, 64));
   wlast = __builtin_amdgcn_readfirstlane(wlast);
+  if (lane == 0) atomicMax(&s_maxlast, wlast);
   __syncthreads();
   const uint32_t maxlast = s_maxlast;
 
   // ---- reverse sweep ----
-  float G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
-  if (inside) {
-    G0 = a.dL[p];
-    G1 = a.dL[hw + p];
-    G2 = a.dL[2 * hw + p];
+  for (int q = 0; q < 2; ++q) {
+    P[q].G0 = P[q].G1 = P[q].G2 = 0.0f;
+    if (P[q].inside) {
+      P[q].G0 = a.dL[P[q].p];
+      P[q].G1 = a.dL[hw + P[q].p];
+      P[q].G2 = a.dL[2 * hw + P[q].p];
+    }
+    P[q].B0 = a.bg[0];
+    P[q].B1 = a.bg[1];
+    P[q].B2 = a.bg[2];
   }
-  float B0 = a.bg[0], B1 = a.bg[1], B2 = a.bg[2];  // colour behind the current Gaussian
-  float Tc = T;
   // this lane's slot in the row reduce-scatter
   const uint32_t rpos = threadIdx.x & 15u;
   const bool rb3 = (rpos >> 3) & 1u, rb2 = (rpos >> 2) & 1u, rb1 = (rpos >> 1) & 1u, rb0 = rpos & 1u;
   const int rval = (rb3 ? 5 : 0) + (rb2 ? 3 : 0) + (rb1 ? 2 : 0) + (rb0 ? 1 : 0);
   const bool rvalid = (kRowValid >> rpos) & 1u;
-  for (int end = (int)maxlast; end > 0; end -= kBlock) {
-    const int beg = max(end - kBlock, 0);
+  for (int end = (int)maxlast; end > 0; end -= kBwdChunk) {
+    const int beg = max(end - kBwdChunk, 0);
     __syncthreads();
     uint32_t m = 0;
     if (beg + (int)threadIdx.x < end) {
@@ -370,49 +482,27 @@ __global__ __launch_bounds__(kBlock) void blend_backward_kernel(BlendBwdArgs a) 
       stage_splat(a.splats, a.colors, g, x0, y0, ta, tb, tc);
       sa[threadIdx.x] = ta;
       sb[threadIdx.x] = tb;
-      sc[threadIdx.x] = make_float4(tc.x, tc.y, kNegTwoLn2 * ta.z, kNegTwoLn2 * tb.x);
-      m = quadrant_mask(ta, tb);
+      sc[threadIdx.x] = tc;
+      m = half_mask(ta, tb);
     }
     for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
-    const int cnt = build_quad_lists(m, Q);
+    const int cnt = build_half_lists(m, Q);
     for (int jj = cnt - 1; jj >= 0; --jj) {
       const int idx = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
-      const int e = beg + idx;
-      if ((uint32_t)e >= wlast) continue;  // past every pixel of this wave
+      const uint32_t e = (uint32_t)(beg + idx);
+      if (e >= wlast) continue;  // past every pixel of this wave
       const float4 ga = sa[idx], gb = sb[idx];
-      float dx, dy, t;
-      const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
-      const bool pass = (uint32_t)e < last && q2 >= gb.y;
-      if (__ballot(pass) == 0ull) continue;  // wave-uniform
-      // one path for every lane: a lane the splat does not reach gets
-      // alpha = 0, which leaves Tc and the colour behind unchanged and
-      // zeroes its gradient terms, so the DPP exchange needs no branches
-      const float4 gc = sc[idx];  // g, b, A, D (natural scale)
-      const float eq = __builtin_amdgcn_exp2f(q2);
-      const float raw = gb.z * eq;
-      const float alpha = pass ? fminf(kAlphaMax, raw) : 0.0f;
-      const float om = 1.0f - alpha;
-      const float Ti = pass ? Tc * __builtin_amdgcn_rcpf(om) : Tc;
-      const float w = alpha * Ti;
+      float dx0, dy0, t0, dx1, dy1, t1;
+      const float q20 = exponent2(ga, gb, P[0].fi, P[0].fj, dx0, dy0, t0);
+      const float q21 = exponent2(ga, gb, P[1].fi, P[1].fj, dx1, dy1, t1);
+      const bool pass0 = e < P[0].last && q20 >= gb.y;
+      const bool pass1 = e < P[1].last && q21 >= gb.y;
+      if (__ballot(pass0 || pass1) == 0ull) continue;  // wave-uniform
+      const float2 gc = sc[idx];
       float v[9];
-      v[6] = w * G0;
-      v[7] = w * G1;
-      v[8] = w * G2;
-      const float dLda = Ti * ((gb.w - B0) * G0 + (gc.x - B1) * G1 + (gc.y - B2) * G2);
-      B0 = alpha * gb.w + om * B0;
-      B1 = alpha * gc.x + om * B1;
-      B2 = alpha * gc.y + om * B2;
-      Tc = Ti;
-      const bool live = pass && raw < kAlphaMax;  // the clamp passes no gradient
-      const float dLdq = live ? dLda * alpha : 0.0f;
-      v[5] = live ? dLda * eq : 0.0f;
-      const float At = gc.z * t;
-      v[0] = -dLdq * At;
-      v[1] = -dLdq * (ga.w * At + gc.w * dy);
-      const float h = -0.5f * dLdq, hdx = h * dx;
-      v[2] = hdx * dx;
-      v[3] = (hdx + hdx) * dy;
-      v[4] = (h * dy) * dy;
+      for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+      reverse_step(P[0], pass0, q20, dx0, dy0, t0, ga, gb, gc, v);
+      reverse_step(P[1], pass1, q21, dx1, dy1, t1, ga, gb, gc, v);
       // wave-uniform: every lane takes part in the DPP exchanges
       const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
       if (rvalid) atomicAdd(&acc[rval][idx], part);
@@ -471,7 +561,7 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.n = (uint32_t)n;
   const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
   ProfScope prof(s, kKBlendBackward);
-  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kBwdThreads), 0, s, a);
   return hipGetLastError();
 }
 

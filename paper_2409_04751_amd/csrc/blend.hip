@@ -1,11 +1,11 @@
 // Front-to-back alpha blending of each 16x16 tile (Eq. 3) and its reverse-
 // order backward.
 //
-// One block of 256 threads per tile, one thread per pixel.  The four wave64s
-// of a block each own an 8x8 quadrant, so a small splat touches few waves and
-// the backward can skip whole waves.  The tile's sorted list is consumed in
-// batches of 256 Gaussians whose 2D records are staged in LDS once and then
-// read by all 256 pixels (broadcast reads, no bank conflicts).
+// One block of 128 threads per tile: two wave64s, each owning a 16x8 half,
+// two pixels per lane.  The tile's sorted list is consumed in batches of 128
+// Gaussians whose 2D records are staged in LDS once and then read by all
+// pixels (broadcast reads, no bank conflicts); per batch each half gets the
+// list of splats that can reach it, so a wave skips the others.
 //
 // Per (pixel, Gaussian) the exponent is evaluated as
 //   q = -(A t^2 + D dy^2) / 2,  t = dx + (B/A) dy,  D = C - B^2/A,
@@ -39,18 +39,6 @@ struct BlendArgs {
   ViewBatch batch;
 };
 
-// Pixel of this thread inside its tile: wave w owns quadrant (w & 1, w >> 1).
-__device__ inline void pixel_of_thread(int& i, int& j) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  i = (w & 1) * 8 + (l & 7);
-  j = (w >> 1) * 8 + (l >> 3);
-}
-
-struct Staged {
-  float4 a;  // mx, my (tile-relative), A', beta
-  float4 b;  // D', q2min, o, r
-  float2 c;  // g, b
-};
 
 __device__ inline void stage_splat(const float4* splats, const float4* colors, uint32_t g, float x0, float y0,
                                    float4& a, float4& b, float2& c) {
@@ -72,8 +60,7 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
 }
 
 // Which parts of a tile can hold a pixel at which the splat is not skipped
-// (the forward's waves own 8x8 quadrants, the backward's 16x8 halves).  Such
-// a pixel has
+// (a wave owns one 16x8 half).  Such a pixel has
 // |A'| t^2 + |D'| dy^2 <= P = -q2min with t = dx + beta dy: an ellipse with
 // half extents ry = sqrt(P / |D'|) in y and rx = sqrt(P (1/|A'| + beta^2/|D'|))
 // in x.  The box is widened by 1% + 1/16 px, so the float evaluation of the
@@ -100,20 +87,6 @@ __device__ inline int splat_box(const float4& a, const float4& b, float& rx, flo
   return 1;
 }
 
-// Bit q + 2 r set if the box meets pixels [8q, 8q+7] x [8r, 8r+7] of the tile.
-__device__ inline uint32_t quadrant_mask(const float4& a, const float4& b) {
-  float rx, ry;
-  const int k = splat_box(a, b, rx, ry);
-  if (k != 1) return k == 2 ? 0xFu : 0u;
-  uint32_t m = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float qx0 = (float)((q & 1) * 8), qy0 = (float)((q >> 1) * 8);
-    if (a.x + rx >= qx0 && a.x - rx <= qx0 + 7.0f && a.y + ry >= qy0 && a.y - ry <= qy0 + 7.0f) m |= 1u << q;
-  }
-  return m;
-}
-
 // Bit h set if the box meets pixel rows [8h, 8h+7] of the tile.
 __device__ inline uint32_t half_mask(const float4& a, const float4& b) {
   float rx, ry;
@@ -126,68 +99,73 @@ __device__ inline uint32_t half_mask(const float4& a, const float4& b) {
   return m;
 }
 
-// Per-quadrant lists of the staged entries, in entry order.
-struct QuadLists {
-  uint8_t idx[4][kBlock];
-  uint32_t wcount[4][4];  // [staging wave][quadrant]
-};
-
 __device__ inline uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Called by all threads after thread t staged entry t with quadrant mask m
-// (0 for no entry); returns the length of the calling wave's list.  Contains
-// the barriers that publish the staged records too.
-__device__ inline int build_quad_lists(uint32_t m, QuadLists& Q) {
+// Both blends run two waves per tile, and each lane owns two pixels of its
+// wave's 16x8 half: (l & 15, 8w + (l >> 4)) and the pixel 4 rows below.  Every
+// LDS read of a staged splat (and, in the backward, every DPP reduction) then
+// serves two pixels: the per-splat loops are bound by LDS bandwidth and VALU
+// issue together.
+constexpr int kPairThreads = 128;
+constexpr int kPairChunk = kPairThreads;
+
+struct HalfLists {
+  uint8_t idx[2][kPairChunk];
+  uint32_t wcount[2][2];  // [staging wave][half]
+};
+
+// Per-half lists of the staged entries, in entry order; called by all threads
+// after thread t staged entry t with half mask m (0 for no entry); returns
+// the length of the calling wave's list.  Contains the barriers that publish
+// the staged records too.
+__device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  uint64_t bal[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) bal[q] = __ballot((m >> q) & 1u);
+  const uint64_t bal0 = __ballot(m & 1u), bal1 = __ballot((m >> 1) & 1u);
   if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Q.wcount[wave][q] = (uint32_t)__builtin_popcountll(bal[q]);
+    Q.wcount[wave][0] = (uint32_t)__builtin_popcountll(bal0);
+    Q.wcount[wave][1] = (uint32_t)__builtin_popcountll(bal1);
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if ((m >> q) & 1u) {
-      uint32_t off = 0;
-      for (uint32_t w = 0; w < wave; ++w) off += Q.wcount[w][q];
-      Q.idx[q][off + lanes_below(bal[q])] = (uint8_t)threadIdx.x;
-    }
-  }
-  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave] + Q.wcount[2][wave] + Q.wcount[3][wave]);
+  if (m & 1u) Q.idx[0][(wave ? Q.wcount[0][0] : 0u) + lanes_below(bal0)] = (uint8_t)threadIdx.x;
+  if (m & 2u) Q.idx[1][(wave ? Q.wcount[0][1] : 0u) + lanes_below(bal1)] = (uint8_t)threadIdx.x;
+  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave]);
   __syncthreads();
   return n;
 }
 
 // One block per tile of every view of the batch (tiles are numbered view by
 // view; the view of a block is found from the views' first tile ids).
-__global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
-  __shared__ float4 sa[kBlock];
-  __shared__ float4 sb[kBlock];
-  __shared__ float2 sc[kBlock];
-  __shared__ QuadLists Q;
-  const uint32_t wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(kPairThreads) void blend_forward_kernel(BlendArgs a) {
+  __shared__ float4 sa[kPairChunk];
+  __shared__ float4 sb[kPairChunk];
+  __shared__ float2 sc[kPairChunk];
+  __shared__ HalfLists Q;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x);
   int vi = 0;
   while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
   const ViewParams& vp = a.batch.v[vi];
   const int tile = (int)(gtile - vp.tile_base);
   const int tx = tile % vp.tiles_x, ty = tile / vp.tiles_x;
-  int i, j;
-  pixel_of_thread(i, j);
-  const int px = tx * kTile + i, py = ty * kTile + j;
-  const bool inside = px < vp.width && py < vp.height;
-  const float fi = (float)i, fj = (float)j;
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 r = a.ranges[gtile];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t last = 0;
-  bool done = !inside;
-  for (uint32_t base = r.x; base < r.y; base += kBlock) {
-    if (__syncthreads_count(!done) == 0) break;
+  const int i = (int)(lane & 15u), j0 = (int)(8u * wave + (lane >> 4));
+  const float fi = (float)i, fj[2] = {(float)j0, (float)(j0 + 4)};
+  const int px = tx * kTile + i;
+  bool inside[2], done[2];
+  float T[2], C0[2], C1[2], C2[2];
+  uint32_t last[2];
+  for (int q = 0; q < 2; ++q) {
+    inside[q] = px < vp.width && ty * kTile + j0 + 4 * q < vp.height;
+    done[q] = !inside[q];
+    T[q] = 1.0f;
+    C0[q] = C1[q] = C2[q] = 0.0f;
+    last[q] = 0;
+  }
+  for (uint32_t base = r.x; base < r.y; base += kPairChunk) {
+    if (__syncthreads_count(!(done[0] && done[1])) == 0) break;
     const uint32_t k = base + threadIdx.x;
     uint32_t m = 0;
     if (k < r.y) {
@@ -197,41 +175,47 @@ __global__ __launch_bounds__(kBlock) void blend_forward_kernel(BlendArgs a) {
       sa[threadIdx.x] = ta;
       sb[threadIdx.x] = tb;
       sc[threadIdx.x] = tc;
-      m = quadrant_mask(ta, tb);
+      m = half_mask(ta, tb);
     }
-    const int cnt = build_quad_lists(m, Q);
-    if (!done) {
+    const int cnt = build_half_lists(m, Q);
+    if (!(done[0] && done[1])) {
       for (int jj = 0; jj < cnt; ++jj) {
         const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
         const float4 ga = sa[e], gb = sb[e];
-        float dx, dy, t;
-        const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
-        if (!(q2 >= gb.y)) continue;
-        const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
-        const float tn = T * (1.0f - alpha);
-        if (tn < kTmin) {
-          done = true;
-          break;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float dx, dy, t;
+          const float q2 = exponent2(ga, gb, fi, fj[q], dx, dy, t);
+          if (done[q] || !(q2 >= gb.y)) continue;
+          const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
+          const float tn = T[q] * (1.0f - alpha);
+          if (tn < kTmin) {
+            done[q] = true;
+            continue;
+          }
+          const float2 gc = sc[e];
+          const float w = alpha * T[q];
+          C0[q] = __builtin_fmaf(gb.w, w, C0[q]);
+          C1[q] = __builtin_fmaf(gc.x, w, C1[q]);
+          C2[q] = __builtin_fmaf(gc.y, w, C2[q]);
+          T[q] = tn;
+          last[q] = base - r.x + (uint32_t)e + 1u;
         }
-        const float2 gc = sc[e];
-        const float w = alpha * T;
-        C0 = __builtin_fmaf(gb.w, w, C0);
-        C1 = __builtin_fmaf(gc.x, w, C1);
-        C2 = __builtin_fmaf(gc.y, w, C2);
-        T = tn;
-        last = base - r.x + (uint32_t)e + 1u;
+        if (done[0] && done[1]) break;
       }
     }
   }
-  if (inside) {
-    const size_t hw = (size_t)vp.width * vp.height, p = (size_t)py * vp.width + px;
-    float* out = a.out.rgb[vi];
-    out[p] = __builtin_fmaf(T, vp.bg[0], C0);
-    out[hw + p] = __builtin_fmaf(T, vp.bg[1], C1);
-    out[2 * hw + p] = __builtin_fmaf(T, vp.bg[2], C2);
+  const size_t hw = (size_t)vp.width * vp.height;
+  float* out = a.out.rgb[vi];
+  for (int q = 0; q < 2; ++q) {
+    if (!inside[q]) continue;
+    const size_t p = (size_t)(ty * kTile + j0 + 4 * q) * vp.width + px;
+    out[p] = __builtin_fmaf(T[q], vp.bg[0], C0[q]);
+    out[hw + p] = __builtin_fmaf(T[q], vp.bg[1], C1[q]);
+    out[2 * hw + p] = __builtin_fmaf(T[q], vp.bg[2], C2[q]);
     if (a.save) {
-      a.pixel_T[vp.pixel_base + p] = T;
-      a.pixel_last[vp.pixel_base + p] = last;
+      a.pixel_T[vp.pixel_base + p] = T[q];
+      a.pixel_last[vp.pixel_base + p] = last[q];
     }
   }
 }
@@ -296,34 +280,6 @@ __device__ inline float row_reduce_scatter9(const float v[9], bool b3, bool b2, 
   return keep + dpp<kDppQuadXor1>(send);
 }
 
-// The backward runs two waves per tile, and each lane owns two pixels of its
-// wave's 16x8 half: (l & 15, 8w + (l >> 4)) and the pixel 4 rows below.  Every
-// LDS read of a staged splat and every DPP reduction then serves two pixels
-// (the reverse sweep is bound by LDS bandwidth and VALU issue together).
-constexpr int kBwdThreads = 128;
-constexpr int kBwdChunk = kBwdThreads;
-
-struct HalfLists {
-  uint8_t idx[2][kBwdChunk];
-  uint32_t wcount[2][2];  // [staging wave][half]
-};
-
-// As build_quad_lists, for the two halves and two waves of a backward block.
-__device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint64_t bal0 = __ballot(m & 1u), bal1 = __ballot((m >> 1) & 1u);
-  if (lane == 0) {
-    Q.wcount[wave][0] = (uint32_t)__builtin_popcountll(bal0);
-    Q.wcount[wave][1] = (uint32_t)__builtin_popcountll(bal1);
-  }
-  __syncthreads();
-  if (m & 1u) Q.idx[0][(wave ? Q.wcount[0][0] : 0u) + lanes_below(bal0)] = (uint8_t)threadIdx.x;
-  if (m & 2u) Q.idx[1][(wave ? Q.wcount[0][1] : 0u) + lanes_below(bal1)] = (uint8_t)threadIdx.x;
-  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave]);
-  __syncthreads();
-  return n;
-}
-
 // State of one pixel in the backward.
 struct BwdPixel {
   float fi, fj;        // tile-relative position
@@ -383,12 +339,12 @@ __device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx,
   v[4] += (h * dy) * dy;
 }
 
-__global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArgs a) {
-  __shared__ float4 sa[kBwdChunk];
-  __shared__ float4 sb[kBwdChunk];
-  __shared__ float2 sc[kBwdChunk];
-  __shared__ uint32_t sid[kBwdChunk];
-  __shared__ float acc[9][kBwdChunk];
+__global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdArgs a) {
+  __shared__ float4 sa[kPairChunk];
+  __shared__ float4 sb[kPairChunk];
+  __shared__ float2 sc[kPairChunk];
+  __shared__ uint32_t sid[kPairChunk];
+  __shared__ float acc[9][kPairChunk];
   __shared__ uint32_t s_maxlast;
   __shared__ HalfLists Q;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -419,7 +375,7 @@ __global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArg
       }
   } else {
     bool done0 = !P[0].inside, done1 = !P[1].inside;
-    for (uint32_t base = r.x; base < r.y; base += kBwdChunk) {
+    for (uint32_t base = r.x; base < r.y; base += kPairChunk) {
       if (__syncthreads_count(!(done0 && done1)) == 0) break;
       const uint32_t k = base + threadIdx.x;
       uint32_t m = 0;
@@ -470,8 +426,8 @@ __global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArg
   const bool rb3 = (rpos >> 3) & 1u, rb2 = (rpos >> 2) & 1u, rb1 = (rpos >> 1) & 1u, rb0 = rpos & 1u;
   const int rval = (rb3 ? 5 : 0) + (rb2 ? 3 : 0) + (rb1 ? 2 : 0) + (rb0 ? 1 : 0);
   const bool rvalid = (kRowValid >> rpos) & 1u;
-  for (int end = (int)maxlast; end > 0; end -= kBwdChunk) {
-    const int beg = max(end - kBwdChunk, 0);
+  for (int end = (int)maxlast; end > 0; end -= kPairChunk) {
+    const int beg = max(end - kPairChunk, 0);
     __syncthreads();
     uint32_t m = 0;
     if (beg + (int)threadIdx.x < end) {
@@ -536,7 +492,7 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
   a.out = out;
   a.batch = b;
   ProfScope prof(s, kKBlendForward);
-  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)total_tiles), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)total_tiles), dim3(kPairThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -561,7 +517,7 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.n = (uint32_t)n;
   const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
   ProfScope prof(s, kKBlendBackward);
-  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kBwdThreads), 0, s, a);
+  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kPairThreads), 0, s, a);
   return hipGetLastError();
 }
 

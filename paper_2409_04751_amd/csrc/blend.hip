@@ -25,7 +25,6 @@ namespace {
 
 constexpr float kTmin = 1e-4f;
 constexpr float kAlphaMax = 0.99f;
-constexpr float kNegTwoLn2 = -1.3862943611198906f;  // converts the log2-scaled A, D back to natural units
 
 struct BlendArgs {
   const uint2* ranges;
@@ -309,35 +308,45 @@ __device__ inline void resweep_step(BwdPixel& px, bool& done, const float4& ga, 
 // Reverse step for one pixel, adding its 9 gradient terms to v.  One path
 // for every lane: a pixel the splat does not reach takes alpha = 0, which
 // leaves its transmittance and colour-behind exactly unchanged and adds
-// zeros, so the DPP exchange needs no branches.
+// zeros, so the DPP exchange needs no branches.  Terms 0-4 are accumulated
+// without their constant factors (kGradScale), which are applied once per
+// splat when the block's sums are flushed.
 __device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx, float dy, float t, const float4& ga,
                                     const float4& gb, const float2& gc, float v[9]) {
   const float eq = __builtin_amdgcn_exp2f(q2);
   const float raw = gb.z * eq;
   const float alpha = pass ? fminf(kAlphaMax, raw) : 0.0f;
-  const float om = 1.0f - alpha;
-  const float Ti = pass ? px.T * __builtin_amdgcn_rcpf(om) : px.T;
+  const float Ti = pass ? px.T * __builtin_amdgcn_rcpf(1.0f - alpha) : px.T;
   const float w = alpha * Ti;
-  v[6] += w * px.G0;
-  v[7] += w * px.G1;
-  v[8] += w * px.G2;
-  const float dLda = Ti * ((gb.w - px.B0) * px.G0 + (gc.x - px.B1) * px.G1 + (gc.y - px.B2) * px.G2);
-  px.B0 = alpha * gb.w + om * px.B0;
-  px.B1 = alpha * gc.x + om * px.B1;
-  px.B2 = alpha * gc.y + om * px.B2;
+  v[6] = __builtin_fmaf(w, px.G0, v[6]);
+  v[7] = __builtin_fmaf(w, px.G1, v[7]);
+  v[8] = __builtin_fmaf(w, px.G2, v[8]);
+  // colour minus colour behind, for dL/dalpha and for the update behind
+  const float d0 = gb.w - px.B0, d1 = gc.x - px.B1, d2 = gc.y - px.B2;
+  const float dLda = Ti * __builtin_fmaf(d0, px.G0, __builtin_fmaf(d1, px.G1, d2 * px.G2));
+  px.B0 = __builtin_fmaf(alpha, d0, px.B0);
+  px.B1 = __builtin_fmaf(alpha, d1, px.B1);
+  px.B2 = __builtin_fmaf(alpha, d2, px.B2);
   px.T = Ti;
-  const bool live = pass && raw < kAlphaMax;  // the clamp passes no gradient
-  const float dLdq = live ? dLda * alpha : 0.0f;
-  v[5] += live ? dLda * eq : 0.0f;
-  const float A = kNegTwoLn2 * ga.z, D = kNegTwoLn2 * gb.x;  // natural-scale conic terms
-  const float At = A * t;
-  v[0] += -dLdq * At;
-  v[1] += -dLdq * (ga.w * At + D * dy);
-  const float h = -0.5f * dLdq, hdx = h * dx;
-  v[2] += hdx * dx;
-  v[3] += (hdx + hdx) * dy;
-  v[4] += (h * dy) * dy;
+  const float dl = (pass && raw < kAlphaMax) ? dLda : 0.0f;  // the clamp passes no gradient
+  v[5] = __builtin_fmaf(dl, eq, v[5]);
+  const float g = dl * alpha;  // dL/dq of the natural exponent
+  const float azt = ga.z * t, bdy = gb.x * dy;  // products the exponent formed
+  v[0] = __builtin_fmaf(g, azt, v[0]);
+  v[1] = __builtin_fmaf(g, __builtin_fmaf(ga.w, azt, bdy), v[1]);
+  const float gdx = g * dx, gdy = g * dy;
+  v[2] = __builtin_fmaf(gdx, dx, v[2]);
+  v[3] = __builtin_fmaf(gdx, dy, v[3]);
+  v[4] = __builtin_fmaf(gdy, dy, v[4]);
 }
+
+// Factors of the accumulated terms.  With q = -(A t^2 + D dy^2) / 2 and the
+// record's A' = -A/(2 ln2), D' = -D/(2 ln2): dL/dmu_x = -sum g A t =
+// 2 ln2 sum g A' t, dL/dmu_y = -sum g (beta A t + D dy) = 2 ln2 sum g (beta A' t
+// + D' dy), dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy (B enters q twice),
+// dL/dC = -sum g dy^2 / 2.
+__constant__ const float kGradScale[9] = {1.3862943611198906f, 1.3862943611198906f, -0.5f, -1.0f, -0.5f,
+                                          1.0f, 1.0f, 1.0f, 1.0f};
 
 __global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ float4 sa[kPairChunk];
@@ -467,7 +476,7 @@ __global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdAr
     if ((int)threadIdx.x < end - beg) {
       const uint32_t g = sid[threadIdx.x];
       for (int k = 0; k < 9; ++k) {
-        const float val = acc[k][threadIdx.x];
+        const float val = acc[k][threadIdx.x] * kGradScale[k];
         if (val != 0.0f) atomicAdd(&a.grad2d[(size_t)k * a.n + g], val);
       }
     }

@@ -36,8 +36,8 @@ def log(*a):
 
 def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | None:
     """Algorithmic HBM bytes of ONE launch of `name` (byte model)."""
-    if name == "preprocess":
-        return 52.0 * N + 44.0 * V
+    if name == "preprocess":  # one view: geometry and colour fused
+        return 52.0 * N + (4.0 * S + 76.0) * V
     if name == "color":
         return 4.0 * N + (4.0 * S + 32.0) * V
     if name == "depth_sort_scatter":

@@ -173,28 +173,12 @@ __global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block
   if (threadIdx.x == 0) out[blockIdx.x] = s_sum;
 }
 
-// Both forward kernels run one thread per (view, Gaussian) entry on a grid of
-// nviews x blocks-per-view blocks.  The xcd_chunk order puts the views of one
-// Gaussian block on one XCD at about the same time, so the parameters come
-// from HBM once per batch and from that XCD's L2 for the other views, while
-// each thread stays as lean as a single-view one.
-__device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i) {
-  // one view: plain order, so that all XCDs stream neighbouring lines of each
-  // plane (eight separate streams per plane lose DRAM row locality)
-  const uint32_t logical = nviews > 1 ? xcd_chunk(blockIdx.x, gridDim.x) : blockIdx.x;
-  vi = logical % nviews;
-  i = (logical / nviews) * kBlock + threadIdx.x;
-}
-
-// Geometry: cull, project, conic, radius, tile rect, depth key.  Culled
-// entries write only their tile count (0) and an all-ones depth key.
-__global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
-  uint32_t vi, i;
-  entry_of_block((uint32_t)a.batch.count, vi, i);
-  if (i >= a.n) return;
+// Geometry of entry e = (view vi, Gaussian i): cull, project, conic, radius,
+// tile rect, depth key.  A culled entry writes only its tile count (0) and an
+// all-ones depth key.  Returns the tile count.
+__device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_t i, size_t e) {
   const uint32_t n = a.n;
   const ViewParams& vp = a.batch.v[vi];
-  const size_t e = (size_t)vi * n + i;
   uint32_t key = 0xFFFFFFFFu, ntiles = 0;
   Geometry G;
   do {
@@ -225,13 +209,62 @@ __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   } while (false);
   a.depth_keys[e] = key;
   a.tiles[e] = ntiles;
+  return ntiles;
 }
 
-// SH colour of every entry the geometry kernel kept.  An entry whose colour
-// is not finite is culled here, before the scans read the tile counts.  With
-// several views each block also leaves its tile total in
-// block_tiles[view][block] (a plain store per block, summed per view
-// afterwards: no contended atomics).
+// SH colour of a kept entry, coefficients c already loaded.  An entry whose
+// colour is not finite is culled here, before the scans read the tile
+// counts.  Returns the entry's tile count afterwards.
+template <int DEG>
+__device__ inline uint32_t entry_color(const PreArgs& a, uint32_t vi, uint32_t i, size_t e, const float c[48],
+                                       uint32_t ntiles) {
+  float dir[3], Y[16], rgb[3];
+  double vd[3], vlen;
+  view_dir(a.means, i, a.n, a.batch.v[vi].campos, dir, vd, vlen);
+  sh_color<DEG>(c, dir, rgb, Y);
+  if (isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2])) {
+    a.colors[e] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+    return ntiles;
+  }
+  a.tiles[e] = 0;
+  a.depth_keys[e] = 0xFFFFFFFFu;
+  return 0;
+}
+
+// One view: geometry and colour in one thread (the coefficients are read
+// only for the Gaussians the view keeps).
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void preprocess_fused_kernel(PreArgs a) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const uint32_t ntiles = entry_geometry(a, 0u, i, i);
+  if (ntiles == 0) return;
+  float c[48];
+  load_sh<DEG>(a.sh, i, a.n, c);
+  entry_color<DEG>(a, 0u, i, i, c, ntiles);
+}
+
+// Batches: the geometry and the colour run as two kernels over a grid of
+// nviews x blocks-per-view blocks (one thread per entry; a thread looping
+// over the views needed over 200 VGPRs once the compiler hoisted the
+// view-invariant work).  The xcd_chunk order puts the views of one Gaussian
+// block on one XCD at about the same time, so the parameters come from HBM
+// once per batch and from that XCD's L2 for the other views.
+__device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i) {
+  const uint32_t logical = xcd_chunk(blockIdx.x, gridDim.x);
+  vi = logical % nviews;
+  i = (logical / nviews) * kBlock + threadIdx.x;
+}
+
+__global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
+  uint32_t vi, i;
+  entry_of_block((uint32_t)a.batch.count, vi, i);
+  if (i >= a.n) return;
+  entry_geometry(a, vi, i, (size_t)vi * a.n + i);
+}
+
+// Also leaves each block's tile total in block_tiles[view][block] (a plain
+// store per block, summed per view afterwards: no contended atomics).
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void color_kernel(PreArgs a) {
   uint32_t vi, i;
@@ -240,33 +273,19 @@ __global__ __launch_bounds__(kBlock) void color_kernel(PreArgs a) {
   const size_t e = (size_t)vi * n + i;
   const bool in_range = i < n;
   uint32_t ntiles = in_range ? a.tiles[e] : 0u;
-  // the coefficients and the mean are loaded without waiting for the
-  // visibility (a wave with any visible lane fetches all of their lines)
+  // the coefficients are loaded without waiting for the visibility (a wave
+  // with any visible lane fetches all of their lines)
   float c[48];
   if (in_range) load_sh<DEG>(a.sh, i, n, c);
-  if (ntiles != 0) {
-    float dir[3], Y[16], rgb[3];
-    double vd[3], vlen;
-    view_dir(a.means, i, n, a.batch.v[vi].campos, dir, vd, vlen);
-    sh_color<DEG>(c, dir, rgb, Y);
-    if (isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2])) {
-      a.colors[e] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
-    } else {
-      a.tiles[e] = 0;
-      a.depth_keys[e] = 0xFFFFFFFFu;
-      ntiles = 0;
-    }
-  }
-  if (a.batch.count > 1) {  // uniform
-    __shared__ uint32_t s_sum;
-    if (threadIdx.x == 0) s_sum = 0;
-    __syncthreads();
-    const uint32_t wsum = wave_sum_u32(ntiles);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, wsum);
-    __syncthreads();
-    // thread 0 holds the block's first Gaussian, so i / kBlock is the block of the view
-    if (threadIdx.x == 0) a.block_tiles[(size_t)vi * (gridDim.x / a.batch.count) + i / kBlock] = s_sum;
-  }
+  if (ntiles != 0) ntiles = entry_color<DEG>(a, vi, i, e, c, ntiles);
+  __shared__ uint32_t s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  const uint32_t wsum = wave_sum_u32(ntiles);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&s_sum, wsum);
+  __syncthreads();
+  // thread 0 holds the block's first Gaussian, so i / kBlock is the block of the view
+  if (threadIdx.x == 0) a.block_tiles[(size_t)vi * (gridDim.x / a.batch.count) + i / kBlock] = s_sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -455,6 +474,18 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* w
   a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
   const bool multi = b.count > 1;
+  if (!multi) {
+    ProfScope prof(s, kKPreprocess);
+#define FGS_PRE_LAUNCH(D) hipLaunchKernelGGL((preprocess_fused_kernel<D>), dim3(blocks), dim3(kBlock), 0, s, a);
+    switch (g.sh_degree) {
+      case 0: FGS_PRE_LAUNCH(0) break;
+      case 1: FGS_PRE_LAUNCH(1) break;
+      case 2: FGS_PRE_LAUNCH(2) break;
+      default: FGS_PRE_LAUNCH(3) break;
+    }
+#undef FGS_PRE_LAUNCH
+    return hipGetLastError();
+  }
   const dim3 grid(blocks * (unsigned)b.count);
   {
     ProfScope prof(s, kKPreprocess);
@@ -469,7 +500,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* w
     default: FGS_PRE_LAUNCH(3) break;
   }
 #undef FGS_PRE_LAUNCH
-  if (multi) {
+  {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(view_sums_kernel, dim3(b.count), dim3(kBlock), 0, s, a.block_tiles, blocks,

@@ -44,8 +44,10 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * N
     if name == "depth_sort_hist":
         return 4.0 * N
-    if name == "duplicate":
-        return 20.0 * V + 8.0 * K
+    if name == "reach":  # ids, splat records and tile counts in; reach records and counts out
+        return 76.0 * V
+    if name == "duplicate":  # ids, rects, offsets and reach records in; K pairs out
+        return 48.0 * V + 8.0 * K
     if name == "tile_sort_hist":
         return 4.0 * K
     if name == "tile_sort_scatter":
@@ -67,19 +69,69 @@ def path_bytes(N: int, V: int, K: int, P: int, S: int) -> float:
     return 52.0 * N + (12.0 * S + 316.0) * V + 124.0 * K + 44.0 * P
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_room3m_1752x1168.json")
+
+
 def traffic_for(kernel: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
-    if not os.path.exists(path):
-        return None
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is
+    none or it was taken on other sources than the current ones."""
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha") != source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+# Floating-point operations of the blend backward (an FMA counts 2, exp2 and
+# rcp count 1 each).  Every (pixel, entry) pair up to the pixel's last
+# blended entry evaluates the exponent (9) and tests it (1); a pair that
+# blends adds alpha 3, transmittance in front 3, colour gradient 7, colour
+# difference 3, dL/dalpha 6, colour behind 6, opacity term 2, dL/dq 1 and the
+# mean and conic terms 16.
+BLEND_BWD_FLOPS_TESTED = 10.0
+BLEND_BWD_FLOPS_BLENDED = 47.0
+
+
+def contributing_pairs(ws, lay, n: int, K: int) -> tuple[int, int]:
+    """(E_b, C) of the blend backward: E_b = (pixel, entry) pairs up to each
+    pixel's last blended entry (the sum of the saved counts); C = those whose
+    alpha is at least 1/255 at the pixel, evaluated from the library's own
+    state in fp64."""
+    import torch
+
+    tx, ty = lay.tiles_x, lay.tiles_y
+    W, H = lay.width, lay.height
+    rng = ws.view(lay.ranges, 2 * tx * ty, torch.int32).view(-1, 2).long()
+    ids = ws.view(lay.tile_ids, K, torch.int32).long()
+    sp = ws.view(lay.splats, 8 * n, torch.float32).view(n, 8).double()
+    last = ws.view(lay.pixel_last, W * H, torch.int32).long()
+    counts = (rng[:, 1] - rng[:, 0]).clamp_min(0)
+    tile = torch.repeat_interleave(torch.arange(tx * ty, device=ids.device), counts)
+    assert tile.numel() == K
+    rel = torch.arange(K, device=ids.device) - rng[tile, 0]
+    u = torch.arange(16, device=ids.device)
+    total = 0
+    step = 1 << 19
+    for s in range(0, K, step):
+        e = min(K, s + step)
+        g = ids[s:e]
+        t = tile[s:e]
+        px = (t % tx)[:, None, None] * 16 + u[None, None, :]
+        py = (t // tx)[:, None, None] * 16 + u[None, :, None]
+        inside = (px < W) & (py < H)
+        rec = sp[g]
+        dx = (rec[:, 0] + rec[:, 2])[:, None, None] - px
+        dy = (rec[:, 1] + rec[:, 3])[:, None, None] - py
+        q = dx + rec[:, 5][:, None, None] * dy
+        q2 = rec[:, 4][:, None, None] * q * q + rec[:, 6][:, None, None] * dy * dy
+        lp = last[(py.clamp(max=H - 1) * W + px.clamp(max=W - 1))]
+        ok = inside & (q2 >= rec[:, 7][:, None, None]) & (rel[s:e][:, None, None] < lp)
+        total += int(ok.sum().item())
+    return int(last.sum().item()), total
 
 
 def source_sha() -> str:
@@ -293,6 +345,13 @@ def main() -> int:
     V = int((tiles > 0).sum().item())
     N, P, S = scene.n, cam.width * cam.height, scene.sh.shape[0]
 
+    pairs = None
+    if not args.no_profile:
+        _, ws3, _ = R.render_forward(*[x.detach() for x in leaves], deg, pose, cam, bg, save_pixel_state=True)
+        pairs = contributing_pairs(ws3, ws3.layout(scene.n, cam.width, cam.height), scene.n, K)
+        del ws3
+        log(f"blend backward pairs: tested {pairs[0]}, blended {pairs[1]}")
+
     kernels = {k: dict(launches=v[0] // args.steps if args.steps else 0, ms=v[1] / args.steps,
                        avg_ms=v[1] / max(v[0], 1)) for k, v in prof.items()}
     roofline = None
@@ -305,6 +364,13 @@ def main() -> int:
             roofline = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                             frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for(dom),
                             bytes_per_launch=b, avg_launch_ms=round(d["avg_ms"], 5))
+        elif dom == "blend_backward" and pairs:
+            fl = BLEND_BWD_FLOPS_TESTED * pairs[0] + BLEND_BWD_FLOPS_BLENDED * pairs[1]
+            ach = fl / (d["avg_ms"] * 1e-3) / 1e12
+            roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 2), peak=FP32_VALU_PEAK_TFLOPS,
+                            unit="TFLOP/s", frac=round(ach / FP32_VALU_PEAK_TFLOPS, 4), traffic=traffic_for(dom),
+                            flops_per_launch=fl, pairs_tested=pairs[0], pairs_blended=pairs[1],
+                            avg_launch_ms=round(d["avg_ms"], 5))
         else:
             roofline = dict(kernel=dom, bound="alu", achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                             frac=None, traffic=traffic_for(dom), avg_launch_ms=round(d["avg_ms"], 5))

@@ -54,6 +54,11 @@ extern "C" {
 #define FGS_SAVE_PIXEL_STATE 1u /* also store per-pixel final transmittance and
                                    contributor count; the backward then reads
                                    them instead of recomputing them */
+#define FGS_RECT_BINNING 2u     /* bin each Gaussian to every tile of its
+                                   3-sigma rectangle (the vanilla 3DGS lists)
+                                   instead of only the tiles its alpha >= 1/255
+                                   ellipse can reach (the default); images and
+                                   gradients are the same either way */
 
 /* Intrinsics of one view (Sec. 3.2: f_x, f_y, c_x, c_y).  Gaussians are culled
  * when |mu_c| <= near_dist or when the incidence angle theta exceeds

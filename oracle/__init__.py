@@ -115,7 +115,11 @@ def sh_basis(degree: int, d) -> np.ndarray:
 
 # -- pipeline --------------------------------------------------------------
 
-def preprocess(scene, pose, cam) -> dict:
+def preprocess(scene, pose, cam, binning: str = "tight") -> dict:
+    """binning "tight": each Gaussian keeps only the tiles of its 3-sigma rect
+    that its (margin-grown) alpha >= 1/255 ellipse reaches; "rect": every tile
+    of the rect (vanilla lists).  Images and gradients are the same."""
+    assert binning in ("tight", "rect")
     n = scene.n
     o = dict(
         visible=np.zeros(n, np.uint8), mu_p=np.zeros((n, 2)), conic=np.zeros((n, 3)), rgb=np.zeros((n, 3)),
@@ -128,6 +132,10 @@ def preprocess(scene, pose, cam) -> dict:
                          _p(o["mu_p"]), _p(o["conic"]), _p(o["rgb"]), _p(o["clamped"]), _p(o["radius"]),
                          _p(o["rect"]), _p(o["depth"]), _p(o["tiles"]), _p(o["tie"]))
     o["opacity"] = opac
+    o["binning"] = binning
+    if binning == "tight":
+        lib().orc_tighten(ctypes.c_int64(n), _p(o["visible"]), _p(o["mu_p"]), _p(o["conic"]), _p(opac),
+                          _p(o["rect"]), _p(o["tiles"]), _p(o["tie"]))
     return o
 
 
@@ -139,7 +147,8 @@ def bin_and_sort(pre: dict, cam) -> dict:
     ranges = np.zeros((cam.tiles_x * cam.tiles_y, 2), np.uint32)
     lib().orc_bin(ctypes.c_int64(n), _p(pre["visible"]), _p(pre["rect"]), _p(pre["depth"]),
                   ctypes.c_int32(cam.width), ctypes.c_int32(cam.height), ctypes.c_int64(k), _p(keys), _p(vals),
-                  _p(ranges))
+                  _p(ranges), ctypes.c_int(1 if pre.get("binning", "rect") == "tight" else 0), _p(pre["mu_p"]),
+                  _p(pre["conic"]), _p(pre["opacity"]))
     return dict(K=int(k), keys=keys[:k], vals=vals[:k], ranges=ranges)
 
 
@@ -209,9 +218,9 @@ def preprocess_backward(scene, pose, cam, pre: dict, g2d: dict) -> dict:
     return out
 
 
-def render(scene, pose, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL) -> dict:
+def render(scene, pose, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL, binning: str = "tight") -> dict:
     """Full forward: preprocess, bin + sort, blend."""
-    pre = preprocess(scene, pose, cam)
+    pre = preprocess(scene, pose, cam, binning)
     bins = bin_and_sort(pre, cam)
     out = blend(pre, bins, cam, bg, tol)
     out.update(pre=pre, bins=bins)

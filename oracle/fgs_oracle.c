@@ -425,6 +425,91 @@ void orc_preprocess(int64_t n, const double* means, const double* scales, const 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tight binning: only the tiles of the rect the splat can reach.             */
+/* ------------------------------------------------------------------------ */
+/*
+ * A pixel (x, y) is blended with a splat only if alpha >= 1/255, that is
+ * q = -(A u^2 + 2 B u v + C v^2) / 2 >= ln(1 / (255 o)) with (u, v) = (x, y) -
+ * mu_p, i.e. inside the ellipse A u^2 + 2 B u v + C v^2 <= r2 = 2 ln(255 o).
+ * A tile (tx, ty) of the 3-sigma rect is kept if that ellipse, grown to
+ * r2 * 1.0201 (radius + 1%) and padded by 1/8 px, reaches the tile's
+ * pixel-centre box [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15]; dropping the
+ * other tiles changes no pixel.  The margin is the library's, so that its
+ * float evaluation of the per-pixel test never passes outside the kept
+ * tiles.  Conventions shared with it (in log2 units P = r2 / (2 ln 2)):
+ * P < 0 keeps no tile, 0 <= P <= 1e-6 and |B / A| > 1e3 keep the whole rect.
+ *
+ * Per row of tiles the reached columns are one interval: the ellipse's
+ * u-extent over the row's v-range.  u_max(v) = (-B v + sqrt(A r2 - det v^2)) / A
+ * is concave with its peak at v = -B sqrt(r2 / (det C)), u_min(v) =
+ * (-B v - sqrt(A r2 - det v^2)) / A convex with its trough at the opposite
+ * v, det = A C - B^2; each is clamped to the row's v-range.
+ */
+static const double kTightGrow = 1.0201, kTightPad = 0.125, kTightP0 = 1e-6, kTightBeta = 1e3;
+
+/* 0: no tile, 1: per-row intervals, 2: the whole rect. */
+static int tight_kind(const double* con, double opac) {
+  const double P = log2(255.0 * opac);
+  if (!(P >= 0.0)) return 0;
+  if (P <= kTightP0) return 2;
+  if (!(fabs(con[1] / con[0]) <= kTightBeta)) return 2;
+  return 1;
+}
+
+/* Columns [c0, c1) of tile row ty reached within [x0, x1) (kind 1). */
+static void tight_row(const double* mu, const double* con, double opac, int ty, int x0, int x1, double grow,
+                      double pad, int* c0, int* c1) {
+  const double A = con[0], B = con[1], C = con[2], det = A * C - B * B;
+  const double r2 = 2.0 * log(255.0 * opac) * grow;
+  *c0 = *c1 = x0;
+  const double vmax = sqrt(A * r2 / det);
+  const double vlo = fmax(TILE * ty - pad - mu[1], -vmax), vhi = fmin(TILE * ty + TILE - 1 + pad - mu[1], vmax);
+  if (!(vlo <= vhi)) return;
+  const double vs = B * sqrt(r2 / (det * C));
+  const double va = fmin(fmax(-vs, vlo), vhi), vb = fmin(fmax(vs, vlo), vhi);
+  const double umax = (-B * va + sqrt(fmax(0.0, A * r2 - det * va * va))) / A;
+  const double umin = (-B * vb - sqrt(fmax(0.0, A * r2 - det * vb * vb))) / A;
+  const double xlo = mu[0] + umin - pad, xhi = mu[0] + umax + pad;
+  const int lo = (int)fmin(fmax(ceil((xlo - (TILE - 1)) / TILE), x0), x1);
+  const int hi = (int)fmin(fmax(floor(xhi / TILE) + 1, x0), x1);
+  if (hi > lo) { *c0 = lo; *c1 = hi; }
+}
+
+/* Counts the kept tiles of every visible Gaussian into tiles[] (a Gaussian
+ * with none becomes invisible) and flags as a tie any whose count or
+ * intervals move when the margins move by 1e-4 (relative) / 4e-3 px (well
+ * beyond the float rounding of the library's evaluation). */
+void orc_tighten(int64_t n, uint8_t* visible, const double* mu_p, const double* conic, const double* opac,
+                 const int32_t* rect, uint32_t* tiles, uint8_t* tie) {
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i) {
+    if (!visible[i]) continue;
+    const int32_t* rc = &rect[i * 4];
+    const double* con = &conic[i * 3];
+    const double P = log2(255.0 * opac[i]);
+    if (fabs(P) < 1e-9 || fabs(P - kTightP0) < 1e-9 ||
+        fabs(fabs(con[1] / con[0]) - kTightBeta) < 1e-6 * kTightBeta)
+      tie[i] = 1;
+    const int kind = tight_kind(con, opac[i]);
+    int64_t count = 0;
+    if (kind == 2) {
+      count = (int64_t)(rc[2] - rc[0]) * (rc[3] - rc[1]);
+    } else if (kind == 1) {
+      for (int ty = rc[1]; ty < rc[3]; ++ty) {
+        int a0, a1, b0, b1, d0, d1;
+        tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow, kTightPad, &a0, &a1);
+        tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow * (1 + 1e-4), kTightPad + 4e-3, &b0, &b1);
+        tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow * (1 - 1e-4), kTightPad - 4e-3, &d0, &d1);
+        if (a1 - a0 != b1 - b0 || a1 - a0 != d1 - d0 || (a1 > a0 && (a0 != b0 || a0 != d0))) tie[i] = 1;
+        count += a1 - a0;
+      }
+    }
+    tiles[i] = (uint32_t)count;
+    if (count == 0) visible[i] = 0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tile binning and sort (Sec. 3.1 "Rendering").                              */
 /* ------------------------------------------------------------------------ */
 int64_t orc_count_pairs(int64_t n, const uint8_t* visible, const uint32_t* tiles) {
@@ -444,11 +529,13 @@ static int cmp_pair(const void* a, const void* b) {
   return 0;
 }
 
-/* Emit one (key, id) pair per (Gaussian, tile of its rect), key =
+/* Emit one (key, id) pair per (Gaussian, tile of its rect -- with tight, per
+ * kept tile), key =
  * tile_id << 32 | float bits of depth, then sort by (key, id) and find
  * each tile's [start, end) in the sorted list.  ranges is [ntiles][2]. */
 void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float* depth, int32_t width,
-             int32_t height, int64_t kcount, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+             int32_t height, int64_t kcount, uint64_t* keys, uint32_t* vals, uint32_t* ranges, int tight,
+             const double* mu_p, const double* conic, const double* opac) {
   const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
   pair_t* p = (pair_t*)malloc(sizeof(pair_t) * (size_t)(kcount > 0 ? kcount : 1));
   int64_t k = 0;
@@ -456,12 +543,19 @@ void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float
     if (!visible[i]) continue;
     uint32_t bits;
     memcpy(&bits, &depth[i], 4);
-    for (int ty = rect[i * 4 + 1]; ty < rect[i * 4 + 3]; ++ty)
-      for (int tx = rect[i * 4 + 0]; tx < rect[i * 4 + 2]; ++tx) {
+    const int kind = tight ? tight_kind(&conic[i * 3], opac[i]) : 2;
+    for (int ty = rect[i * 4 + 1]; ty < rect[i * 4 + 3]; ++ty) {
+      int c0 = rect[i * 4 + 0], c1 = rect[i * 4 + 2];
+      if (kind == 0) c1 = c0;
+      if (kind == 1)
+        tight_row(&mu_p[i * 2], &conic[i * 3], opac[i], ty, rect[i * 4 + 0], rect[i * 4 + 2], kTightGrow,
+                  kTightPad, &c0, &c1);
+      for (int tx = c0; tx < c1; ++tx) {
         p[k].key = ((uint64_t)(uint32_t)(ty * gx + tx) << 32) | bits;
         p[k].val = (uint32_t)i;
         ++k;
       }
+    }
   }
   qsort(p, (size_t)k, sizeof(pair_t), cmp_pair);
   for (int64_t t = 0; t < (int64_t)gx * gy * 2; ++t) ranges[t] = 0;

@@ -19,6 +19,7 @@ FGS_ERR_HIP = -3
 FGS_ERR_OVERFLOW = -4
 FGS_MODEL_EQUIDISTANT = 0
 FGS_SAVE_PIXEL_STATE = 1
+FGS_RECT_BINNING = 2
 FGS_MAX_BATCH = 8
 
 c_size = ctypes.c_size_t

@@ -73,6 +73,8 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.drx_b = take(nv * 4);
   L.dry_b = take(nv * 4);
   L.offsets = take(nv * 4);
+  L.reach = take(nv * 2 * sizeof(float4));
+  L.counts = take(nv * 4);
   L.grad2d = take(nn * 9 * 4);
   L.ranges = take((size_t)L.total_tiles * 8);
   L.pixel_T = take((size_t)L.total_pixels * 4);
@@ -239,7 +241,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
 
   HIP_TRY(launch_fill_u32(counters, 0u, kNumCounters, s), "clear counters");
   HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
-  HIP_TRY(launch_preprocess(*g, b, ws, L, s), "preprocess");
+  const bool tight = (flags & FGS_RECT_BINNING) == 0;
+  HIP_TRY(launch_preprocess(*g, b, tight, ws, L, s), "preprocess");
   // stable compaction of the visible (view, Gaussian) entries; offsets holds
   // their positions until the tile-count scan reuses it.  The compaction
   // also sums K and finds the depth-key range, so one read-back gives every
@@ -286,10 +289,16 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint32_t* d_ry = odd ? U(L.dry_b) : U(L.dry_a);
   if (odd && V > 0)
     HIP_TRY(hipMemcpyAsync(U(L.dvals_a), d_ids, (size_t)V * 4, hipMemcpyDeviceToDevice, s), "depth order");
-  HIP_TRY(launch_scan(d_rx, d_ry, nullptr, V, kScanRectArea, partials, counters + kCountK, U(L.offsets), s),
+  // per depth-ordered entry: reach parameters and kept-tile count, then the
+  // pair offsets as the exclusive scan of the counts
+  float4* reach = reinterpret_cast<float4*>(ws + L.reach);
+  HIP_TRY(launch_reach(d_ids, reinterpret_cast<const float4*>(ws + L.splats), U(L.tiles), V, tight, reach,
+                       U(L.counts), s),
+          "reach");
+  HIP_TRY(launch_scan(U(L.counts), nullptr, nullptr, V, kScanPlain, partials, counters + kCountK, U(L.offsets), s),
           "tile count scan");
-  HIP_TRY(launch_duplicate(d_ids, d_rx, d_ry, U(L.offsets), nullptr, V, K, b, n, L.tile_bits,
-                           hist, U(L.tkeys_a), U(L.tvals_a), s),
+  HIP_TRY(launch_duplicate(d_ids, d_rx, d_ry, U(L.offsets), nullptr, V, K, b, n, L.tile_bits, reach, hist,
+                           U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
   HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, true),
@@ -350,7 +359,7 @@ int fgs_render_forward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_c
   if (rc == FGS_OK) rc = check_view(pose, cam, bg);
   if (rc != FGS_OK) return rc;
   if (!workspace || !out_rgb) return fail(FGS_ERR_ARG, "null workspace or output");
-  if (flags & ~FGS_SAVE_PIXEL_STATE) return fail(FGS_ERR_ARG, "unknown flags");
+  if (flags & ~(FGS_SAVE_PIXEL_STATE | FGS_RECT_BINNING)) return fail(FGS_ERR_ARG, "unknown flags");
   float* outs[1] = {out_rgb};
   return forward_impl(g, 1, pose, cam, bg, flags, workspace, workspace_bytes, outs, nullptr, k_out,
                       reinterpret_cast<hipStream_t>(stream));

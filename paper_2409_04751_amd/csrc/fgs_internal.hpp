@@ -37,6 +37,7 @@ enum ScanMode {
   kScanPlain = 0,     // in_a[i]
   kScanFlag = 1,      // in_a[i] != 0
   kScanRectArea = 2,  // tile count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
+  kScanGather = 3,    // in_b[in_a[i]]
 };
 
 // Key / payload planes of a radix sort: input in *_a, scratch in *_b.
@@ -65,6 +66,7 @@ enum KernelId {
   kKPreprocessBackward,
   kKShBackward,
   kKColor,
+  kKReach,
   kKNumKernels
 };
 const char* kernel_name(int id);
@@ -114,6 +116,7 @@ struct Layout {
   size_t splats, colors, depth_keys, tiles, rects, radii;
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
+  size_t reach, counts;  // per depth-ordered visible entry: reach parameters (2 float4), kept-tile count
   size_t hist, partials, block_tiles;
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
   int tile_bits = 0, tile_passes = 0;
@@ -153,7 +156,7 @@ struct BatchOut {
 
 // Preprocess: writes splats, depth_keys, tiles, rects, radii, and seeds the
 // depth sort with (key, id) in dkeys_a / dvals_a.
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* ws, const Layout& L,
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, char* ws, const Layout& L,
                              hipStream_t s);
 
 // Exclusive scan of u32 values read as `mode` says; the item count is
@@ -190,9 +193,18 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
 // sort (tile_bits key bits) into hist.
 // Ids are view-major (view * n + Gaussian); the pair's key is the view's
 // tile_base plus the tile index inside the view.
+// Per depth-ordered visible entry j (ids[j]): its reach parameters (two
+// float4, from the splat record; the whole rect unless tight) and its tile
+// count tiles[ids[j]], both contiguous in j for the duplication.
+hipError_t launch_reach(const uint32_t* ids, const float4* splats, const uint32_t* tiles, int64_t V, bool tight,
+                        float4* reach, uint32_t* counts, hipStream_t s);
+
+// Emits every kept tile of each depth-ordered entry (its reach parameters
+// from launch_reach).
 hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
                             const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s);
+                            int tile_bits, const float4* reach, uint32_t* hist, uint32_t* out_keys,
+                            uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);
 

@@ -11,6 +11,7 @@
 // contiguous 256-byte segment per plane.
 #include "fgs_internal.hpp"
 #include "fisheye.hpp"
+#include "reach.hpp"
 
 namespace fgs {
 namespace {
@@ -35,6 +36,7 @@ struct PreArgs {
   uint2* rects;
   int32_t* radii;
   uint32_t* block_tiles;  // [view][block] tiles touched (multi-view only)
+  int tight;              // count only the tiles the alpha >= 1/255 ellipse reaches
   ViewBatch batch;
 };
 
@@ -193,14 +195,26 @@ __device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_
                  vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
     const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
     const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
-    const uint32_t area = (x1 - x0) * (y1 - y0);
+    uint32_t area = (x1 - x0) * (y1 - y0);
     if (area == 0) break;
     const float o = a.opac[i];
     const double A = G.conic[0], B = G.conic[1];
     const float hx = (float)G.mu[0], hy = (float)G.mu[1];
-    a.splats[2 * e + 0] = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-    a.splats[2 * e + 1] = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A),
-                                      (float)(-0.5 * kLog2e / (G.det * A)), (float)(-log2(255.0 * (double)o)));
+    const float4 s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+    const float4 s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
+                                  (float)(-log2(255.0 * (double)o)));
+    if (a.tight) {  // the tiles of the rect the splat's pixels can lie in
+      const SplatReach rr = splat_reach(s0, s1);
+      area = 0;
+      for (uint32_t ty = y0; ty < y1; ++ty) {
+        int c0, c1;
+        reach_row(rr, (int)ty, (int)x0, (int)x1, c0, c1);
+        area += (uint32_t)(c1 - c0);
+      }
+      if (area == 0) break;
+    }
+    a.splats[2 * e + 0] = s0;
+    a.splats[2 * e + 1] = s1;
     a.rects[e] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
     a.radii[e] = (int32_t)rad;
     const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
@@ -453,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
 
 }  // namespace
 
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* ws, const Layout& L,
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, char* ws, const Layout& L,
                              hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   PreArgs a;
@@ -465,6 +479,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, char* w
   a.n = (uint32_t)g.n;
   a.sh_degree = g.sh_degree;
   a.batch = b;
+  a.tight = tight ? 1 : 0;
   a.block_tiles = reinterpret_cast<uint32_t*>(ws + L.block_tiles);
   a.splats = reinterpret_cast<float4*>(ws + L.splats);
   a.colors = reinterpret_cast<float4*>(ws + L.colors);

@@ -20,6 +20,7 @@
 // memory (the visible count): grids are sized for the host-side bound and
 // blocks past the device count do nothing.
 #include "fgs_internal.hpp"
+#include "reach.hpp"
 
 namespace fgs {
 namespace {
@@ -65,7 +66,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* smem /* kW
 // ---- scan inputs -----------------------------------------------------------
 struct ScanIn {
   const uint32_t* a;  // values, flags, or rect x0|y0 plane
-  const uint32_t* b;  // rect x1|y1 plane (kScanRectArea)
+  const uint32_t* b;  // rect x1|y1 plane (kScanRectArea), or the gathered values (kScanGather)
 };
 
 template <int MODE>
@@ -75,6 +76,7 @@ __device__ inline uint32_t scan_value(const ScanIn& in, uint32_t idx) {
     const uint32_t a = in.a[idx], b = in.b[idx];
     return ((b & 0xFFFFu) - (a & 0xFFFFu)) * ((b >> 16) - (a >> 16));
   }
+  if (MODE == kScanGather) return in.b[in.a[idx]];
   return in.a[idx];
 }
 
@@ -146,6 +148,8 @@ __device__ inline void load16(const ScanIn& in, uint32_t idx, uint32_t count, ui
           vals[4 * q + r] = ((bb & 0xFFFFu) - (aa & 0xFFFFu)) * ((bb >> 16) - (aa >> 16));
         }
       }
+    } else if (MODE == kScanGather) {
+      for (int k = 0; k < 16; ++k) vals[k] = in.b[av[k]];
     } else {
       for (int k = 0; k < 16; ++k) vals[k] = MODE == kScanFlag ? (av[k] != 0u ? 1u : 0u) : av[k];
     }
@@ -428,7 +432,6 @@ __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4
 // exactly that sort's first histogram.
 constexpr int kDupItems = kBlock * kIptPayload1;  // 4096
 
-__device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
 
 struct TileMap {
   int32_t count;                     // views
@@ -460,11 +463,40 @@ __device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32
   return lo;
 }
 
+__device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
+
+// Per depth-ordered visible entry: reach parameters and kept-tile count,
+// contiguous in j, so that the duplication reads one record per Gaussian
+// with no dependent gather.
+__global__ __launch_bounds__(kBlock) void reach_kernel(const uint32_t* ids, const float4* splats, const uint32_t* tiles,
+                                                       uint32_t V, int tight, float4* reach, uint32_t* counts) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= V) return;
+  const uint32_t g = ids[j];
+  SplatReach r;
+  if (tight) {
+    r = splat_reach(splats[2 * (size_t)g], splats[2 * (size_t)g + 1]);
+  } else {
+    r.mx = r.my = r.Pa = r.da = r.beta = r.ry = r.ds = 0.0f;
+    r.kind = 2;
+  }
+  float4 p0, p1;
+  pack_reach(r, p0, p1);
+  reach[2 * (size_t)j] = p0;
+  reach[2 * (size_t)j + 1] = p1;
+  counts[j] = tiles[g];
+}
+
+// Each thread emits 16 consecutive slots: it finds the Gaussian of its first
+// slot in the LDS copy of the offsets, then walks that Gaussian's kept tiles
+// row by row (the columns reach_row keeps, or the whole rect) and moves on to
+// the next Gaussian at its offset.  The slots are staged in LDS and written
+// coalesced.
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
                                                            const uint32_t* offsets, const uint32_t* d_count,
                                                            uint32_t max_count, uint32_t K, TileMap map,
-                                                           int digit_bits, uint32_t nblocks, uint32_t* hist,
-                                                           uint32_t* out_keys, uint32_t* out_vals) {
+                                                           int digit_bits, uint32_t nblocks, const float4* reach,
+                                                           uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals) {
   __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
   __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
   __shared__ uint32_t s_off[kDupItems];  // offsets of the Gaussians that own this block's slots
@@ -498,37 +530,54 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, 
       if (s_off[mid] <= o) lo = mid; else hi = mid;
     }
     uint32_t local = lo;
-    uint32_t j = first + local;
     uint32_t next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-    uint32_t a = rx[j], b = ry[j], g = ids[j];
-    uint32_t x0 = a & 0xFFFFu, y0 = a >> 16, w = (b & 0xFFFFu) - x0;
-    uint32_t tbase, tiles_x;
-    view_of(map, g, tbase, tiles_x);
-    const uint32_t lcl = o - s_off[local];
-    uint32_t row = lcl / w, col = lcl - row * w;
+    // the current Gaussian's kept tiles: row y, columns [c0, c1), at col
+    uint32_t g = 0, tbase = 0, tiles_x = 0;
+    int x0 = 0, x1 = 0, y = 0, y1 = 0, c0 = 0, c1 = 0, col = 0;
+    SplatReach rr;
+    auto enter = [&](uint32_t jj, uint32_t skip) {  // Gaussian jj, from its skip-th kept tile
+      const uint32_t a = rx[jj], b = ry[jj];
+      g = ids[jj];
+      x0 = (int)(a & 0xFFFFu);
+      y = (int)(a >> 16);
+      x1 = (int)(b & 0xFFFFu);
+      y1 = (int)(b >> 16);
+      view_of(map, g, tbase, tiles_x);
+      rr = unpack_reach(reach[2 * (size_t)jj], reach[2 * (size_t)jj + 1]);
+      if (rr.kind == 1) {
+        reach_row(rr, y, x0, x1, c0, c1);
+        while (skip >= (uint32_t)(c1 - c0) && y + 1 < y1) {
+          skip -= (uint32_t)(c1 - c0);
+          reach_row(rr, ++y, x0, x1, c0, c1);
+        }
+      } else {  // the whole rect (a kind-0 entry is never visible)
+        const uint32_t w = (uint32_t)(x1 - x0);
+        y += (int)(skip / w);
+        skip -= (skip / w) * w;
+        c0 = x0;
+        c1 = x1;
+      }
+      col = c0 + (int)skip;
+    };
+    enter(first + local, o - s_off[local]);
     for (int k = 0; k < kIptPayload1 && o < o_end; ++k, ++o) {
       if (o == next) {
         ++local;
-        ++j;
         next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-        a = rx[j];
-        b = ry[j];
-        g = ids[j];
-        x0 = a & 0xFFFFu;
-        y0 = a >> 16;
-        w = (b & 0xFFFFu) - x0;
-        view_of(map, g, tbase, tiles_x);
-        row = 0;
-        col = 0;
+        enter(first + local, 0u);
       }
-      const uint32_t key = tbase + (y0 + row) * tiles_x + (x0 + col);
+      const uint32_t key = tbase + (uint32_t)y * tiles_x + (uint32_t)col;
       const uint32_t e = o - o_begin;
       s_keys[pad_index(e)] = key;
       s_vals[pad_index(e)] = g;
       atomicAdd(&s_hist[key & dmask], 1u);
-      if (++col == w) {
-        col = 0;
-        ++row;
+      if (++col == c1) {  // next row with a kept tile (bounded by the rect)
+        const bool rows = rr.kind == 1;
+        do {
+          ++y;
+          if (rows) reach_row(rr, y, x0, x1, c0, c1);
+        } while (rows && c1 == c0 && y + 1 < y1);
+        col = c0;
       }
     }
   }
@@ -647,6 +696,10 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
       hipLaunchKernelGGL(scan_partials_kernel<kScanRectArea>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
                          (uint32_t)max_count, partials);
       break;
+    case kScanGather:
+      hipLaunchKernelGGL(scan_partials_kernel<kScanGather>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
+                         (uint32_t)max_count, partials);
+      break;
     default:
       hipLaunchKernelGGL(scan_partials_kernel<kScanPlain>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
                          (uint32_t)max_count, partials);
@@ -663,6 +716,7 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
   switch (mode) {
     case kScanFlag: FGS_APPLY(kScanFlag) break;
     case kScanRectArea: FGS_APPLY(kScanRectArea) break;
+    case kScanGather: FGS_APPLY(kScanGather) break;
     default: FGS_APPLY(kScanPlain) break;
   }
 #undef FGS_APPLY
@@ -698,9 +752,19 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
   return hipGetLastError();
 }
 
+hipError_t launch_reach(const uint32_t* ids, const float4* splats, const uint32_t* tiles, int64_t V, bool tight,
+                        float4* reach, uint32_t* counts, hipStream_t s) {
+  if (V <= 0) return hipSuccess;
+  ProfScope prof(s, kKReach);
+  hipLaunchKernelGGL(reach_kernel, dim3((unsigned)ceil_div(V, kBlock)), dim3(kBlock), 0, s, ids, splats, tiles,
+                     (uint32_t)V, tight ? 1 : 0, reach, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
                             const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s) {
+                            int tile_bits, const float4* reach, uint32_t* hist, uint32_t* out_keys,
+                            uint32_t* out_vals, hipStream_t s) {
   if (max_count <= 0 || K <= 0) return hipSuccess;
   const int passes = radix_passes(tile_bits);
   const int first_bits = passes > 0 ? (tile_bits + passes - 1) / passes : 0;  // as launch_radix_sort
@@ -714,7 +778,7 @@ hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint3
     map.tiles_x[v] = v < b.count ? (uint32_t)b.v[v].tiles_x : 1u;
   }
   hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, ids, rx, ry, offsets, d_count,
-                     (uint32_t)max_count, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
+                     (uint32_t)max_count, (uint32_t)K, map, first_bits, nb, reach, hist, out_keys, out_vals);
   return hipGetLastError();
 }
 

@@ -87,8 +87,10 @@ def _stream_handle(device) -> int:
 
 def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg=(0.0, 0.0, 0.0),
                    workspace: Workspace | None = None, save_pixel_state: bool = False, out: torch.Tensor | None = None,
-                   k_hint: int | None = None):
-    """Render one view.  Returns (image [3, H, W], workspace, K)."""
+                   k_hint: int | None = None, binning: str = "tight"):
+    """Render one view.  Returns (image [3, H, W], workspace, K).  binning
+    "rect" lists every tile of each Gaussian's 3-sigma rectangle, "tight"
+    only the tiles its alpha >= 1/255 ellipse reaches (same image)."""
     g = gaussians_struct(means, scales, quats, opacities, sh, sh_degree)
     c = camera_struct(cam)
     p = pose_struct(pose)
@@ -99,7 +101,7 @@ def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, ca
     if ws.buf is None:
         kcap = k_hint if k_hint is not None else 8 * g.n + 65536
         ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, kcap))
-    flags = FGS_SAVE_PIXEL_STATE if save_pixel_state else 0
+    flags = (FGS_SAVE_PIXEL_STATE if save_pixel_state else 0) | (L.FGS_RECT_BINNING if binning == "rect" else 0)
     for _ in range(3):
         rc, K = L.fgs_render_forward(g, p, c, bg, flags, ws.ptr, ws.nbytes, out.data_ptr(), _stream_handle(dev))
         if rc == L.FGS_ERR_WORKSPACE and K >= 0:

@@ -27,11 +27,25 @@ def _params(gs):
     return gs["means"], gs["scales"], gs["quats"], gs["opacities"], gs["sh"], gs["sh_degree"]
 
 
-def gpu_forward(gs, pose, cam, bg=(0.0, 0.0, 0.0), save_pixel_state=False, workspace=None, k_hint=None):
+def gpu_forward(gs, pose, cam, bg=(0.0, 0.0, 0.0), save_pixel_state=False, workspace=None, k_hint=None,
+                binning="tight"):
     img, ws, K = R.render_forward(*_params(gs), pose, cam, bg, workspace=workspace,
-                                  save_pixel_state=save_pixel_state, k_hint=k_hint)
+                                  save_pixel_state=save_pixel_state, k_hint=k_hint, binning=binning)
     torch.cuda.synchronize()
     return img, ws, K
+
+
+def check_k(K, pre, bins):
+    """The intersection count equals the oracle's, except for Gaussians the
+    oracle marks as ties (a binning decision at its margin), whose kept tiles
+    may differ -- by at most their rects."""
+    tie = pre["tie"] > 0
+    if not tie.any():
+        assert K == bins["K"], (K, bins["K"])
+        return
+    r = pre["rect"][tie].astype(np.int64)
+    slack = int(((r[:, 2] - r[:, 0]) * (r[:, 3] - r[:, 1])).sum())
+    assert abs(K - bins["K"]) <= slack, (K, bins["K"], slack)
 
 
 def read_state(ws, n, cam, K):

@@ -17,18 +17,18 @@ import oracle  # noqa: E402
 from paper_2409_04751_amd import _lib as L  # noqa: E402
 from paper_2409_04751_amd import synth  # noqa: E402
 
-from parity import (compare_preprocess, compare_tile_lists, gpu_forward, image_tolerance_check,  # noqa: E402
+from parity import (check_k, compare_preprocess, compare_tile_lists, gpu_forward, image_tolerance_check,  # noqa: E402
                     read_state, to_gpu)
 
 pytestmark = pytest.mark.gpu
 
 
-def _full_check(scene, pose, cam, bg=(0.0, 0.0, 0.0), save=False):
-    print(f"case n={scene.n} cam={cam.width}x{cam.height} bg={bg}", flush=True)
+def _full_check(scene, pose, cam, bg=(0.0, 0.0, 0.0), save=False, binning="tight"):
+    print(f"case n={scene.n} cam={cam.width}x{cam.height} bg={bg} binning={binning}", flush=True)
     gs = to_gpu(scene)
-    img, ws, K = gpu_forward(gs, pose, cam, bg, save_pixel_state=save)
-    ora = oracle.render(scene, pose, cam, bg)
-    assert K == ora["bins"]["K"] or (ora["pre"]["tie"] > 0).any()
+    img, ws, K = gpu_forward(gs, pose, cam, bg, save_pixel_state=save, binning=binning)
+    ora = oracle.render(scene, pose, cam, bg, binning=binning)
+    check_k(K, ora["pre"], ora["bins"])
     st = read_state(ws, scene.n, cam, K)
     compare_preprocess(st, ora["pre"])
     compare_tile_lists(st, ora["bins"], ora["pre"])
@@ -122,7 +122,9 @@ def test_workspace_too_small_then_grown():
     out = torch.empty((3, cam.height, cam.width), device="cuda")
     rc, K = L.fgs_render_forward(g, R.pose_struct(poses[0]), R.camera_struct(cam), (0, 0, 0), 0, ws.ptr, ws.nbytes,
                                  out.data_ptr(), R._stream_handle(out.device))
-    assert rc == L.FGS_ERR_WORKSPACE and K == oracle.render(scene, poses[0], cam)["bins"]["K"]
+    ora = oracle.render(scene, poses[0], cam)
+    assert rc == L.FGS_ERR_WORKSPACE
+    check_k(K, ora["pre"], ora["bins"])
     ws.ensure(L.fgs_workspace_bytes(scene.n, cam.width, cam.height, K))
     rc, K2 = L.fgs_render_forward(g, R.pose_struct(poses[0]), R.camera_struct(cam), (0, 0, 0), 0, ws.ptr, ws.nbytes,
                                   out.data_ptr(), R._stream_handle(out.device))
@@ -142,3 +144,17 @@ def test_forward_is_bit_deterministic():
     assert torch.equal(a, b)
     np.testing.assert_array_equal(sa["tile_ids"], sb["tile_ids"])
     np.testing.assert_array_equal(sa["ranges"], sb["ranges"])
+
+
+def test_rect_binning_matches_oracle_and_tight_image():
+    """Vanilla 3-sigma-rect lists (FGS_RECT_BINNING) against the oracle's rect
+    binning, and the tight lists' image equal to it bit for bit: binning only
+    drops pairs that are never blended."""
+    scene = synth.room_scene(60_000, 3, 0.02, 3)
+    _, cam, poses = synth.workload("room3m_2k")
+    cam = synth.fisheye_camera(320, 256, 200.0)
+    img_r, ws_r, K_r, st_r, ora_r = _full_check(scene, poses[1], cam, binning="rect")
+    gs = to_gpu(scene)
+    img_t, ws_t, K_t = gpu_forward(gs, poses[1], cam, binning="tight")
+    assert K_t < K_r
+    assert torch.equal(img_t, img_r)

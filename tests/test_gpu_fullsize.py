@@ -19,7 +19,7 @@ import oracle  # noqa: E402
 from paper_2409_04751_amd import render as R  # noqa: E402
 from paper_2409_04751_amd import synth  # noqa: E402
 
-from parity import (compare_preprocess, compare_tile_lists, gpu_forward, gradient_parity,  # noqa: E402
+from parity import (check_k, compare_preprocess, compare_tile_lists, gpu_forward, gradient_parity,  # noqa: E402
                     image_tolerance_check, masked_upstream, read_state, to_gpu)
 
 pytestmark = pytest.mark.gpu
@@ -68,7 +68,7 @@ def test_room3m_2048_200deg_pose0_and_2k_crop(scene3m):
     img, ws, K = gpu_forward(gs, pose, cam)
     pre = oracle.preprocess(scene3m, pose, cam)
     bins = oracle.bin_and_sort(pre, cam)
-    assert K == bins["K"]
+    check_k(K, pre, bins)
     st = read_state(ws, scene3m.n, cam, K)
     compare_preprocess(st, pre)
     compare_tile_lists(st, bins, pre)

@@ -181,3 +181,78 @@ def test_transmittance_and_background():
     # pixels no Gaussian reaches keep T = 1 and the background
     untouched = a["last"] == 0
     assert np.all(T[untouched] == 1.0)
+
+
+def _pairs(bins, gx):
+    tile = (bins["keys"] >> np.uint64(32)).astype(np.int64)
+    return set(zip(tile.tolist(), bins["vals"].astype(np.int64).tolist()))
+
+
+def _reaches(pre, g, tx, ty, cam):
+    """Brute force: does Gaussian g reach any pixel centre of tile (tx, ty)
+    with alpha >= 1/255 (the blend's skip rule)?"""
+    xs = np.arange(tx * 16, min(tx * 16 + 16, cam.width), dtype=np.float64)
+    ys = np.arange(ty * 16, min(ty * 16 + 16, cam.height), dtype=np.float64)
+    u = xs[None, :] - pre["mu_p"][g, 0]
+    v = ys[:, None] - pre["mu_p"][g, 1]
+    A, B, C = pre["conic"][g]
+    q = -0.5 * (A * u * u + C * v * v) - B * u * v
+    return bool(np.any(pre["opacity"][g] * np.exp(q) >= 1.0 / 255.0))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tight_binning_drops_only_unreached_tiles(seed):
+    """Tight binning keeps a subset of the 3-sigma rect pairs; the image is
+    bit-identical to rect binning, and brute force over every pixel of
+    every dropped (Gaussian, tile) pair finds no pixel the Gaussian would be
+    blended into."""
+    cam = synth.fisheye_camera(64, 48, 190.0)
+    scene = _tiny_scene(seed)
+    bg = (0.1, 0.2, 0.3)
+    tight = oracle.render(scene, synth.identity_pose(), cam, bg, binning="tight")
+    rect = oracle.render(scene, synth.identity_pose(), cam, bg, binning="rect")
+    np.testing.assert_array_equal(tight["image"], rect["image"])
+    kt, kr = _pairs(tight["bins"], cam.tiles_x), _pairs(rect["bins"], cam.tiles_x)
+    assert kt <= kr and len(kt) < len(kr)
+    for tile, g in kr - kt:
+        assert not _reaches(rect["pre"], g, tile % cam.tiles_x, tile // cam.tiles_x, cam), (tile, g)
+    # and every kept tile of a Gaussian lies in one interval per tile row
+    for g in np.nonzero(tight["pre"]["visible"])[0][:200]:
+        tiles = sorted(t for t, gg in kt if gg == g)
+        rows = {}
+        for t in tiles:
+            rows.setdefault(t // cam.tiles_x, []).append(t % cam.tiles_x)
+        for cols in rows.values():
+            assert cols == list(range(cols[0], cols[0] + len(cols)))
+
+
+def test_tight_binning_thin_diagonal_splat():
+    """A long thin Gaussian at 45 degrees: its 3-sigma square covers a block
+    of tiles, the kept tiles follow the diagonal, and the image is the same."""
+    cam = synth.fisheye_camera(256, 256, 180.0)
+    c, s = math.cos(math.pi / 8), math.sin(math.pi / 8)  # 45 deg about the optical axis
+    sc = _single((0.0, 0.0, 3.0), 0.0, 0.9, (0.8, 0.5, 0.2), quat=(c, 0.0, 0.0, s))
+    sc.scales[:, 0] = (0.6, 0.01, 0.01)
+    tight = oracle.render(sc, synth.identity_pose(), cam, binning="tight")
+    rect = oracle.render(sc, synth.identity_pose(), cam, binning="rect")
+    np.testing.assert_array_equal(tight["image"], rect["image"])
+    assert tight["bins"]["K"] * 2 < rect["bins"]["K"]
+    kt = _pairs(tight["bins"], cam.tiles_x)
+    for tile, g in _pairs(rect["bins"], cam.tiles_x) - kt:
+        assert not _reaches(rect["pre"], g, tile % cam.tiles_x, tile // cam.tiles_x, cam)
+    # a kept tile on the diagonal through the centre, none far off it
+    gx = cam.tiles_x
+    cols = {t % gx for t, _ in kt if t // gx == 8}
+    assert cols and max(cols) - min(cols) <= 4
+
+
+def test_tight_binning_drops_faint_gaussians():
+    """Opacity below 1/255: no pixel is ever blended, so tight binning keeps
+    no tile and the Gaussian is not visible; with opacity just above, it is."""
+    cam = synth.fisheye_camera(64, 64, 180.0)
+    faint = _single((0.0, 0.0, 2.0), 0.05, 0.9 / 255.0, (1.0, 1.0, 1.0))
+    pre = oracle.preprocess(faint, synth.identity_pose(), cam, "tight")
+    assert pre["visible"][0] == 0 and pre["tiles"][0] == 0
+    assert oracle.preprocess(faint, synth.identity_pose(), cam, "rect")["visible"][0] == 1
+    bright = _single((0.0, 0.0, 2.0), 0.05, 2.0 / 255.0, (1.0, 1.0, 1.0))
+    assert oracle.preprocess(bright, synth.identity_pose(), cam, "tight")["visible"][0] == 1

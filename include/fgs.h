@@ -46,7 +46,21 @@ extern "C" {
 #define FGS_ERR_HIP (-3)       /* HIP runtime error; text in fgs_last_error() */
 #define FGS_ERR_OVERFLOW (-4)  /* more than 2^31 - 1 intersections or Gaussians */
 
-#define FGS_MODEL_EQUIDISTANT 0 /* r_d = f theta (Sec. 3.2) */
+/* Camera models (fgs_camera.model).  Radial models place a point at
+ * incidence theta = atan2(|(x_c, y_c)|, z_c) on its azimuth's ray at
+ * distance f r(theta) from (c_x, c_y); Sec. 3.2 lists the four fisheye
+ * projections, and the pinhole is the textbook r = tan theta.  The panorama
+ * is the equirectangular projection of Sec. 5.4 ("Extension to Other
+ * Cameras Models"): x_p = c_x + f_x atan2(x_c, z_c),
+ * y_p = c_y + f_y atan2(y_c, |(x_c, z_c)|); the paper's image of width w and
+ * height h has f_x = w / (2 pi), f_y = h / pi, c = (w/2, h/2).  Splats are
+ * not wrapped across the panorama's left/right seam. */
+#define FGS_MODEL_EQUIDISTANT 0   /* r = theta (Sec. 3.2) */
+#define FGS_MODEL_PINHOLE 1       /* r = tan theta */
+#define FGS_MODEL_PANORAMA 2      /* equirectangular (Sec. 5.4) */
+#define FGS_MODEL_EQUISOLID 3     /* r = 2 sin(theta / 2) */
+#define FGS_MODEL_ORTHOGRAPHIC 4  /* r = sin theta */
+#define FGS_MODEL_STEREOGRAPHIC 5 /* r = 2 tan(theta / 2) */
 
 #define FGS_MAX_BATCH 8 /* views per fgs_render_forward_batch call */
 
@@ -61,9 +75,11 @@ extern "C" {
                                    gradients are the same either way */
 
 /* Intrinsics of one view (Sec. 3.2: f_x, f_y, c_x, c_y).  Gaussians are culled
- * when |mu_c| <= near_dist or when the incidence angle theta exceeds
- * theta_max (radians, < pi: the splat of a Gaussian near the rear axis is
- * unbounded). */
+ * when |mu_c| <= near_dist or when the model's cull angle exceeds theta_max
+ * (radians): for radial models the incidence angle theta, with theta_max < pi
+ * (< pi/2 for the pinhole and orthographic models), since the splat of a
+ * Gaussian near the rear axis is unbounded; for the panorama the absolute
+ * latitude, with theta_max < pi/2, since its J is unbounded at the poles. */
 typedef struct fgs_camera {
   int32_t width, height;
   double fx, fy, cx, cy;

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class _Cam(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_double),
                 ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
-                ("near_dist", ctypes.c_double), ("theta_max", ctypes.c_double)]
+                ("near_dist", ctypes.c_double), ("theta_max", ctypes.c_double), ("model", ctypes.c_int32)]
 
 
 class _Tol(ctypes.Structure):
@@ -64,7 +64,7 @@ def _p(a: np.ndarray):
 
 
 def _cam(cam) -> _Cam:
-    return _Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near, cam.theta_max)
+    return _Cam(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near, cam.theta_max, cam.model)
 
 
 def _f32(a) -> np.ndarray:
@@ -104,6 +104,36 @@ def jacobian_grad(p, fx, fy) -> np.ndarray:
     dJ = np.zeros(18)
     lib().orc_jacobian_grad(_p(p), ctypes.c_double(fx), ctypes.c_double(fy), _p(dJ))
     return dJ.reshape(3, 2, 3)
+
+
+def project_model(model: int, p, fx, fy, cx, cy) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(2)
+    lib().orc_project_model(ctypes.c_int(model), _p(p), ctypes.c_double(fx), ctypes.c_double(fy),
+                            ctypes.c_double(cx), ctypes.c_double(cy), _p(out))
+    return out
+
+
+def jacobian_model(model: int, p, fx, fy) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    J = np.zeros(6)
+    lib().orc_jacobian_model(ctypes.c_int(model), _p(p), ctypes.c_double(fx), ctypes.c_double(fy), _p(J))
+    return J.reshape(2, 3)
+
+
+def jacobian_grad_model(model: int, p, fx, fy) -> np.ndarray:
+    """[3, 2, 3]: d J / d(x_c, y_c, z_c) for camera model `model`."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    dJ = np.zeros(18)
+    lib().orc_jacobian_grad_model(ctypes.c_int(model), _p(p), ctypes.c_double(fx), ctypes.c_double(fy), _p(dJ))
+    return dJ.reshape(3, 2, 3)
+
+
+def cull_angle(model: int, p) -> float:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    f = lib().orc_cull_angle
+    f.restype = ctypes.c_double
+    return float(f(ctypes.c_int(model), _p(p)))
 
 
 def sh_basis(degree: int, d) -> np.ndarray:

@@ -19,6 +19,14 @@
  *                                      theta terms; read as f times the whole entry)
  *   Sec. 4.3                          dJ/dx_c, dJ/dy_c, dJ/dz_c via S1..S8 (entry
  *                                      [0][2] of dJ/dy_c printed with f_y; read as f_x)
+ *   Sec. 3.2 (model list), Sec. 5.4   other camera models: the equisolid-angle,
+ *                                      orthographic and stereographic fisheyes Sec. 3.2
+ *                                      names, the pinhole, and the panorama projection of
+ *                                      Sec. 5.4 "Extension to Other Cameras Models"; their
+ *                                      J and dJ are the first and second derivatives of
+ *                                      the projection, taken by forward-mode
+ *                                      differentiation (the paper prints only the
+ *                                      panorama's J)
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   theta = atan2(l_z, z_c) (the printed arctan(l_z/z_c) only covers z_c > 0);
@@ -44,7 +52,18 @@ typedef struct {
   int32_t width, height;
   double fx, fy, cx, cy;
   double near_dist, theta_max;
+  int32_t model;
 } orc_camera;
+
+/* Camera models.  Radial models put a point at incidence theta on the ray of
+ * its azimuth at distance f r(theta) from the principal point:
+ *   equidistant r = theta (Sec. 3.2), pinhole r = tan theta,
+ *   equisolid angle r = 2 sin(theta / 2), orthographic r = sin theta,
+ *   stereographic r = 2 tan(theta / 2)  (the fisheye models Sec. 3.2 lists).
+ * The panorama (Sec. 5.4) maps longitude atan2(x_c, z_c) and latitude
+ * atan2(y_c, |(x_c, z_c)|) linearly to x and y. */
+enum { MODEL_EQUIDISTANT = 0, MODEL_PINHOLE = 1, MODEL_PANORAMA = 2, MODEL_EQUISOLID = 3, MODEL_ORTHOGRAPHIC = 4,
+       MODEL_STEREOGRAPHIC = 5 };
 
 /* ------------------------------------------------------------------------ */
 /* Forward-mode dual numbers, used for the parts of the backward that the     */
@@ -175,6 +194,128 @@ void orc_jacobian_grad(const double p[3], double fx, double fy, double dJ[18]) {
   /* d/dz_c */
   dJ[12] = fx * S5 / l22;          dJ[13] = 2 * fx * x * y / l22; dJ[14] = 2 * fx * x * z / l22;
   dJ[15] = 2 * fy * x * y / l22;   dJ[16] = fy * S6 / l22;        dJ[17] = 2 * fy * y * z / l22;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Other camera models: projection, J = d mu_p / d mu_c and dJ / d mu_c as    */
+/* the value, gradient and Hessian of each pixel coordinate, carried through  */
+/* the projection's formula by second-order forward-mode differentiation:     */
+/* for a value v with gradient g and Hessian H in (x_c, y_c, z_c),            */
+/*   (a b)'' = a'' b + a' b'^T + b' a'^T + a b'',                               */
+/*   f(a)'' = f'(a) a'' + f''(a) a' a'^T.                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct { double v, g[3], h[9]; } hd;
+
+static hd hd_const(double v) { hd r; memset(&r, 0, sizeof r); r.v = v; return r; }
+static hd hd_var(double v, int k) { hd r = hd_const(v); r.g[k] = 1.0; return r; }
+static hd hd_add(hd a, hd b) {
+  hd r; r.v = a.v + b.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] + b.g[k];
+  for (int k = 0; k < 9; ++k) r.h[k] = a.h[k] + b.h[k];
+  return r;
+}
+static hd hd_scale(hd a, double s) {
+  hd r; r.v = a.v * s;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * s;
+  for (int k = 0; k < 9; ++k) r.h[k] = a.h[k] * s;
+  return r;
+}
+static hd hd_mul(hd a, hd b) {
+  hd r; r.v = a.v * b.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * b.v + a.v * b.g[k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      r.h[i * 3 + j] = a.h[i * 3 + j] * b.v + a.g[i] * b.g[j] + b.g[i] * a.g[j] + a.v * b.h[i * 3 + j];
+  return r;
+}
+/* f(a) given f(a.v), f'(a.v), f''(a.v) */
+static hd hd_chain(hd a, double f0, double f1, double f2) {
+  hd r; r.v = f0;
+  for (int k = 0; k < 3; ++k) r.g[k] = f1 * a.g[k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.h[i * 3 + j] = f1 * a.h[i * 3 + j] + f2 * a.g[i] * a.g[j];
+  return r;
+}
+static hd hd_recip(hd a) { return hd_chain(a, 1.0 / a.v, -1.0 / (a.v * a.v), 2.0 / (a.v * a.v * a.v)); }
+static hd hd_sqrt(hd a) {
+  double s = sqrt(a.v);
+  return hd_chain(a, s, 0.5 / s, -0.25 / (s * a.v));
+}
+static hd hd_sin(hd a) { return hd_chain(a, sin(a.v), cos(a.v), -sin(a.v)); }
+static hd hd_tan(hd a) {
+  double t = tan(a.v), sec2 = 1.0 + t * t;
+  return hd_chain(a, t, sec2, 2.0 * sec2 * t);
+}
+/* atan2(a, b): partials b / s and -a / s with s = a^2 + b^2; second partials
+ * -2ab / s^2 (aa), 2ab / s^2 (bb), (a^2 - b^2) / s^2 (ab). */
+static hd hd_atan2(hd a, hd b) {
+  double s = a.v * a.v + b.v * b.v, s2 = s * s;
+  double fa = b.v / s, fb = -a.v / s;
+  double faa = -2.0 * a.v * b.v / s2, fbb = 2.0 * a.v * b.v / s2, fab = (a.v * a.v - b.v * b.v) / s2;
+  hd r; r.v = atan2(a.v, b.v);
+  for (int k = 0; k < 3; ++k) r.g[k] = fa * a.g[k] + fb * b.g[k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      r.h[i * 3 + j] = fa * a.h[i * 3 + j] + fb * b.h[i * 3 + j] + faa * a.g[i] * a.g[j] + fbb * b.g[i] * b.g[j] +
+                       fab * (a.g[i] * b.g[j] + b.g[i] * a.g[j]);
+  return r;
+}
+
+/* The pixel coordinates of a camera-space point as hd values. */
+static void project_hd(int model, const double p[3], double fx, double fy, double cx, double cy, hd out[2]) {
+  hd x = hd_var(p[0], 0), y = hd_var(p[1], 1), z = hd_var(p[2], 2);
+  if (model == MODEL_PANORAMA) {
+    hd rho = hd_sqrt(hd_add(hd_mul(x, x), hd_mul(z, z)));
+    out[0] = hd_add(hd_const(cx), hd_scale(hd_atan2(x, z), fx));
+    out[1] = hd_add(hd_const(cy), hd_scale(hd_atan2(y, rho), fy));
+    return;
+  }
+  hd lz = hd_sqrt(hd_add(hd_mul(x, x), hd_mul(y, y)));
+  hd th = hd_atan2(lz, z), r;
+  switch (model) {
+    case MODEL_PINHOLE: r = hd_tan(th); break;
+    case MODEL_EQUISOLID: r = hd_scale(hd_sin(hd_scale(th, 0.5)), 2.0); break;
+    case MODEL_ORTHOGRAPHIC: r = hd_sin(th); break;
+    case MODEL_STEREOGRAPHIC: r = hd_scale(hd_tan(hd_scale(th, 0.5)), 2.0); break;
+    default: r = th; break;
+  }
+  hd k = hd_mul(r, hd_recip(lz)); /* r(theta) / l_z */
+  out[0] = hd_add(hd_const(cx), hd_scale(hd_mul(k, x), fx));
+  out[1] = hd_add(hd_const(cy), hd_scale(hd_mul(k, y), fy));
+}
+
+/* The angle each model culls on: the incidence theta for radial models, the
+ * absolute latitude for the panorama (its poles are where J is unbounded). */
+double orc_cull_angle(int model, const double p[3]) {
+  if (model == MODEL_PANORAMA) return fabs(atan2(p[1], sqrt(p[0] * p[0] + p[2] * p[2])));
+  return atan2(sqrt(p[0] * p[0] + p[1] * p[1]), p[2]);
+}
+
+/* Model dispatch: the equidistant model keeps the paper's closed forms
+ * (Sec. 3.2, 4.2, 4.3); the others use the hd derivatives.  Radial models
+ * other than the equidistant are not evaluated exactly on the optical axis
+ * (l_z = 0), where the hd chain divides by zero. */
+void orc_project_model(int model, const double p[3], double fx, double fy, double cx, double cy, double out[2]) {
+  if (model == MODEL_EQUIDISTANT) { orc_project(p, fx, fy, cx, cy, out); return; }
+  hd m[2];
+  project_hd(model, p, fx, fy, cx, cy, m);
+  out[0] = m[0].v;
+  out[1] = m[1].v;
+}
+void orc_jacobian_model(int model, const double p[3], double fx, double fy, double J[6]) {
+  if (model == MODEL_EQUIDISTANT) { orc_jacobian(p, fx, fy, J); return; }
+  hd m[2];
+  project_hd(model, p, fx, fy, 0.0, 0.0, m);
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k) J[r * 3 + k] = m[r].g[k];
+}
+void orc_jacobian_grad_model(int model, const double p[3], double fx, double fy, double dJ[18]) {
+  if (model == MODEL_EQUIDISTANT) { orc_jacobian_grad(p, fx, fy, dJ); return; }
+  hd m[2];
+  project_hd(model, p, fx, fy, 0.0, 0.0, m);
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) dJ[c * 6 + r * 3 + k] = m[r].h[k * 3 + c];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -314,14 +455,13 @@ static int geometry(int64_t i, int64_t n, const double* means, const double* sca
     g->pc[r] = ((Rw[r * 3 + 0] * mf[0] + Rw[r * 3 + 1] * mf[1]) + Rw[r * 3 + 2] * mf[2]) + tw[r];
   double dist = sqrt((g->pc[0] * g->pc[0] + g->pc[1] * g->pc[1]) + g->pc[2] * g->pc[2]);
   if (!(dist > cam->near_dist)) return 0;
-  double lz = sqrt(g->pc[0] * g->pc[0] + g->pc[1] * g->pc[1]);
-  g->theta = atan2(lz, g->pc[2]);
+  g->theta = orc_cull_angle(cam->model, g->pc);
   if (!(g->theta <= cam->theta_max)) return 0;
-  orc_project(g->pc, cam->fx, cam->fy, cam->cx, cam->cy, g->mu_p);
+  orc_project_model(cam->model, g->pc, cam->fx, cam->fy, cam->cx, cam->cy, g->mu_p);
   double s[3] = {sf[0], sf[1], sf[2]}, q[4] = {qf[0], qf[1], qf[2], qf[3]};
   cov3d_dual(s, q, Sig);
   for (int k = 0; k < 9; ++k) g->Sig[k] = Sig[k].v;
-  orc_jacobian(g->pc, cam->fx, cam->fy, g->J);
+  orc_jacobian_model(cam->model, g->pc, cam->fx, cam->fy, g->J);
   /* T = J W */
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c) {
@@ -859,7 +999,7 @@ void orc_preprocess_backward(int64_t n, const double* means, const double* scale
       }
     /* dL/dmu_c: mean projection + Jacobian's dependence on mu_c */
     double dJ[18];
-    orc_jacobian_grad(g.pc, cam->fx, cam->fy, dJ);
+    orc_jacobian_grad_model(cam->model, g.pc, cam->fx, cam->fy, dJ);
     double gmc[3];
     for (int c = 0; c < 3; ++c) {
       double acc = g.J[0 * 3 + c] * g_mu_p[i * 2 + 0] + g.J[1 * 3 + c] * g_mu_p[i * 2 + 1];

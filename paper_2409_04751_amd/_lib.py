@@ -18,6 +18,11 @@ FGS_ERR_WORKSPACE = -2
 FGS_ERR_HIP = -3
 FGS_ERR_OVERFLOW = -4
 FGS_MODEL_EQUIDISTANT = 0
+FGS_MODEL_PINHOLE = 1
+FGS_MODEL_PANORAMA = 2
+FGS_MODEL_EQUISOLID = 3
+FGS_MODEL_ORTHOGRAPHIC = 4
+FGS_MODEL_STEREOGRAPHIC = 5
 FGS_SAVE_PIXEL_STATE = 1
 FGS_RECT_BINNING = 2
 FGS_MAX_BATCH = 8

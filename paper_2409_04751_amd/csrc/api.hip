@@ -137,12 +137,16 @@ int check_view(const fgs_pose* pose, const fgs_camera* cam, const float* bg) {
   if ((int64_t)cam->width * cam->height > ((int64_t)1 << 31)) return fail(FGS_ERR_ARG, "image too large");
   if (tiles_of(cam->width) > 0xFFFF || tiles_of(cam->height) > 0xFFFF)
     return fail(FGS_ERR_ARG, "more than 65535 tiles along one axis");
-  if (cam->model != FGS_MODEL_EQUIDISTANT) return fail(FGS_ERR_ARG, "unsupported camera model");
+  if (cam->model < FGS_MODEL_EQUIDISTANT || cam->model > FGS_MODEL_STEREOGRAPHIC)
+    return fail(FGS_ERR_ARG, "unsupported camera model");
   if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
       !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
     return fail(FGS_ERR_ARG, "focal lengths must be positive and the principal point finite");
-  if (!(cam->theta_max > 0) || !(cam->theta_max < 3.14159265358979323846))
-    return fail(FGS_ERR_ARG, "theta_max must be in (0, pi)");
+  const bool half = cam->model == FGS_MODEL_PINHOLE || cam->model == FGS_MODEL_ORTHOGRAPHIC ||
+                    cam->model == FGS_MODEL_PANORAMA;
+  if (!(cam->theta_max > 0) || !(cam->theta_max < (half ? 0.5 : 1.0) * 3.14159265358979323846))
+    return fail(FGS_ERR_ARG, half ? "theta_max must be in (0, pi/2) for this camera model"
+                                  : "theta_max must be in (0, pi)");
   if (!(cam->near_dist >= 0) || !std::isfinite(cam->near_dist)) return fail(FGS_ERR_ARG, "near_dist must be >= 0");
   for (int k = 0; k < 9; ++k)
     if (!std::isfinite(pose->R[k])) return fail(FGS_ERR_ARG, "non-finite pose");
@@ -163,6 +167,7 @@ ViewParams make_view(const fgs_pose* pose, const fgs_camera* cam, const float* b
   v.cy = cam->cy;
   v.near_dist = cam->near_dist;
   v.theta_max = cam->theta_max;
+  v.model = cam->model;
   v.width = cam->width;
   v.height = cam->height;
   v.tiles_x = tiles_of(cam->width);

@@ -136,6 +136,7 @@ struct ViewParams {
   double campos[3];  // -R^T t
   double fx, fy, cx, cy;
   double near_dist, theta_max;
+  int32_t model;
   int32_t width, height, tiles_x, tiles_y;
   uint32_t tile_base;   // first global tile id of the view
   uint32_t pixel_base;  // first pixel of the view in the per-pixel arrays

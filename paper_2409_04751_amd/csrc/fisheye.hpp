@@ -104,6 +104,169 @@ __device__ inline void fisheye_jacobian_vjp(const FisheyePoint& P, double fx, do
   g[2] += a0 * S5 + a1 * xy2 + a2 * xz2 + b0 * xy2 + b1 * S6 + b2 * yz2;
 }
 
+// ---- other camera models --------------------------------------------------
+//
+// Radial models (pinhole r = tan theta and the equisolid-angle, orthographic
+// and stereographic fisheyes that Sec. 3.2 lists) put a point at
+// mu_p = c + f r(theta) (x, y) / l_z.  Written through three scalars of
+// (theta, d = |p|),
+//   a = cos(theta) r'(theta) / d,   e = r'(theta) / d^2,
+//   h = H(theta) / d^3,  H = (sin cos r' - r) / sin^3,
+// J_phi has the same shape as the equidistant one:
+//   [[fx (a - y^2 h), fx x y h, -fx x e], [fy x y h, fy (a - x^2 h), -fy y e]].
+// For these four models H, H' / sin(theta) and r'' / sin(theta) have closed
+// forms without cancellation, and nothing divides by l_z, so the optical
+// axis needs no special case.  The backward differentiates a, e and h
+// through theta and d: with F~ = (dF/dtheta) / l_z,
+//   grad F = F~ (z / d^2) (x, y, 0) - F~ (0, 0, l_z^2 / d^2) + (dF/dd) p / d.
+//
+// The panorama (Sec. 5.4) maps longitude atan2(x, z) and latitude
+// atan2(y, rho), rho = |(x, z)|, linearly: mu_p = c + (fx lon, fy lat).  Its
+// J rows are fx grad lon and fy grad lat; the backward takes the Hessians of
+// lon and lat against the two rows of dL/dJ.
+enum CameraModel : int32_t {
+  kModelEquidistant = 0,
+  kModelPinhole = 1,
+  kModelPanorama = 2,
+  kModelEquisolid = 3,
+  kModelOrthographic = 4,
+  kModelStereographic = 5,
+};
+
+struct OtherPoint {
+  double x, y, z, lz2, l2, d;
+  double angle;         // incidence theta (radial) or |latitude| (panorama), for the cull
+  double a, e, h;       // radial J scalars
+  double at, et, ht;    // radial: dF/dtheta / l_z of a, e, h
+  double rho2, rho;     // panorama
+};
+
+// r, r', r''/sin, H and H'/sin of a radial model at incidence th.
+__device__ inline void radial_functions(int model, double th, double& r, double& r1, double& R2, double& H,
+                                        double& Hp) {
+  if (model == kModelPinhole) {
+    const double c = cos(th);
+    r = tan(th);
+    r1 = 1.0 / (c * c);
+    R2 = 2.0 * r1 / c;
+    H = 0.0;
+    Hp = 0.0;
+  } else if (model == kModelEquisolid) {
+    const double c = cos(0.5 * th), c2 = c * c, c3 = c2 * c;
+    r = 2.0 * sin(0.5 * th);
+    r1 = c;
+    R2 = -0.25 / c;
+    H = -(1.0 + 2.0 * c2) / (4.0 * c3);
+    Hp = -(3.0 + 2.0 * c2) / (16.0 * c3 * c2);
+  } else if (model == kModelOrthographic) {
+    r = sin(th);
+    r1 = cos(th);
+    R2 = -1.0;
+    H = -1.0;
+    Hp = 0.0;
+  } else {  // stereographic
+    const double c = cos(0.5 * th), ic2 = 1.0 / (c * c);
+    r = 2.0 * tan(0.5 * th);
+    r1 = ic2;
+    R2 = 0.5 * ic2 * ic2;
+    H = -R2;
+    Hp = -R2 * ic2;
+  }
+}
+
+// Fills P (x, y, z set) and, if the point survives the cull angle, mu and J.
+__device__ inline bool other_project(int model, OtherPoint& P, double angle_max, double fx, double fy, double cx,
+                                     double cy, bool need_vjp, double mu[2], double J[6]) {
+  const double x = P.x, y = P.y, z = P.z;
+  if (model == kModelPanorama) {
+    P.rho2 = x * x + z * z;
+    P.rho = sqrt(P.rho2);
+    P.l2 = P.rho2 + y * y;
+    const double lat = atan2(y, P.rho);
+    P.angle = fabs(lat);
+    if (!(P.angle <= angle_max)) return false;
+    mu[0] = cx + fx * atan2(x, z);
+    mu[1] = cy + fy * lat;
+    const double ir2 = 1.0 / P.rho2, k = fy / (P.rho * P.l2);
+    J[0] = fx * z * ir2;
+    J[1] = 0.0;
+    J[2] = -fx * x * ir2;
+    J[3] = -k * x * y;
+    J[4] = k * P.rho2;
+    J[5] = -k * y * z;
+    return true;
+  }
+  P.lz2 = x * x + y * y;
+  P.l2 = P.lz2 + z * z;
+  P.d = sqrt(P.l2);
+  const double lz = sqrt(P.lz2);
+  const double th = atan2(lz, z);
+  P.angle = th;
+  if (!(th <= angle_max)) return false;
+  double r, r1, R2, H, Hp;
+  radial_functions(model, th, r, r1, R2, H, Hp);
+  const double ct = z / P.d;
+  P.a = ct * r1 / P.d;
+  P.e = r1 / P.l2;
+  P.h = H / (P.d * P.l2);
+  if (need_vjp) {
+    P.at = (ct * R2 - r1) / P.l2;
+    P.et = R2 / (P.d * P.l2);
+    P.ht = Hp / (P.l2 * P.l2);
+  }
+  if (lz > 0.0) {
+    mu[0] = cx + fx * r * x / lz;
+    mu[1] = cy + fy * r * y / lz;
+  } else {
+    mu[0] = cx;
+    mu[1] = cy;
+  }
+  J[0] = fx * (P.a - y * y * P.h);
+  J[1] = fx * x * y * P.h;
+  J[2] = -fx * x * P.e;
+  J[3] = fy * x * y * P.h;
+  J[4] = fy * (P.a - x * x * P.h);
+  J[5] = -fy * y * P.e;
+  return true;
+}
+
+// g[k] += sum_ij G[i][j] dJ_ij / dp_k for the models of other_project.
+__device__ inline void other_jacobian_vjp(int model, const OtherPoint& P, double fx, double fy, const double G[6],
+                                          double g[3]) {
+  const double x = P.x, y = P.y, z = P.z;
+  if (model == kModelPanorama) {
+    // row 0: fx grad lon, grad lon = (z, 0, -x) / rho^2
+    const double ir2 = 1.0 / P.rho2, u = G[0] * z - G[2] * x;
+    g[0] += fx * (-G[2] * ir2 - 2.0 * x * u * ir2 * ir2);
+    g[2] += fx * (G[0] * ir2 - 2.0 * z * u * ir2 * ir2);
+    // row 1: fy grad lat, grad lat = (rho e_y - y grad rho) / d^2
+    const double rho = P.rho, ir = 1.0 / rho, s = G[3] * x + G[5] * z;
+    const double N = rho * G[4] - y * s * ir;
+    const double ir3 = ir * ir * ir, il2 = 1.0 / P.l2;
+    const double dN0 = G[4] * x * ir - y * (G[3] * ir - s * x * ir3);
+    const double dN1 = -s * ir;
+    const double dN2 = G[4] * z * ir - y * (G[5] * ir - s * z * ir3);
+    const double q = 2.0 * N * il2 * il2;
+    g[0] += fy * (dN0 * il2 - q * x);
+    g[1] += fy * (dN1 * il2 - q * y);
+    g[2] += fy * (dN2 * il2 - q * z);
+    return;
+  }
+  const double a0 = fx * G[0], a1 = fx * G[1], a2 = fx * G[2];
+  const double b0 = fy * G[3], b1 = fy * G[4], b2 = fy * G[5];
+  const double cA = a0 + b1;
+  const double m = a1 + b0;
+  const double cH = -a0 * y * y + m * x * y - b1 * x * x;
+  const double cE = -a2 * x - b2 * y;
+  const double S = cA * P.at + cH * P.ht + cE * P.et;
+  const double il2 = 1.0 / P.l2;
+  const double Q = -(cA * P.a + 3.0 * cH * P.h + 2.0 * cE * P.e) * il2;
+  const double Szl = S * z * il2;
+  g[0] += Szl * x + Q * x + m * y * P.h - 2.0 * b1 * x * P.h - a2 * P.e;
+  g[1] += Szl * y + Q * y + m * x * P.h - 2.0 * a0 * y * P.h - b2 * P.e;
+  g[2] += -S * P.lz2 * il2 + Q * z;
+}
+
 // Rotation of the normalised quaternion (w, x, y, z), row-major.
 __device__ inline void quat_to_rot(const double q[4], double R[9]) {
   const double w = q[0], x = q[1], y = q[2], z = q[3];

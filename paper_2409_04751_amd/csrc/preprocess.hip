@@ -3,7 +3,7 @@
 // Forward, one thread per Gaussian, in the order of the 3DGS preprocess the
 // paper modifies (Sec. 4.1; only the projection changes, Sec. 4.2-4.3):
 // cull (non-finite, |mu_c| <= near, theta > theta_max), project the mean by
-// the equidistant model (Sec. 3.2), Sigma = R S S^T R^T (Eq. 1), T = J W,
+// the equidistant model (Sec. 3.2) or another camera model, Sigma = R S S^T R^T (Eq. 1), T = J W,
 // Sigma_p = T Sigma T^T (Eq. 2) plus a 0.3 px^2 low-pass dilation, conic,
 // radius = ceil(3 sqrt(lambda_max)), tile rectangle, SH colour, depth key.
 //
@@ -42,7 +42,8 @@ struct PreArgs {
 
 struct Geometry {
   double pc[3];
-  FisheyePoint P;
+  FisheyePoint P;   // equidistant model
+  OtherPoint O;     // the other models
   double mu[2];
   double Rq[9];  // rotation of the normalised quaternion
   double qn[4], qnorm;
@@ -55,8 +56,20 @@ struct Geometry {
   double conic[3];
 };
 
+// Which camera models a kernel instantiation handles: only the equidistant
+// one, only the others, or any (a batch that mixes them).  Keeping the
+// equidistant path alone in its own instantiation keeps its register count.
+enum ModelClass { kMcEquidistant = 0, kMcOther = 1, kMcAny = 2 };
+
+__host__ inline int model_class_of(const ViewBatch& b) {
+  bool eq = false, other = false;
+  for (int k = 0; k < b.count; ++k) (b.v[k].model == kModelEquidistant ? eq : other) = true;
+  return eq && other ? kMcAny : (other ? kMcOther : kMcEquidistant);
+}
+
 // Returns false if culled.  Shared by forward and backward so both take the
 // same decisions on the same inputs.
+template <int MC>
 __device__ inline bool compute_geometry(const float* means, const float* scales, const float* quats,
                                         const float* opac, uint32_t i, uint32_t n, const ViewParams& v,
                                         bool need_m, Geometry& G) {
@@ -78,17 +91,25 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   const double x = G.pc[0], y = G.pc[1], z = G.pc[2];
   const double dist = sqrt((x * x + y * y) + z * z);
   if (!(dist > v.near_dist)) return false;
-  G.P.x = x;
-  G.P.y = y;
-  G.P.z = z;
-  fisheye_terms(G.P, need_m);
-  if (!(G.P.theta <= v.theta_max)) return false;
-  if (G.P.lz > 0.0) {
-    G.mu[0] = v.cx + v.fx * G.P.theta * x / G.P.lz;
-    G.mu[1] = v.cy + v.fy * G.P.theta * y / G.P.lz;
+  if (MC == kMcEquidistant || (MC == kMcAny && v.model == kModelEquidistant)) {
+    G.P.x = x;
+    G.P.y = y;
+    G.P.z = z;
+    fisheye_terms(G.P, need_m);
+    if (!(G.P.theta <= v.theta_max)) return false;
+    if (G.P.lz > 0.0) {
+      G.mu[0] = v.cx + v.fx * G.P.theta * x / G.P.lz;
+      G.mu[1] = v.cy + v.fy * G.P.theta * y / G.P.lz;
+    } else {
+      G.mu[0] = v.cx;
+      G.mu[1] = v.cy;
+    }
+    fisheye_jacobian(G.P, v.fx, v.fy, G.J);
   } else {
-    G.mu[0] = v.cx;
-    G.mu[1] = v.cy;
+    G.O.x = x;
+    G.O.y = y;
+    G.O.z = z;
+    if (!other_project(v.model, G.O, v.theta_max, v.fx, v.fy, v.cx, v.cy, need_m, G.mu, G.J)) return false;
   }
   // Sigma = M M^T, M = R S
   G.qnorm = sqrt(q2);
@@ -104,7 +125,6 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   G.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
   G.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
   G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-  fisheye_jacobian(G.P, v.fx, v.fy, G.J);
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c)
       G.T[r * 3 + c] = G.J[r * 3 + 0] * v.R[0 * 3 + c] + G.J[r * 3 + 1] * v.R[1 * 3 + c] + G.J[r * 3 + 2] * v.R[2 * 3 + c];
@@ -178,13 +198,14 @@ __global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block
 // Geometry of entry e = (view vi, Gaussian i): cull, project, conic, radius,
 // tile rect, depth key.  A culled entry writes only its tile count (0) and an
 // all-ones depth key.  Returns the tile count.
+template <int MC>
 __device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_t i, size_t e) {
   const uint32_t n = a.n;
   const ViewParams& vp = a.batch.v[vi];
   uint32_t key = 0xFFFFFFFFu, ntiles = 0;
   Geometry G;
   do {
-    if (!compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
+    if (!compute_geometry<MC>(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
     const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
     const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
     double rad = ceil(3.0 * sqrt(lam));
@@ -247,11 +268,11 @@ __device__ inline uint32_t entry_color(const PreArgs& a, uint32_t vi, uint32_t i
 
 // One view: geometry and colour in one thread (the coefficients are read
 // only for the Gaussians the view keeps).
-template <int DEG>
+template <int DEG, int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_fused_kernel(PreArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
-  const uint32_t ntiles = entry_geometry(a, 0u, i, i);
+  const uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i);
   if (ntiles == 0) return;
   float c[48];
   load_sh<DEG>(a.sh, i, a.n, c);
@@ -270,11 +291,12 @@ __device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i
   i = (logical / nviews) * kBlock + threadIdx.x;
 }
 
+template <int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   uint32_t vi, i;
   entry_of_block((uint32_t)a.batch.count, vi, i);
   if (i >= a.n) return;
-  entry_geometry(a, vi, i, (size_t)vi * a.n + i);
+  entry_geometry<MC>(a, vi, i, (size_t)vi * a.n + i);
 }
 
 // Also leaves each block's tile total in block_tiles[view][block] (a plain
@@ -377,12 +399,14 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
 // Geometry part of the backward (Sec. 4.3): from dL/d(mu_p, conic, opacity)
 // to dL/d(mu, s, q, o) through the fisheye Jacobian, in fp64.  Runs after
 // sh_backward_kernel and adds to the direction term it left in g_means.
+template <int MC>
 __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
   const uint32_t n = a.n;
   Geometry G;
-  const bool visible = a.tiles[i] != 0 && compute_geometry(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
+  const bool visible =
+      a.tiles[i] != 0 && compute_geometry<MC>(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
   if (!visible) {
     for (int c = 0; c < 3; ++c) { a.g_means[c * n + i] = 0.0f; a.g_scales[c * n + i] = 0.0f; }
     for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = 0.0f;
@@ -427,7 +451,10 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
   // dL/dmu_c
   double gpc[3];
   for (int c = 0; c < 3; ++c) gpc[c] = G.J[0 * 3 + c] * gmu[0] + G.J[1 * 3 + c] * gmu[1];
-  fisheye_jacobian_vjp(G.P, a.v.fx, a.v.fy, dJ, gpc);
+  if (MC == kMcEquidistant)
+    fisheye_jacobian_vjp(G.P, a.v.fx, a.v.fy, dJ, gpc);
+  else
+    other_jacobian_vjp(a.v.model, G.O, a.v.fx, a.v.fy, dJ, gpc);
   double gm[3];
   for (int c = 0; c < 3; ++c)
     gm[c] = a.v.R[0 * 3 + c] * gpc[0] + a.v.R[1 * 3 + c] * gpc[1] + a.v.R[2 * 3 + c] * gpc[2];
@@ -489,9 +516,14 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
   a.radii = reinterpret_cast<int32_t*>(ws + L.radii);
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
   const bool multi = b.count > 1;
+  const int mc = model_class_of(b);
   if (!multi) {
     ProfScope prof(s, kKPreprocess);
-#define FGS_PRE_LAUNCH(D) hipLaunchKernelGGL((preprocess_fused_kernel<D>), dim3(blocks), dim3(kBlock), 0, s, a);
+#define FGS_PRE_LAUNCH(D)                                                                          \
+  if (mc == kMcEquidistant)                                                                        \
+    hipLaunchKernelGGL((preprocess_fused_kernel<D, kMcEquidistant>), dim3(blocks), dim3(kBlock), 0, s, a); \
+  else                                                                                             \
+    hipLaunchKernelGGL((preprocess_fused_kernel<D, kMcOther>), dim3(blocks), dim3(kBlock), 0, s, a);
     switch (g.sh_degree) {
       case 0: FGS_PRE_LAUNCH(0) break;
       case 1: FGS_PRE_LAUNCH(1) break;
@@ -504,7 +536,12 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
   const dim3 grid(blocks * (unsigned)b.count);
   {
     ProfScope prof(s, kKPreprocess);
-    hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kBlock), 0, s, a);
+    if (mc == kMcEquidistant)
+      hipLaunchKernelGGL(preprocess_kernel<kMcEquidistant>, grid, dim3(kBlock), 0, s, a);
+    else if (mc == kMcOther)
+      hipLaunchKernelGGL(preprocess_kernel<kMcOther>, grid, dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL(preprocess_kernel<kMcAny>, grid, dim3(kBlock), 0, s, a);
   }
   ProfScope prof(s, kKColor);
 #define FGS_PRE_LAUNCH(D) hipLaunchKernelGGL((color_kernel<D>), grid, dim3(kBlock), 0, s, a);
@@ -555,7 +592,10 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
     }
   }
   ProfScope prof(s, kKPreprocessBackward);
-  hipLaunchKernelGGL(geometry_backward_kernel, dim3(blocks), dim3(kBlock), 0, s, a);
+  if (v.model == kModelEquidistant)
+    hipLaunchKernelGGL(geometry_backward_kernel<kMcEquidistant>, dim3(blocks), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(geometry_backward_kernel<kMcOther>, dim3(blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -32,7 +32,9 @@ TILE = 16
 
 @dataclasses.dataclass(frozen=True)
 class Camera:
-    """Intrinsics of one view.  model 0 = equidistant fisheye (Sec. 3.2)."""
+    """Intrinsics of one view.  model: 0 equidistant fisheye (Sec. 3.2),
+    1 pinhole, 2 panorama (Sec. 5.4), 3 equisolid-angle, 4 orthographic,
+    5 stereographic fisheye."""
 
     width: int
     height: int
@@ -86,20 +88,49 @@ class Scene:
         )
 
 
-def fisheye_camera(width: int, height: int, fov_deg: float, near: float = 0.2) -> Camera:
-    """Equidistant fisheye whose horizontal field of view spans the image width.
+MODEL_EQUIDISTANT, MODEL_PINHOLE, MODEL_PANORAMA, MODEL_EQUISOLID, MODEL_ORTHOGRAPHIC, MODEL_STEREOGRAPHIC = range(6)
+RADIAL_MODELS = (MODEL_EQUIDISTANT, MODEL_PINHOLE, MODEL_EQUISOLID, MODEL_ORTHOGRAPHIC, MODEL_STEREOGRAPHIC)
 
-    f = width / FOV (radians); principal point at (width/2, height/2).
-    theta_max (the rear-axis cull) = min(theta_corner + 0.25, 0.95 pi), where
-    theta_corner is the incidence angle r/f of the image corner farthest from
-    the principal point.  These are workload parameters handed unchanged to
+# r(theta) and its inverse for the radial models, and the largest theta_max
+# the camera builder hands out for each (where r' or the splat degenerates)
+_RADIAL = {
+    MODEL_PINHOLE: (math.tan, math.atan, 0.45 * math.pi),
+    MODEL_EQUISOLID: (lambda t: 2.0 * math.sin(t / 2.0), lambda r: 2.0 * math.asin(min(1.0, r / 2.0)), 0.95 * math.pi),
+    MODEL_ORTHOGRAPHIC: (math.sin, lambda r: math.asin(min(1.0, r)), 0.45 * math.pi),
+    MODEL_STEREOGRAPHIC: (lambda t: 2.0 * math.tan(t / 2.0), lambda r: 2.0 * math.atan(r / 2.0), 0.95 * math.pi),
+}
+
+
+def fisheye_camera(width: int, height: int, fov_deg: float, near: float = 0.2, model: int = MODEL_EQUIDISTANT) -> Camera:
+    """Radial camera whose horizontal field of view spans the image width.
+
+    Equidistant (the default): f = width / FOV (radians).  Other radial
+    models: f r(FOV / 2) = width / 2.  Principal point at (width/2, height/2).
+    theta_max (the rear-axis cull) = min(theta_corner + 0.25, cap), where
+    theta_corner is the incidence angle of the image corner farthest from the
+    principal point and cap is 0.95 pi (0.45 pi for the pinhole and
+    orthographic models).  These are workload parameters handed unchanged to
     both implementations.
     """
-    f = width / math.radians(fov_deg)
     cx, cy = width / 2.0, height / 2.0
     corner = max(math.hypot(ax - cx, ay - cy) for ax in (0.0, float(width)) for ay in (0.0, float(height)))
-    theta_max = min(corner / f + 0.25, 0.95 * math.pi)
-    return Camera(width, height, f, f, cx, cy, 0, near, theta_max)
+    if model == MODEL_EQUIDISTANT:
+        f = width / math.radians(fov_deg)
+        theta_max = min(corner / f + 0.25, 0.95 * math.pi)
+        return Camera(width, height, f, f, cx, cy, 0, near, theta_max)
+    r, r_inv, cap = _RADIAL[model]
+    f = (width / 2.0) / r(math.radians(fov_deg) / 2.0)
+    theta_max = min(r_inv(corner / f) + 0.25, cap)
+    return Camera(width, height, f, f, cx, cy, model, near, theta_max)
+
+
+def panorama_camera(width: int, height: int, near: float = 0.2, lat_max: float = 0.45 * math.pi) -> Camera:
+    """Equirectangular panorama (Sec. 5.4): longitude over the full width,
+    latitude over the full height: f_x = width / (2 pi), f_y = height / pi,
+    c = (width/2, height/2).  Gaussians above |latitude| lat_max are culled
+    (theta_max carries it)."""
+    return Camera(width, height, width / (2.0 * math.pi), height / math.pi, width / 2.0, height / 2.0,
+                  MODEL_PANORAMA, near, lat_max)
 
 
 def identity_pose(position=(0.0, 0.0, 0.0)) -> Pose:

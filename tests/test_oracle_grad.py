@@ -17,17 +17,33 @@ import oracle
 from paper_2409_04751_amd import synth
 
 
-def _scene_and_view(seed, degree=3, n=10):
+def _camera(model):
+    if model == synth.MODEL_PANORAMA:
+        return synth.panorama_camera(64, 32)
+    if model == synth.MODEL_EQUIDISTANT:
+        return synth.fisheye_camera(48, 40, 200.0)
+    fov = {synth.MODEL_PINHOLE: 100.0, synth.MODEL_ORTHOGRAPHIC: 160.0}.get(model, 200.0)
+    return synth.fisheye_camera(48, 40, fov, model=model)
+
+
+def _scene_and_view(seed, degree=3, n=10, model=synth.MODEL_EQUIDISTANT):
     rng = np.random.default_rng(seed)
     # a posed camera looking at a cluster of Gaussians
-    cam = synth.fisheye_camera(48, 40, 200.0)
+    cam = _camera(model)
     R = synth._haar_rotation(rng)
     pos = rng.normal(size=3)
-    # Gaussians in front of the camera: camera-space points mapped to world
-    theta = rng.uniform(0, math.radians(95), n)
-    psi = rng.uniform(0, 2 * math.pi, n)
-    r = rng.uniform(1.0, 3.0, n)
-    pc = np.stack([r * np.sin(theta) * np.cos(psi), r * np.sin(theta) * np.sin(psi), r * np.cos(theta)])
+    # Gaussians in view: camera-space points mapped to world
+    if model == synth.MODEL_PANORAMA:  # any longitude, latitude within 60 degrees
+        lon = rng.uniform(-0.9 * math.pi, 0.9 * math.pi, n)
+        lat = rng.uniform(-math.pi / 3, math.pi / 3, n)
+        r = rng.uniform(1.0, 3.0, n)
+        pc = np.stack([r * np.cos(lat) * np.sin(lon), r * np.sin(lat), r * np.cos(lat) * np.cos(lon)])
+    else:  # incidence up to 95 degrees (up to the camera's half-FOV for the narrower models)
+        top = math.radians(95) if model == synth.MODEL_EQUIDISTANT else min(math.radians(95), cam.theta_max - 0.3)
+        theta = rng.uniform(0, top, n)
+        psi = rng.uniform(0, 2 * math.pi, n)
+        r = rng.uniform(1.0, 3.0, n)
+        pc = np.stack([r * np.sin(theta) * np.cos(psi), r * np.sin(theta) * np.sin(psi), r * np.cos(theta)])
     means = R.T @ pc + pos[:, None]
     S = 3 * (degree + 1) ** 2
     sh = rng.normal(0, 0.2, size=(S, n))
@@ -55,9 +71,9 @@ TOL = (1e-3, 1e-3, 1e-3)
 STEP = {"means": 1e-7, "scales": 1e-6, "quats": 1e-6, "opacity": 1e-6, "sh": 1e-5}
 
 
-@pytest.mark.parametrize("seed", [3, 11])
-def test_gradients_match_finite_differences(seed):
-    scene, pose, cam = _scene_and_view(seed)
+@pytest.mark.parametrize("seed,model", [(3, 0), (11, 0), (5, 1), (6, 2), (7, 3), (8, 4), (9, 5)])
+def test_gradients_match_finite_differences(seed, model):
+    scene, pose, cam = _scene_and_view(seed, model=model)
     rng = np.random.default_rng(100 + seed)
     bg = (0.2, 0.1, 0.3)
     w = rng.normal(size=(3, cam.height, cam.width))

@@ -87,13 +87,17 @@ def traffic_for(kernel: str):
 
 
 # Floating-point operations of the blend backward (an FMA counts 2, exp2 and
-# rcp count 1 each).  Every (pixel, entry) pair up to the pixel's last
-# blended entry evaluates the exponent (9) and tests it (1); a pair that
-# blends adds alpha 3, transmittance in front 3, colour gradient 7, colour
-# difference 3, dL/dalpha 6, colour behind 6, opacity term 2, dL/dq 1 and the
-# mean and conic terms 16.
-BLEND_BWD_FLOPS_TESTED = 10.0
-BLEND_BWD_FLOPS_BLENDED = 47.0
+# rcp count 1 each).  The autograd path keeps no per-pixel state, so the
+# backward first re-sweeps front to back: every (pixel, entry) pair up to the
+# pixel's last blended entry evaluates the exponent (9) and tests it (1); a
+# pair that blends adds alpha 3 (exp2, scale, clamp), 1 - alpha, the new
+# transmittance and the stop test (3).  The reverse pass then evaluates and
+# tests the exponent again (10); a pair that blends adds alpha 3,
+# transmittance in front 3, colour gradient 7, colour difference 3,
+# dL/dalpha 6, colour behind 6, opacity term 2, dL/dq 1 and the mean and
+# conic terms 16.
+BLEND_BWD_FLOPS_TESTED = 10.0 + 10.0
+BLEND_BWD_FLOPS_BLENDED = 6.0 + 47.0
 
 
 def contributing_pairs(ws, lay, n: int, K: int) -> tuple[int, int]:

@@ -465,6 +465,27 @@ __device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32
 
 __device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts of
+// 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from outside the
+// row add 0), then the row totals broadcast from lane 15 into row 1 and 3
+// and from lane 31 into rows 2 and 3.
+template <int CTRL, int ROW_MASK>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+  v += dpp_u32<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_u32<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_u32<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_u32<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_u32<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+// Per depth-ordered visible entry: reach parameters and kept-tile count,
+// contiguous in j, so that the duplication reads one record per Gaussian
+// with no dependent gather.
 // Per depth-ordered visible entry: reach parameters and kept-tile count,
 // contiguous in j, so that the duplication reads one record per Gaussian
 // with no dependent gather.
@@ -522,49 +543,122 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, 
   for (uint32_t t = threadIdx.x; t < m; t += kBlock) s_off[t] = offsets[first + t];
   __syncthreads();
   uint32_t o = o_begin + threadIdx.x * kIptPayload1;
-  if (o < o_end) {
-    // this thread's first Gaussian: largest local index with s_off <= o
+  const bool active = o < o_end;
+  // this thread's first Gaussian (largest local index with s_off <= o) and
+  // how many of its kept tiles come before slot o
+  uint32_t local = 0, next = 0xFFFFFFFFu, skip = 0;
+  if (active) {
     uint32_t lo = 0, hi = m;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (s_off[mid] <= o) lo = mid; else hi = mid;
     }
-    uint32_t local = lo;
-    uint32_t next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-    // the current Gaussian's kept tiles: row y, columns [c0, c1), at col
-    uint32_t g = 0, tbase = 0, tiles_x = 0;
-    int x0 = 0, x1 = 0, y = 0, y1 = 0, c0 = 0, c1 = 0, col = 0;
-    SplatReach rr;
-    auto enter = [&](uint32_t jj, uint32_t skip) {  // Gaussian jj, from its skip-th kept tile
-      const uint32_t a = rx[jj], b = ry[jj];
-      g = ids[jj];
-      x0 = (int)(a & 0xFFFFu);
-      y = (int)(a >> 16);
-      x1 = (int)(b & 0xFFFFu);
-      y1 = (int)(b >> 16);
-      view_of(map, g, tbase, tiles_x);
-      rr = unpack_reach(reach[2 * (size_t)jj], reach[2 * (size_t)jj + 1]);
-      if (rr.kind == 1) {
-        reach_row(rr, y, x0, x1, c0, c1);
-        while (skip >= (uint32_t)(c1 - c0) && y + 1 < y1) {
-          skip -= (uint32_t)(c1 - c0);
-          reach_row(rr, ++y, x0, x1, c0, c1);
-        }
-      } else {  // the whole rect (a kind-0 entry is never visible)
-        const uint32_t w = (uint32_t)(x1 - x0);
-        y += (int)(skip / w);
-        skip -= (skip / w) * w;
-        c0 = x0;
-        c1 = x1;
+    local = lo;
+    next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
+    skip = o - s_off[local];
+  }
+  // the current Gaussian's kept tiles: row y, columns [c0, c1), at col
+  uint32_t g = 0, tbase = 0, tiles_x = 0;
+  int x0 = 0, x1 = 0, y = 0, y1 = 0, c0 = 0, c1 = 0, col = 0;
+  SplatReach rr;
+  rr.kind = 2;
+  auto load = [&](uint32_t jj) {
+    const uint32_t a = rx[jj], b = ry[jj];
+    g = ids[jj];
+    x0 = (int)(a & 0xFFFFu);
+    y = (int)(a >> 16);
+    x1 = (int)(b & 0xFFFFu);
+    y1 = (int)(b >> 16);
+    view_of(map, g, tbase, tiles_x);
+    rr = unpack_reach(reach[2 * (size_t)jj], reach[2 * (size_t)jj + 1]);
+  };
+  // from the current row on, the row holding the skip-th kept tile
+  auto walk = [&](uint32_t sk) {
+    if (rr.kind == 1) {
+      reach_row(rr, y, x0, x1, c0, c1);
+      while (sk >= (uint32_t)(c1 - c0) && y + 1 < y1) {
+        sk -= (uint32_t)(c1 - c0);
+        reach_row(rr, ++y, x0, x1, c0, c1);
       }
-      col = c0 + (int)skip;
-    };
-    enter(first + local, o - s_off[local]);
+    } else {  // the whole rect (a kind-0 entry is never visible)
+      const uint32_t w = (uint32_t)(x1 - x0);
+      y += (int)(sk / w);
+      sk -= (sk / w) * w;
+      c0 = x0;
+      c1 = x1;
+    }
+    col = c0 + (int)sk;
+  };
+  // A thread that starts deep inside a Gaussian of many rows would walk
+  // them one reach_row at a time, and its wave would wait for its longest
+  // walk.  Instead the wave evaluates such a Gaussian's rows together, one
+  // per lane, and every lane that starts inside it finds its row in the
+  // prefix sums of the row counts.
+  bool coop = false;
+  if (active) {
+    load(first + local);
+    // only walks of more than about 8 rows: skip rows / count estimates it
+    const uint32_t count = local + 1u < m ? s_off[local + 1u] - s_off[local] : 0xFFFFFFFFu;
+    coop = rr.kind == 1 && skip > 0 && (float)skip * (float)(y1 - y) > 8.0f * (float)count;
+    if (!coop) walk(skip);
+  }
+  const int lane = (int)lane_id();
+  for (uint64_t pending = __ballot(coop); pending != 0; pending = __ballot(coop)) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t lj = (uint32_t)__shfl((int)local, leader);
+    SplatReach lr;
+    lr.mx = __shfl(rr.mx, leader);
+    lr.my = __shfl(rr.my, leader);
+    lr.Pa = __shfl(rr.Pa, leader);
+    lr.da = __shfl(rr.da, leader);
+    lr.beta = __shfl(rr.beta, leader);
+    lr.ry = __shfl(rr.ry, leader);
+    lr.ds = __shfl(rr.ds, leader);
+    lr.kind = 1;
+    const int lx0 = __shfl(x0, leader), lx1 = __shfl(x1, leader);
+    const int ly0 = __shfl(y, leader), ly1 = __shfl(y1, leader);
+    const bool mine = coop && local == lj;
+    uint32_t before = 0;  // kept tiles in the rows of earlier chunks
+    for (int base = ly0; base < ly1; base += 64) {
+      const int row = base + lane;
+      int r0 = lx0, r1 = lx0;
+      if (row < ly1) reach_row(lr, row, lx0, lx1, r0, r1);
+      const uint32_t cnt = (uint32_t)(r1 - r0);
+      const uint32_t incl = wave_inclusive_scan(cnt);
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      // every lane searches (the shuffles need the whole wave); only the
+      // lanes that start in this chunk of the leader's Gaussian use it: the
+      // last lane whose exclusive prefix is <= the skip holds the tile
+      // (an empty row shares its prefix with the next, non-empty one)
+      const uint32_t want = skip - before;
+      int p = 0;
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int probe = p + step;
+        const uint32_t ex = (uint32_t)__shfl((int)incl, probe - 1);  // exclusive prefix of lane probe
+        if (ex <= want) p = probe;
+      }
+      const uint32_t exp_ = (uint32_t)__shfl((int)incl, p > 0 ? p - 1 : 0);
+      const int pr0 = __shfl(r0, p), pr1 = __shfl(r1, p);
+      if (mine && coop && skip < before + total) {
+        y = base + p;
+        c0 = pr0;
+        c1 = pr1;
+        col = c0 + (int)(want - (p > 0 ? exp_ : 0u));
+        coop = false;
+      }
+      before += total;
+    }
+    // the leader's Gaussian is done (a skip past its rows cannot happen: the
+    // rows hold exactly its count)
+    coop = coop && local != lj;
+  }
+  if (active) {
     for (int k = 0; k < kIptPayload1 && o < o_end; ++k, ++o) {
       if (o == next) {
         ++local;
         next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-        enter(first + local, 0u);
+        load(first + local);
+        walk(0u);
       }
       const uint32_t key = tbase + (uint32_t)y * tiles_x + (uint32_t)col;
       const uint32_t e = o - o_begin;

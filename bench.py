@@ -36,8 +36,8 @@ def log(*a):
 
 def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | None:
     """Algorithmic HBM bytes of ONE launch of `name` (byte model)."""
-    if name == "preprocess":  # one view: geometry and colour fused
-        return 52.0 * N + (4.0 * S + 76.0) * V
+    if name == "preprocess":  # one view: geometry and colour fused, plus the colour's direction gradient
+        return 52.0 * N + (4.0 * S + 124.0) * V
     if name == "color":
         return 4.0 * N + (4.0 * S + 32.0) * V
     if name == "depth_sort_scatter":
@@ -54,8 +54,8 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * K
     if name == "ranges":
         return 4.0 * K
-    if name == "sh_backward":
-        return 4.0 * N + (24.0 + 4.0 * S) * V + (12.0 + 4.0 * S) * N
+    if name == "sh_backward":  # tile count, mean, dL/drgb, direction gradient in; dL/dSH, dL/dmu out
+        return 28.0 * N + 48.0 * V + (12.0 + 4.0 * S) * N
     if name == "preprocess_backward":
         return 4.0 * N + 80.0 * V + 44.0 * N
     return None

@@ -91,6 +91,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.tvals_a = take((size_t)kk * 4);
   L.tkeys_b = take((size_t)kk * 4);
   L.tvals_b = take((size_t)kk * 4);
+  L.colorjac = take(nn * 3 * sizeof(float4));
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);

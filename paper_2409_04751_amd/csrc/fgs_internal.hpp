@@ -114,6 +114,7 @@ struct Layout {
   int64_t kcap = 0;
   size_t bytes = 0;
   size_t splats, colors, depth_keys, tiles, rects, radii;
+  size_t colorjac;  // single view: float4 [n][3], d rgb / d view direction per channel + clamp mask
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
   size_t reach, counts;  // per depth-ordered visible entry: reach parameters (2 float4), kept-tile count

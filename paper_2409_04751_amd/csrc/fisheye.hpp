@@ -370,4 +370,57 @@ __device__ inline void sh_grad_dir(float x, float y, float z, const float w[16],
   }
 }
 
+// D[ch] = sum_k c[k*3+ch] grad Y_k at (x, y, z) for the three channels at
+// once (the gradient of each channel's colour in the view direction, each
+// Y_k read as a polynomial in R^3), the monomials shared.
+template <int DEG>
+__device__ inline void sh_grad_dir3(float x, float y, float z, const float c[48], float D[3][3]) {
+  for (int ch = 0; ch < 3; ++ch) D[ch][0] = D[ch][1] = D[ch][2] = 0.0f;
+  auto add = [&](int k, int a, float v) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) D[ch][a] += v * c[k * 3 + ch];
+  };
+  if constexpr (DEG >= 1) {
+    add(1, 1, -kY1);
+    add(2, 2, kY1);
+    add(3, 0, -kY1);
+  }
+  if constexpr (DEG >= 2) {
+    add(4, 0, kY2a * y);
+    add(4, 1, kY2a * x);
+    add(5, 1, -kY2a * z);
+    add(5, 2, -kY2a * y);
+    add(6, 0, -2.0f * kY2b * x);
+    add(6, 1, -2.0f * kY2b * y);
+    add(6, 2, 4.0f * kY2b * z);
+    add(7, 0, -kY2a * z);
+    add(7, 2, -kY2a * x);
+    add(8, 0, 2.0f * kY2c * x);
+    add(8, 1, -2.0f * kY2c * y);
+  }
+  if constexpr (DEG >= 3) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, xz = x * z, yz = y * z;
+    add(9, 0, -6.0f * kY3a * xy);
+    add(9, 1, -3.0f * kY3a * (xx - yy));
+    add(10, 0, kY3b * yz);
+    add(10, 1, kY3b * xz);
+    add(10, 2, kY3b * xy);
+    add(11, 0, 2.0f * kY3c * xy);
+    add(11, 1, -kY3c * (4.0f * zz - xx - 3.0f * yy));
+    add(11, 2, -8.0f * kY3c * yz);
+    add(12, 0, -6.0f * kY3d * xz);
+    add(12, 1, -6.0f * kY3d * yz);
+    add(12, 2, kY3d * (6.0f * zz - 3.0f * xx - 3.0f * yy));
+    add(13, 0, -kY3c * (4.0f * zz - 3.0f * xx - yy));
+    add(13, 1, 2.0f * kY3c * xy);
+    add(13, 2, -8.0f * kY3c * xz);
+    add(14, 0, 2.0f * kY3e * xz);
+    add(14, 1, -2.0f * kY3e * yz);
+    add(14, 2, kY3e * (xx - yy));
+    add(15, 0, -3.0f * kY3a * (xx - yy));
+    add(15, 1, 6.0f * kY3a * xy);
+  }
+}
+
 }  // namespace fgs

@@ -31,6 +31,7 @@ struct PreArgs {
   // outputs, entry view * n + i
   float4* splats;  // [entry][2]: position, conic
   float4* colors;  // [entry]: opacity, rgb
+  float4* colorjac;  // one view only, [i][3]: d rgb / d dir (9 floats, row per channel), clamp mask; or null
   uint32_t* depth_keys;
   uint32_t* tiles;
   uint2* rects;
@@ -259,6 +260,17 @@ __device__ inline uint32_t entry_color(const PreArgs& a, uint32_t vi, uint32_t i
   sh_color<DEG>(c, dir, rgb, Y);
   if (isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2])) {
     a.colors[e] = make_float4(a.opac[i], fmaxf(rgb[0], 0.0f), fmaxf(rgb[1], 0.0f), fmaxf(rgb[2], 0.0f));
+    if (a.colorjac) {
+      // what the backward needs of the SH: per channel the gradient of the
+      // colour in the view direction (sum_k c_k grad Y_k) and whether the
+      // channel was clamped at 0, so that it need not read the coefficients
+      float D[3][3];
+      sh_grad_dir3<DEG>(dir[0], dir[1], dir[2], c, D);
+      const uint32_t mask = (rgb[0] < 0.0f ? 1u : 0u) | (rgb[1] < 0.0f ? 2u : 0u) | (rgb[2] < 0.0f ? 4u : 0u);
+      a.colorjac[3 * e + 0] = make_float4(D[0][0], D[0][1], D[0][2], D[1][0]);
+      a.colorjac[3 * e + 1] = make_float4(D[1][1], D[1][2], D[2][0], D[2][1]);
+      a.colorjac[3 * e + 2] = make_float4(D[2][2], __uint_as_float(mask), 0.0f, 0.0f);
+    }
     return ntiles;
   }
   a.tiles[e] = 0;
@@ -343,6 +355,7 @@ struct PreBwdArgs {
   ViewParams v;
   const uint32_t* tiles;
   const float* grad2d;  // [9][n]
+  const float4* colorjac;  // [n][3], from the forward
   float* g_means;
   float* g_scales;
   float* g_quats;
@@ -363,32 +376,34 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   const uint32_t n = a.n;
   constexpr int nb = (DEG + 1) * (DEG + 1);
   // one path for every lane (culled lanes compute and select zeros), so each
-  // plane is written by one full-wave store
+  // plane is written by one full-wave store.  The SH coefficients are not
+  // read: the forward left, per channel, the colour's gradient in the view
+  // direction and the clamp mask.
   const bool vis = a.tiles[i] != 0;
   const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
-  float c[48];
-  load_sh<DEG>(a.sh, i, n, c);
-  float dir[3], Y[16], rgb[3];
+  float4 J0 = make_float4(0.f, 0.f, 0.f, 0.f), J1 = J0, J2 = J0;
+  if (vis) {
+    J0 = a.colorjac[3 * (size_t)i + 0];
+    J1 = a.colorjac[3 * (size_t)i + 1];
+    J2 = a.colorjac[3 * (size_t)i + 2];
+  }
+  const uint32_t mask = __float_as_uint(J2.y);
+  float dir[3], Y[16];
   double vd[3], vlen;
   view_dir(a.means, i, n, a.v.campos, dir, vd, vlen);
-  sh_color<DEG>(c, dir, rgb, Y);
+  sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
   float gcol[3];
-  for (int ch = 0; ch < 3; ++ch) gcol[ch] = (vis && !(rgb[ch] < 0.0f)) ? grgb[ch] : 0.0f;
-  float wk[16];
+  for (int ch = 0; ch < 3; ++ch) gcol[ch] = (vis && !((mask >> ch) & 1u)) ? grgb[ch] : 0.0f;
 #pragma unroll
-  for (int k = 0; k < nb; ++k) {
-    float w = 0.0f;
+  for (int k = 0; k < nb; ++k)
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      a.g_sh[(size_t)(k * 3 + ch) * n + i] = vis ? Y[k] * gcol[ch] : 0.0f;
-      w += c[k * 3 + ch] * gcol[ch];
-    }
-    wk[k] = w;
-  }
+    for (int ch = 0; ch < 3; ++ch) a.g_sh[(size_t)(k * 3 + ch) * n + i] = Y[k] * gcol[ch];
   double gm[3] = {0.0, 0.0, 0.0};
   if constexpr (DEG > 0) {
-    float gd[3];
-    sh_grad_dir<DEG>(dir[0], dir[1], dir[2], wk, gd);
+    // sum over channels of dL/drgb_c times the colour's gradient in the direction
+    const float gd[3] = {gcol[0] * J0.x + gcol[1] * J0.w + gcol[2] * J1.z,
+                         gcol[0] * J0.y + gcol[1] * J1.x + gcol[2] * J1.w,
+                         gcol[0] * J0.z + gcol[1] * J1.y + gcol[2] * J2.x};
     // d dir / d v = (I - dir dir^T) / |v|
     const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
     for (int e = 0; e < 3; ++e) gm[e] = ((double)gd[e] - (double)dir[e] * dd) / vlen;
@@ -510,6 +525,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
   a.block_tiles = reinterpret_cast<uint32_t*>(ws + L.block_tiles);
   a.splats = reinterpret_cast<float4*>(ws + L.splats);
   a.colors = reinterpret_cast<float4*>(ws + L.colors);
+  a.colorjac = b.count == 1 ? reinterpret_cast<float4*>(ws + L.colorjac) : nullptr;
   a.depth_keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
   a.tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
   a.rects = reinterpret_cast<uint2*>(ws + L.rects);
@@ -575,6 +591,7 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.v = v;
   a.tiles = reinterpret_cast<const uint32_t*>(ws + L.tiles);
   a.grad2d = reinterpret_cast<const float*>(ws + L.grad2d);
+  a.colorjac = reinterpret_cast<const float4*>(ws + L.colorjac);
   a.g_means = out.means;
   a.g_scales = out.scales;
   a.g_quats = out.quats;

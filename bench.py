@@ -44,10 +44,8 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * N
     if name == "depth_sort_hist":
         return 4.0 * N
-    if name == "reach":  # ids, splat records and tile counts in; reach records and counts out
-        return 76.0 * V
-    if name == "duplicate":  # ids, rects, offsets and reach records in; K pairs out
-        return 48.0 * V + 8.0 * K
+    if name == "duplicate":  # K pairs out (the rows' offsets, ids and columns are read once per row)
+        return 8.0 * K
     if name == "tile_sort_hist":
         return 4.0 * K
     if name == "tile_sort_scatter":

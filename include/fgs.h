@@ -132,16 +132,17 @@ typedef struct fgs_layout {
   size_t rects;        /* uint32 [n][2]: x0 | y0 << 16, x1 | y1 << 16 (half-open) */
   size_t radii;        /* int32 [n]: screen radius ceil(3 sqrt(lambda_max)), 0 if culled */
   size_t depth_order;  /* uint32 [n]: Gaussian ids sorted by (depth, id), culled last */
-  size_t offsets;      /* uint32 [n]: exclusive scan of tiles in depth order */
+  size_t offsets;      /* uint32 [n]: exclusive scan, in depth order, of the tile rows each
+                          visible Gaussian is binned over */
   size_t tile_keys;    /* uint32 [K]: sorted tile id per intersection */
   size_t tile_ids;     /* uint32 [K]: Gaussian id per sorted intersection */
   size_t ranges;       /* uint32 [tiles][2]: [start, end) of each tile's run */
   size_t grad2d;       /* float [9][n]: backward scratch (dL/d mu_p xy, conic A B C, opacity, rgb) */
   size_t pixel_T;      /* float [H][W]: final transmittance (FGS_SAVE_PIXEL_STATE) */
   size_t pixel_last;   /* uint32 [H][W]: 1 + list index of the last blended Gaussian */
-  size_t counters;     /* uint32 [16]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view,
+  size_t counters;     /* uint32 [18]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view,
                           [11] / [12] smallest / largest depth key of a visible entry,
-                          [14..15] K as a uint64 */
+                          [14..15] K as a uint64, [16..17] tile rows binned as a uint64 */
 } fgs_layout;
 
 /* Library version string (static storage). */

@@ -73,8 +73,6 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.drx_b = take(nv * 4);
   L.dry_b = take(nv * 4);
   L.offsets = take(nv * 4);
-  L.reach = take(nv * 2 * sizeof(float4));
-  L.counts = take(nv * 4);
   L.grad2d = take(nn * 9 * 4);
   L.ranges = take((size_t)L.total_tiles * 8);
   L.pixel_T = take((size_t)L.total_pixels * 4);
@@ -84,14 +82,15 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   const int64_t nb_max = std::max(radix_blocks((int64_t)nv, 3), radix_blocks(kk, 1));
   // radix histograms; before the depth sort also the compaction's per-block
   // stats (one uint4 per 256 entries)
-  L.hist = take(std::max((size_t)nb_max * kRadix * 4, (size_t)ceil_div((int64_t)nv, kBlock) * 16));
-  const int64_t scan_items = std::max<int64_t>({(int64_t)nv, nb_max * kRadix});
+  L.hist = take(std::max((size_t)nb_max * kRadix * 4, (size_t)ceil_div((int64_t)nv, kBlock) * 32));
+  const int64_t scan_items = std::max<int64_t>({(int64_t)nv, kk, nb_max * kRadix});
   L.partials = take((size_t)(ceil_div(scan_items, kItemsPerBlock) + 1) * 4);
   L.tkeys_a = take((size_t)kk * 4);
   L.tvals_a = take((size_t)kk * 4);
   L.tkeys_b = take((size_t)kk * 4);
   L.tvals_b = take((size_t)kk * 4);
   L.colorjac = take(nn * 3 * sizeof(float4));
+  L.row_off = take((size_t)kk * 4);
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
@@ -256,9 +255,9 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible, U(L.offsets),
                       s),
           "visibility scan");
-  HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects), U(L.offsets), nv,
-                         U(L.dkeys_a), U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters,
-                         reinterpret_cast<uint4*>(hist), s),
+  HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects),
+                         reinterpret_cast<const float4*>(ws + L.splats), tight, U(L.offsets), nv, U(L.dkeys_a),
+                         U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters, reinterpret_cast<uint4*>(hist), s),
           "compact");
   uint32_t host_counters[kNumCounters];
   HIP_TRY(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s), "read counts");
@@ -271,10 +270,19 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
     for (int v = 0; v < nviews; ++v) k_views[v] = nviews == 1 ? (int64_t)K64 : (int64_t)host_counters[kCountViewK + v];
   if (K64 > 0x7FFFFFFFull) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 intersections");
   const int64_t K = (int64_t)K64;
-  if (K > L.kcap) {
+  // the rows to bin share the intersection capacity (they are fewer with
+  // tight binning unless most rows keep no tile; never more with rect binning)
+  uint64_t R64;
+  std::memcpy(&R64, &host_counters[kCountRows64], sizeof(R64));
+  if (R64 > 0x7FFFFFFFull) return fail(FGS_ERR_OVERFLOW, "more than 2^31-1 rows to bin");
+  const int64_t R = (int64_t)R64;
+  if (K > L.kcap || R > L.kcap) {
+    const int64_t need = std::max(K, R);
+    if (k_total) *k_total = need;
+    if (k_views && nviews == 1) k_views[0] = need;
     char msg[160];
     std::snprintf(msg, sizeof(msg), "workspace holds %lld intersections, %lld needed", (long long)L.kcap,
-                  (long long)K);
+                  (long long)need);
     return fail(FGS_ERR_WORKSPACE, msg);
   }
   // depth sort of the V visible entries carrying (id, rect); digits over
@@ -295,16 +303,21 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint32_t* d_ry = odd ? U(L.dry_b) : U(L.dry_a);
   if (odd && V > 0)
     HIP_TRY(hipMemcpyAsync(U(L.dvals_a), d_ids, (size_t)V * 4, hipMemcpyDeviceToDevice, s), "depth order");
-  // per depth-ordered entry: reach parameters and kept-tile count, then the
-  // pair offsets as the exclusive scan of the counts
-  float4* reach = reinterpret_cast<float4*>(ws + L.reach);
-  HIP_TRY(launch_reach(d_ids, reinterpret_cast<const float4*>(ws + L.splats), U(L.tiles), V, tight, reach,
-                       U(L.counts), s),
-          "reach");
-  HIP_TRY(launch_scan(U(L.counts), nullptr, nullptr, V, kScanPlain, partials, counters + kCountK, U(L.offsets), s),
-          "tile count scan");
-  HIP_TRY(launch_duplicate(d_ids, d_rx, d_ry, U(L.offsets), nullptr, V, K, b, n, L.tile_bits, reach, hist,
-                           U(L.tkeys_a), U(L.tvals_a), s),
+  // binning by rows: the depth-ordered entries' rows to bin (offsets = the
+  // exclusive scan of their row ranges), each row's kept columns, the rows'
+  // pair offsets (exclusive scan of their counts; total K), then the pairs.
+  // The rows' Gaussian ids and (y, first column) sit in the tile sort's
+  // second buffers, which the sort first writes after the duplication.
+  uint32_t* row_g = U(L.tvals_b);
+  uint32_t* row_yc = U(L.tkeys_b);
+  HIP_TRY(launch_scan(d_rx, d_ry, nullptr, V, kScanRows, partials, nullptr, U(L.offsets), s), "row scan");
+  HIP_TRY(launch_rows(d_ids, d_rx, d_ry, U(L.offsets), V, R, reinterpret_cast<const float4*>(ws + L.splats), tight,
+                      U(L.row_off), row_g, row_yc, s),
+          "rows");
+  HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s),
+          "row count scan");
+  HIP_TRY(launch_duplicate(U(L.row_off), row_g, row_yc, R, K, b, n, L.tile_bits, hist, U(L.tkeys_a), U(L.tvals_a),
+                           s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
   HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, true),

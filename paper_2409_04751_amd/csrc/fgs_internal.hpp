@@ -38,6 +38,7 @@ enum ScanMode {
   kScanFlag = 1,      // in_a[i] != 0
   kScanRectArea = 2,  // tile count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
   kScanGather = 3,    // in_b[in_a[i]]
+  kScanRows = 4,      // row count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
 };
 
 // Key / payload planes of a radix sort: input in *_a, scratch in *_b.
@@ -66,7 +67,7 @@ enum KernelId {
   kKPreprocessBackward,
   kKShBackward,
   kKColor,
-  kKReach,
+  kKRows,
   kKNumKernels
 };
 const char* kernel_name(int id);
@@ -98,7 +99,8 @@ enum Counter {
   kCountKeyMin = 3 + kMaxViews,  // smallest depth key of a visible entry
   kCountKeyMax = 4 + kMaxViews,  // largest
   kCountK64 = 14,                // sum of the visible entries' tile counts
-  kNumCounters = 16
+  kCountRows64 = 16,             // sum of the visible entries' row ranges (rows to bin)
+  kNumCounters = 18
 };
 static_assert(kCountKeyMax < kCountK64, "counter slots overlap");
 
@@ -117,7 +119,9 @@ struct Layout {
   size_t colorjac;  // single view: float4 [n][3], d rgb / d view direction per channel + clamp mask
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
-  size_t reach, counts;  // per depth-ordered visible entry: reach parameters (2 float4), kept-tile count
+  size_t row_off;  // [kcap]: per binned row its kept-tile count, then their exclusive scan
+  // the rows' Gaussian and (y << 16 | first column) live in tvals_b / tkeys_b
+  // until the tile sort needs them
   size_t hist, partials, block_tiles;
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
   int tile_bits = 0, tile_passes = 0;
@@ -180,32 +184,36 @@ hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int
 int radix_passes(int bits);
 int64_t radix_blocks(int64_t max_count, int payload);
 
-// Visible Gaussians (tiles > 0) in id order: key, id and rect planes at
-// position pos[i] (exclusive scan of the visibility flags).  Also stores
-// the visible entries' total tile count in counters[kCountK64] (u64) and
-// their depth-key range in counters[kCountKeyMin / kCountKeyMax], through
-// block_stats (one uint4 per 256 entries, scratch).
-hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
-                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters,
-                          uint4* block_stats, hipStream_t s);
+// Visible Gaussians (tiles > 0) in id order: key, id and row-range planes
+// at position pos[i] (exclusive scan of the visibility flags).  The planes
+// hold the rect's columns and the rows that can hold a kept tile: with
+// tight binning the rect rows the splat's reach ellipse spans (plus a row
+// of margin each side), else all of them.  Also stores the visible entries'
+// total tile count in counters[kCountK64] (u64), their total row count in
+// counters[kCountRows64] (u64) and their depth-key range in
+// counters[kCountKeyMin / kCountKeyMax], through block_stats (two uint4 per
+// 256 entries, scratch).
+hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const float4* splats,
+                          bool tight, const uint32_t* pos, int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx,
+                          uint32_t* ry, uint32_t* counters, uint4* block_stats, hipStream_t s);
 
-// One (tile, id) pair per covered tile of each depth-ordered visible
-// Gaussian (ids, rect planes rx / ry), at the exclusive-scan offsets; K
-// pairs in total.  Also writes the first-pass digit histogram of the tile
-// sort (tile_bits key bits) into hist.
-// Ids are view-major (view * n + Gaussian); the pair's key is the view's
-// tile_base plus the tile index inside the view.
-// Per depth-ordered visible entry j (ids[j]): its reach parameters (two
-// float4, from the splat record; the whole rect unless tight) and its tile
-// count tiles[ids[j]], both contiguous in j for the duplication.
-hipError_t launch_reach(const uint32_t* ids, const float4* splats, const uint32_t* tiles, int64_t V, bool tight,
-                        float4* reach, uint32_t* counts, hipStream_t s);
+// Rows to bin, one thread each: row t of depth-ordered entry j (row_base[j]
+// = exclusive scan of its row-range heights) gets its kept columns
+// [c0, c1) -- with tight binning from reach_row on the splat record, else the
+// whole rect row -- as row_cnt[t] = c1 - c0, row_g[t] = Gaussian (entry) id,
+// row_yc[t] = y << 16 | c0.
+hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base, int64_t V,
+                       int64_t R, const float4* splats, bool tight, uint32_t* row_cnt, uint32_t* row_g,
+                       uint32_t* row_yc, hipStream_t s);
 
-// Emits every kept tile of each depth-ordered entry (its reach parameters
-// from launch_reach).
-hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
-                            const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, const float4* reach, uint32_t* hist, uint32_t* out_keys,
+// One (tile, id) pair per kept tile of each row, at the row's offset
+// row_off[t] (exclusive scan of the counts); K pairs in total, in depth
+// order.  Also writes the first-pass digit histogram of the tile sort
+// (tile_bits key bits) into hist.  Ids are view-major (view * n +
+// Gaussian); the pair's key is the view's tile_base plus the tile index
+// inside the view.
+hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc, int64_t R,
+                            int64_t K, const ViewBatch& b, int64_t n, int tile_bits, uint32_t* hist, uint32_t* out_keys,
                             uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);

@@ -77,6 +77,7 @@ __device__ inline uint32_t scan_value(const ScanIn& in, uint32_t idx) {
     return ((b & 0xFFFFu) - (a & 0xFFFFu)) * ((b >> 16) - (a >> 16));
   }
   if (MODE == kScanGather) return in.b[in.a[idx]];
+  if (MODE == kScanRows) return (in.b[idx] >> 16) - (in.a[idx] >> 16);
   return in.a[idx];
 }
 
@@ -138,7 +139,14 @@ __device__ inline void load16(const ScanIn& in, uint32_t idx, uint32_t count, ui
       av[4 * q + 2] = v.z;
       av[4 * q + 3] = v.w;
     }
-    if (MODE == kScanRectArea) {
+    if (MODE == kScanRows) {
+      const uint4* b4 = reinterpret_cast<const uint4*>(in.b + idx);
+      for (int q = 0; q < 4; ++q) {
+        const uint4 v = b4[q];
+        const uint32_t bv[4] = {v.x, v.y, v.z, v.w};
+        for (int r = 0; r < 4; ++r) vals[4 * q + r] = (bv[r] >> 16) - (av[4 * q + r] >> 16);
+      }
+    } else if (MODE == kScanRectArea) {
       const uint4* b4 = reinterpret_cast<const uint4*>(in.b + idx);
       for (int q = 0; q < 4; ++q) {
         const uint4 v = b4[q];
@@ -343,72 +351,94 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
 // single-block pass folds them afterwards (thousands of blocks on three
 // addresses would serialise as global atomics).
 __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* tiles, const uint32_t* depth_keys,
-                                                         const uint2* rects, const uint32_t* pos, uint32_t n,
-                                                         uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry,
-                                                         uint4* block_stats) {
-  __shared__ unsigned long long s_k;
+                                                         const uint2* rects, const float4* splats, int tight,
+                                                         const uint32_t* pos, uint32_t n, uint32_t* keys, uint32_t* ids,
+                                                         uint32_t* rx, uint32_t* ry, uint4* block_stats) {
+  __shared__ unsigned long long s_k, s_r;
   __shared__ uint32_t s_min, s_max;
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (threadIdx.x == 0) {
-    s_k = 0;
+    s_k = s_r = 0;
     s_min = 0xFFFFFFFFu;
     s_max = 0u;
   }
   __syncthreads();
   const uint32_t nt = i < n ? tiles[i] : 0u;
-  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, ksum = 0u;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, ksum = 0u, rsum = 0u;
   if (nt != 0) {
     const uint32_t p = pos[i];
     const uint2 r = rects[i];
     const uint32_t key = depth_keys[i];
+    uint32_t ya = r.x >> 16, yb = r.y >> 16;
+    if (tight) {
+      // the rows the reach ellipse spans, a row of margin each side: a row
+      // outside them is empty for reach_row (its dy range misses [-ry, ry])
+      const SplatReach sr = splat_reach(splats[2 * (size_t)i], splats[2 * (size_t)i + 1]);
+      if (sr.kind == 1) {
+        const float fy0 = (float)ya, fy1 = (float)yb;
+        const float lo = floorf((sr.my - sr.ry - kReachPad - 15.0f) * (1.0f / 16.0f)) - 1.0f;
+        const float hi = floorf((sr.my + sr.ry + kReachPad) * (1.0f / 16.0f)) + 2.0f;
+        ya = (uint32_t)fminf(fmaxf(lo, fy0), fy1);
+        yb = (uint32_t)fminf(fmaxf(hi, fy0), fy1);
+      }
+    }
     keys[p] = key;
     ids[p] = i;
-    rx[p] = r.x;
-    ry[p] = r.y;
+    rx[p] = (r.x & 0xFFFFu) | (ya << 16);
+    ry[p] = (r.y & 0xFFFFu) | (yb << 16);
     kmin = kmax = key;
     ksum = nt;
+    rsum = yb - ya;
   }
-  unsigned long long k64 = ksum;  // a u32 per entry: block sums fit 64 bits
+  unsigned long long k64 = ksum, r64 = rsum;  // u32 per entry: block sums fit 64 bits
   for (int d = 32; d >= 1; d >>= 1) {
     k64 += __shfl_xor(k64, d, 64);
+    r64 += __shfl_xor(r64, d, 64);
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
     kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, 64));
   }
   if ((threadIdx.x & 63) == 0 && k64 != 0) {
     atomicAdd(&s_k, k64);
+    atomicAdd(&s_r, r64);
     atomicMin(&s_min, kmin);
     atomicMax(&s_max, kmax);
   }
   __syncthreads();
-  if (threadIdx.x == 0) block_stats[blockIdx.x] = make_uint4((uint32_t)s_k, (uint32_t)(s_k >> 32), s_min, s_max);
+  if (threadIdx.x == 0) {
+    block_stats[2 * blockIdx.x] = make_uint4((uint32_t)s_k, (uint32_t)(s_k >> 32), s_min, s_max);
+    block_stats[2 * blockIdx.x + 1] = make_uint4((uint32_t)s_r, (uint32_t)(s_r >> 32), 0u, 0u);
+  }
 }
 
 constexpr int kStatsThreads = 1024;
 __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4* block_stats, uint32_t nblocks,
                                                                      uint32_t* counters) {
-  __shared__ unsigned long long s_k;
+  __shared__ unsigned long long s_k, s_r;
   __shared__ uint32_t s_min, s_max;
   if (threadIdx.x == 0) {
-    s_k = 0;
+    s_k = s_r = 0;
     s_min = 0xFFFFFFFFu;
     s_max = 0u;
   }
   __syncthreads();
-  unsigned long long k64 = 0;
+  unsigned long long k64 = 0, r64 = 0;
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
   for (uint32_t b = threadIdx.x; b < nblocks; b += kStatsThreads) {
-    const uint4 st = block_stats[b];
+    const uint4 st = block_stats[2 * b], sr = block_stats[2 * b + 1];
     k64 += (unsigned long long)st.x | ((unsigned long long)st.y << 32);
+    r64 += (unsigned long long)sr.x | ((unsigned long long)sr.y << 32);
     kmin = min(kmin, st.z);
     kmax = max(kmax, st.w);
   }
   for (int d = 32; d >= 1; d >>= 1) {
     k64 += __shfl_xor(k64, d, 64);
+    r64 += __shfl_xor(r64, d, 64);
     kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, d, 64));
     kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d, 64));
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(&s_k, k64);
+    atomicAdd(&s_r, r64);
     atomicMin(&s_min, kmin);
     atomicMax(&s_max, kmax);
   }
@@ -416,6 +446,8 @@ __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4
   if (threadIdx.x == 0) {
     counters[kCountK64] = (uint32_t)s_k;
     counters[kCountK64 + 1] = (uint32_t)(s_k >> 32);
+    counters[kCountRows64] = (uint32_t)s_r;
+    counters[kCountRows64 + 1] = (uint32_t)(s_r >> 32);
     counters[kCountKeyMin] = s_min;
     counters[kCountKeyMax] = s_max;
   }
@@ -455,7 +487,8 @@ __device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32
     const uint32_t step = (hi - lo + 63u) / 64u;
     const uint32_t idx = lo + lane * step;
     const uint64_t m = __ballot(idx < hi && a[idx] <= x);
-    const uint32_t nle = (uint32_t)__builtin_popcountll(m);  // >= 1: a[lo] <= x
+    const uint32_t nle = (uint32_t)__builtin_popcountll(m);  // >= 1 when a[lo] <= x
+    if (nle == 0u) break;  // a[lo] > x: outside the contract; stop at lo rather than leave [lo, hi)
     const uint32_t nlo = lo + (nle - 1u) * step;
     hi = min(hi, lo + nle * step);
     lo = nlo;
@@ -465,74 +498,20 @@ __device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32
 
 __device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
 
-// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts of
-// 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from outside the
-// row add 0), then the row totals broadcast from lane 15 into row 1 and 3
-// and from lane 31 into rows 2 and 3.
-template <int CTRL, int ROW_MASK>
-__device__ inline uint32_t dpp_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
-}
-__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
-  v += dpp_u32<0x111, 0xF>(v);  // row_shr:1
-  v += dpp_u32<0x112, 0xF>(v);  // row_shr:2
-  v += dpp_u32<0x114, 0xF>(v);  // row_shr:4
-  v += dpp_u32<0x118, 0xF>(v);  // row_shr:8
-  v += dpp_u32<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-  v += dpp_u32<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
-  return v;
-}
-
-// Per depth-ordered visible entry: reach parameters and kept-tile count,
-// contiguous in j, so that the duplication reads one record per Gaussian
-// with no dependent gather.
-// Per depth-ordered visible entry: reach parameters and kept-tile count,
-// contiguous in j, so that the duplication reads one record per Gaussian
-// with no dependent gather.
-__global__ __launch_bounds__(kBlock) void reach_kernel(const uint32_t* ids, const float4* splats, const uint32_t* tiles,
-                                                       uint32_t V, int tight, float4* reach, uint32_t* counts) {
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= V) return;
-  const uint32_t g = ids[j];
-  SplatReach r;
-  if (tight) {
-    r = splat_reach(splats[2 * (size_t)g], splats[2 * (size_t)g + 1]);
-  } else {
-    r.mx = r.my = r.Pa = r.da = r.beta = r.ry = r.ds = 0.0f;
-    r.kind = 2;
-  }
-  float4 p0, p1;
-  pack_reach(r, p0, p1);
-  reach[2 * (size_t)j] = p0;
-  reach[2 * (size_t)j + 1] = p1;
-  counts[j] = tiles[g];
-}
-
-// Each thread emits 16 consecutive slots: it finds the Gaussian of its first
-// slot in the LDS copy of the offsets, then walks that Gaussian's kept tiles
-// row by row (the columns reach_row keeps, or the whole rect) and moves on to
-// the next Gaussian at its offset.  The slots are staged in LDS and written
-// coalesced.
-__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
-                                                           const uint32_t* offsets, const uint32_t* d_count,
-                                                           uint32_t max_count, uint32_t K, TileMap map,
-                                                           int digit_bits, uint32_t nblocks, const float4* reach,
-                                                           uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals) {
-  __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
-  __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
-  __shared__ uint32_t s_off[kDupItems];  // offsets of the Gaussians that own this block's slots
-  __shared__ uint32_t s_hist[kRadix];
+// Rows to bin, one thread each (see launch_rows).  The block's rows belong
+// to at most kBlock entries (each entry has at least one row), whose row
+// bases it copies to LDS for a short binary search.
+__global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
+                                                      const uint32_t* row_base, uint32_t V, uint32_t R,
+                                                      const float4* splats, int tight, uint32_t* row_cnt,
+                                                      uint32_t* row_g, uint32_t* row_yc) {
+  __shared__ uint32_t s_base[kBlock];
   __shared__ uint32_t s_first, s_count;
-  const uint32_t V = item_count(d_count, max_count);
-  const uint32_t o_begin = blockIdx.x * kDupItems;
-  const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
-  const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
-  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
+  const uint32_t t0 = blockIdx.x * kBlock;
+  const uint32_t t1 = min(t0 + (uint32_t)kBlock, R);
   if (threadIdx.x < 64) {
-    // the Gaussians owning slots [o_begin, o_end): first .. last, at most
-    // kDupItems of them (every visible Gaussian owns at least one slot)
-    const uint32_t first = wave_search_le(offsets, 0u, V, o_begin);
-    const uint32_t last = wave_search_le(offsets, first, min(V, first + (uint32_t)kDupItems), o_end - 1u);
+    const uint32_t first = wave_search_le(row_base, 0u, V, t0);
+    const uint32_t last = wave_search_le(row_base, first, min(V, first + (uint32_t)kBlock), t1 - 1u);
     if (threadIdx.x == 0) {
       s_first = first;
       s_count = last - first + 1u;
@@ -540,138 +519,100 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* ids, 
   }
   __syncthreads();
   const uint32_t first = s_first, m = s_count;
-  for (uint32_t t = threadIdx.x; t < m; t += kBlock) s_off[t] = offsets[first + t];
+  if (threadIdx.x < m) s_base[threadIdx.x] = row_base[first + threadIdx.x];
   __syncthreads();
+  const uint32_t t = t0 + threadIdx.x;
+  if (t >= R) return;
+  uint32_t lo = 0, hi = m;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_base[mid] <= t) lo = mid; else hi = mid;
+  }
+  const uint32_t j = first + lo;
+  const uint32_t g = ids[j], a = rx[j], b = ry[j];
+  const int x0 = (int)(a & 0xFFFFu), x1 = (int)(b & 0xFFFFu);
+  const int y = (int)(a >> 16) + (int)(t - s_base[lo]);
+  int c0 = x0, c1 = x1;
+  if (tight) reach_row(splat_reach(splats[2 * (size_t)g], splats[2 * (size_t)g + 1]), y, x0, x1, c0, c1);
+  row_cnt[t] = (uint32_t)(c1 - c0);
+  row_g[t] = g;
+  row_yc[t] = ((uint32_t)y << 16) | (uint32_t)c0;
+}
+
+// Each thread emits 16 consecutive slots: it finds the row of its first slot
+// (the last row whose offset is <= the slot: rows without a kept tile share
+// the next row's offset) and emits that row's tiles, moving to the next
+// non-empty row at its offset.  The row offsets of the block's slots are
+// staged in LDS (up to kDupItems rows; rows beyond come from memory).  The
+// slots are staged in LDS and written coalesced.
+__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_off, const uint32_t* row_g,
+                                                           const uint32_t* row_yc, uint32_t R, uint32_t K, TileMap map,
+                                                           int digit_bits, uint32_t nblocks, uint32_t* hist,
+                                                           uint32_t* out_keys, uint32_t* out_vals) {
+  __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
+  __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
+  __shared__ uint32_t s_off[kDupItems];  // offsets of the rows that own this block's slots
+  __shared__ uint32_t s_hist[kRadix];
+  __shared__ uint32_t s_first, s_count;
+  const uint32_t o_begin = blockIdx.x * kDupItems;
+  const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
+  const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
+  if (threadIdx.x < 64) {
+    const uint32_t first = wave_search_le(row_off, 0u, R, o_begin);
+    const uint32_t last = wave_search_le(row_off, first, min(R, first + (uint32_t)kDupItems), o_end - 1u);
+    if (threadIdx.x == 0) {
+      s_first = first;
+      s_count = last - first + 1u;
+    }
+  }
+  __syncthreads();
+  const uint32_t first = s_first, m = s_count;
+  for (uint32_t t = threadIdx.x; t < m; t += kBlock) s_off[t] = row_off[first + t];
+  __syncthreads();
+  // offset of row r (K past the last row)
+  auto off_at = [&](uint32_t r) -> uint32_t {
+    return r - first < m ? s_off[r - first] : (r < R ? row_off[r] : K);
+  };
   uint32_t o = o_begin + threadIdx.x * kIptPayload1;
-  const bool active = o < o_end;
-  // this thread's first Gaussian (largest local index with s_off <= o) and
-  // how many of its kept tiles come before slot o
-  uint32_t local = 0, next = 0xFFFFFFFFu, skip = 0;
-  if (active) {
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s_off[mid] <= o) lo = mid; else hi = mid;
+  if (o < o_end) {
+    uint32_t r;
+    if (m < (uint32_t)kDupItems || o < off_at(first + m)) {
+      uint32_t lo = 0, hi = m;  // the table covers o
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= o) lo = mid; else hi = mid;
+      }
+      r = first + lo;
+    } else {  // more rows than the table holds (many empty ones): search memory
+      uint32_t lo = first + m - 1u, hi = R;
+      while (hi - lo > 1) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (row_off[mid] <= o) lo = mid; else hi = mid;
+      }
+      r = lo;
     }
-    local = lo;
-    next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-    skip = o - s_off[local];
-  }
-  // the current Gaussian's kept tiles: row y, columns [c0, c1), at col
-  uint32_t g = 0, tbase = 0, tiles_x = 0;
-  int x0 = 0, x1 = 0, y = 0, y1 = 0, c0 = 0, c1 = 0, col = 0;
-  SplatReach rr;
-  rr.kind = 2;
-  auto load = [&](uint32_t jj) {
-    const uint32_t a = rx[jj], b = ry[jj];
-    g = ids[jj];
-    x0 = (int)(a & 0xFFFFu);
-    y = (int)(a >> 16);
-    x1 = (int)(b & 0xFFFFu);
-    y1 = (int)(b >> 16);
+    uint32_t g = row_g[r], yc = row_yc[r], tbase, tiles_x;
     view_of(map, g, tbase, tiles_x);
-    rr = unpack_reach(reach[2 * (size_t)jj], reach[2 * (size_t)jj + 1]);
-  };
-  // from the current row on, the row holding the skip-th kept tile
-  auto walk = [&](uint32_t sk) {
-    if (rr.kind == 1) {
-      reach_row(rr, y, x0, x1, c0, c1);
-      while (sk >= (uint32_t)(c1 - c0) && y + 1 < y1) {
-        sk -= (uint32_t)(c1 - c0);
-        reach_row(rr, ++y, x0, x1, c0, c1);
-      }
-    } else {  // the whole rect (a kind-0 entry is never visible)
-      const uint32_t w = (uint32_t)(x1 - x0);
-      y += (int)(sk / w);
-      sk -= (sk / w) * w;
-      c0 = x0;
-      c1 = x1;
-    }
-    col = c0 + (int)sk;
-  };
-  // A thread that starts deep inside a Gaussian of many rows would walk
-  // them one reach_row at a time, and its wave would wait for its longest
-  // walk.  Instead the wave evaluates such a Gaussian's rows together, one
-  // per lane, and every lane that starts inside it finds its row in the
-  // prefix sums of the row counts.
-  bool coop = false;
-  if (active) {
-    load(first + local);
-    // only walks of more than about 8 rows: skip rows / count estimates it
-    const uint32_t count = local + 1u < m ? s_off[local + 1u] - s_off[local] : 0xFFFFFFFFu;
-    coop = rr.kind == 1 && skip > 0 && (float)skip * (float)(y1 - y) > 8.0f * (float)count;
-    if (!coop) walk(skip);
-  }
-  const int lane = (int)lane_id();
-  for (uint64_t pending = __ballot(coop); pending != 0; pending = __ballot(coop)) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const uint32_t lj = (uint32_t)__shfl((int)local, leader);
-    SplatReach lr;
-    lr.mx = __shfl(rr.mx, leader);
-    lr.my = __shfl(rr.my, leader);
-    lr.Pa = __shfl(rr.Pa, leader);
-    lr.da = __shfl(rr.da, leader);
-    lr.beta = __shfl(rr.beta, leader);
-    lr.ry = __shfl(rr.ry, leader);
-    lr.ds = __shfl(rr.ds, leader);
-    lr.kind = 1;
-    const int lx0 = __shfl(x0, leader), lx1 = __shfl(x1, leader);
-    const int ly0 = __shfl(y, leader), ly1 = __shfl(y1, leader);
-    const bool mine = coop && local == lj;
-    uint32_t before = 0;  // kept tiles in the rows of earlier chunks
-    for (int base = ly0; base < ly1; base += 64) {
-      const int row = base + lane;
-      int r0 = lx0, r1 = lx0;
-      if (row < ly1) reach_row(lr, row, lx0, lx1, r0, r1);
-      const uint32_t cnt = (uint32_t)(r1 - r0);
-      const uint32_t incl = wave_inclusive_scan(cnt);
-      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-      // every lane searches (the shuffles need the whole wave); only the
-      // lanes that start in this chunk of the leader's Gaussian use it: the
-      // last lane whose exclusive prefix is <= the skip holds the tile
-      // (an empty row shares its prefix with the next, non-empty one)
-      const uint32_t want = skip - before;
-      int p = 0;
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int probe = p + step;
-        const uint32_t ex = (uint32_t)__shfl((int)incl, probe - 1);  // exclusive prefix of lane probe
-        if (ex <= want) p = probe;
-      }
-      const uint32_t exp_ = (uint32_t)__shfl((int)incl, p > 0 ? p - 1 : 0);
-      const int pr0 = __shfl(r0, p), pr1 = __shfl(r1, p);
-      if (mine && coop && skip < before + total) {
-        y = base + p;
-        c0 = pr0;
-        c1 = pr1;
-        col = c0 + (int)(want - (p > 0 ? exp_ : 0u));
-        coop = false;
-      }
-      before += total;
-    }
-    // the leader's Gaussian is done (a skip past its rows cannot happen: the
-    // rows hold exactly its count)
-    coop = coop && local != lj;
-  }
-  if (active) {
-    for (int k = 0; k < kIptPayload1 && o < o_end; ++k, ++o) {
-      if (o == next) {
-        ++local;
-        next = local + 1u < m ? s_off[local + 1u] : 0xFFFFFFFFu;
-        load(first + local);
-        walk(0u);
-      }
-      const uint32_t key = tbase + (uint32_t)y * tiles_x + (uint32_t)col;
+    uint32_t col = (yc & 0xFFFFu) + (o - off_at(r));
+    uint32_t next = off_at(r + 1u);
+    for (int k = 0; k < kIptPayload1 && o < o_end; ++k) {
+      const uint32_t key = tbase + (yc >> 16) * tiles_x + col;
       const uint32_t e = o - o_begin;
       s_keys[pad_index(e)] = key;
       s_vals[pad_index(e)] = g;
       atomicAdd(&s_hist[key & dmask], 1u);
-      if (++col == c1) {  // next row with a kept tile (bounded by the rect)
-        const bool rows = rr.kind == 1;
+      ++o;
+      ++col;
+      if (o == next && o < o_end) {  // the next row with a kept tile
         do {
-          ++y;
-          if (rows) reach_row(rr, y, x0, x1, c0, c1);
-        } while (rows && c1 == c0 && y + 1 < y1);
-        col = c0;
+          ++r;
+          next = off_at(r + 1u);
+        } while (next == o);
+        g = row_g[r];
+        yc = row_yc[r];
+        view_of(map, g, tbase, tiles_x);
+        col = yc & 0xFFFFu;
       }
     }
   }
@@ -794,9 +735,16 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
       hipLaunchKernelGGL(scan_partials_kernel<kScanGather>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
                          (uint32_t)max_count, partials);
       break;
-    default:
+    case kScanRows:
+      hipLaunchKernelGGL(scan_partials_kernel<kScanRows>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
+                         (uint32_t)max_count, partials);
+      break;
+    case kScanPlain:
       hipLaunchKernelGGL(scan_partials_kernel<kScanPlain>, dim3(nb), dim3(kBlock), 0, s, in, d_count,
                          (uint32_t)max_count, partials);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   const bool fused = nb <= kMaxFusedPartials;
   if (!fused) hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBlock), 0, s, partials, nb, total);
@@ -811,6 +759,7 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
     case kScanFlag: FGS_APPLY(kScanFlag) break;
     case kScanRectArea: FGS_APPLY(kScanRectArea) break;
     case kScanGather: FGS_APPLY(kScanGather) break;
+    case kScanRows: FGS_APPLY(kScanRows) break;
     default: FGS_APPLY(kScanPlain) break;
   }
 #undef FGS_APPLY
@@ -834,32 +783,32 @@ hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int
                                           first_hist_ready, key_bias);
 }
 
-hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const uint32_t* pos,
-                          int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters,
-                          uint4* block_stats, hipStream_t s) {
+hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const float4* splats,
+                          bool tight, const uint32_t* pos, int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx,
+                          uint32_t* ry, uint32_t* counters, uint4* block_stats, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   ProfScope prof(s, kKCompact);
   const unsigned blocks = (unsigned)ceil_div(n, kBlock);
-  hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, s, tiles, depth_keys, rects, pos, (uint32_t)n,
-                     keys, ids, rx, ry, block_stats);
+  hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, s, tiles, depth_keys, rects, splats, tight ? 1 : 0,
+                     pos, (uint32_t)n, keys, ids, rx, ry, block_stats);
   hipLaunchKernelGGL(stats_reduce_kernel, dim3(1), dim3(kStatsThreads), 0, s, block_stats, blocks, counters);
   return hipGetLastError();
 }
 
-hipError_t launch_reach(const uint32_t* ids, const float4* splats, const uint32_t* tiles, int64_t V, bool tight,
-                        float4* reach, uint32_t* counts, hipStream_t s) {
-  if (V <= 0) return hipSuccess;
-  ProfScope prof(s, kKReach);
-  hipLaunchKernelGGL(reach_kernel, dim3((unsigned)ceil_div(V, kBlock)), dim3(kBlock), 0, s, ids, splats, tiles,
-                     (uint32_t)V, tight ? 1 : 0, reach, counts);
+hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base, int64_t V,
+                       int64_t R, const float4* splats, bool tight, uint32_t* row_cnt, uint32_t* row_g,
+                       uint32_t* row_yc, hipStream_t s) {
+  if (V <= 0 || R <= 0) return hipSuccess;
+  ProfScope prof(s, kKRows);
+  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)ceil_div(R, kBlock)), dim3(kBlock), 0, s, ids, rx, ry, row_base,
+                     (uint32_t)V, (uint32_t)R, splats, tight ? 1 : 0, row_cnt, row_g, row_yc);
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* offsets,
-                            const uint32_t* d_count, int64_t max_count, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, const float4* reach, uint32_t* hist, uint32_t* out_keys,
+hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc, int64_t R,
+                            int64_t K, const ViewBatch& b, int64_t n, int tile_bits, uint32_t* hist, uint32_t* out_keys,
                             uint32_t* out_vals, hipStream_t s) {
-  if (max_count <= 0 || K <= 0) return hipSuccess;
+  if (R <= 0 || K <= 0) return hipSuccess;
   const int passes = radix_passes(tile_bits);
   const int first_bits = passes > 0 ? (tile_bits + passes - 1) / passes : 0;  // as launch_radix_sort
   const uint32_t nb = (uint32_t)ceil_div(K, kDupItems);
@@ -871,8 +820,8 @@ hipError_t launch_duplicate(const uint32_t* ids, const uint32_t* rx, const uint3
     map.tile_base[v] = v < b.count ? b.v[v].tile_base : 0u;
     map.tiles_x[v] = v < b.count ? (uint32_t)b.v[v].tiles_x : 1u;
   }
-  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, ids, rx, ry, offsets, d_count,
-                     (uint32_t)max_count, (uint32_t)K, map, first_bits, nb, reach, hist, out_keys, out_vals);
+  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, (uint32_t)R, (uint32_t)K,
+                     map, first_bits, nb, hist, out_keys, out_vals);
   return hipGetLastError();
 }
 

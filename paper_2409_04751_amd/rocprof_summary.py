@@ -58,7 +58,7 @@ KERNELS = {
     "color": "::color_kernel<",
     "compact": "::compact_kernel(",
     "depth_sort_scatter": "::radix_scatter_kernel<3,",
-    "reach": "::reach_kernel(",
+    "rows": "::rows_kernel(",
     "duplicate": "::duplicate_kernel(",
     "tile_sort_hist": "::radix_hist_kernel<16>",
     "tile_sort_scatter": "::radix_scatter_kernel<1,",

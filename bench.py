@@ -345,6 +345,8 @@ def main() -> int:
     lay = ws2.layout(scene.n, cam.width, cam.height)
     tiles = ws2.view(lay.tiles, scene.n, torch.int32)
     V = int((tiles > 0).sum().item())
+    cnt = ws2.view(lay.counters, 18, torch.int32).cpu().numpy().view(np.uint32).astype(np.int64)
+    rows_binned = int(cnt[16] + (cnt[17] << 32))
     N, P, S = scene.n, cam.width * cam.height, scene.sh.shape[0]
 
     pairs = None
@@ -406,6 +408,7 @@ def main() -> int:
                data="synthetic",
                config=dict(workload="room3m_fisheye1752x1168_180deg", gaussians=N, sh_degree=3, width=cam.width,
                            height=cam.height, fov_deg=180.0, views_per_step=1, visible=V, intersections=K,
+                           rows_binned=rows_binned,
                            geometry_dtype="f64"),
                roofline=roofline, cpu_baseline=cpu, kernels=kernels,
                ms_per_step_event_profiled=round(ms_profiled, 4) if ms_profiled else None, serving=serving,

@@ -91,6 +91,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.tvals_b = take((size_t)kk * 4);
   L.colorjac = take(nn * 3 * sizeof(float4));
   L.row_off = take((size_t)kk * 4);
+  L.rowrange = take(nv * 4);
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
@@ -256,7 +257,7 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
                       s),
           "visibility scan");
   HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects),
-                         reinterpret_cast<const float4*>(ws + L.splats), tight, U(L.offsets), nv, U(L.dkeys_a),
+                         U(L.rowrange), tight, U(L.offsets), nv, U(L.dkeys_a),
                          U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters, reinterpret_cast<uint4*>(hist), s),
           "compact");
   uint32_t host_counters[kNumCounters];

@@ -120,6 +120,7 @@ struct Layout {
   size_t dkeys_a, dvals_a, dkeys_b, dvals_b, drx_a, dry_a, drx_b, dry_b;
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
   size_t row_off;  // [kcap]: per binned row its kept-tile count, then their exclusive scan
+  size_t rowrange;  // tight binning, [entry]: first | (last + 1) << 16 of the rows with a kept tile
   // the rows' Gaussian and (y << 16 | first column) live in tvals_b / tkeys_b
   // until the tile sort needs them
   size_t hist, partials, block_tiles;
@@ -186,16 +187,17 @@ int64_t radix_blocks(int64_t max_count, int payload);
 
 // Visible Gaussians (tiles > 0) in id order: key, id and row-range planes
 // at position pos[i] (exclusive scan of the visibility flags).  The planes
-// hold the rect's columns and the rows that can hold a kept tile: with
-// tight binning the rect rows the splat's reach ellipse spans (plus a row
-// of margin each side), else all of them.  Also stores the visible entries'
+// hold the rect's columns and the rows to bin: with tight binning those
+// from the first to the last row with a kept tile (rowrange, from the
+// preprocess), else all rows of the rect.  Also stores the visible entries'
 // total tile count in counters[kCountK64] (u64), their total row count in
 // counters[kCountRows64] (u64) and their depth-key range in
 // counters[kCountKeyMin / kCountKeyMax], through block_stats (two uint4 per
 // 256 entries, scratch).
-hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const float4* splats,
-                          bool tight, const uint32_t* pos, int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx,
-                          uint32_t* ry, uint32_t* counters, uint4* block_stats, hipStream_t s);
+hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects,
+                          const uint32_t* rowrange, bool tight, const uint32_t* pos, int64_t n, uint32_t* keys,
+                          uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters, uint4* block_stats,
+                          hipStream_t s);
 
 // Rows to bin, one thread each: row t of depth-ordered entry j (row_base[j]
 // = exclusive scan of its row-range heights) gets its kept columns

@@ -38,6 +38,7 @@ struct PreArgs {
   int32_t* radii;
   uint32_t* block_tiles;  // [view][block] tiles touched (multi-view only)
   int tight;              // count only the tiles the alpha >= 1/255 ellipse reaches
+  uint32_t* rowrange;     // tight: [entry] first | (last + 1) << 16 of the rows with a kept tile
   ViewBatch batch;
 };
 
@@ -228,12 +229,18 @@ __device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_
     if (a.tight) {  // the tiles of the rect the splat's pixels can lie in
       const SplatReach rr = splat_reach(s0, s1);
       area = 0;
+      uint32_t ya = y1, yb = y0;  // rows with a kept tile: [ya, yb)
       for (uint32_t ty = y0; ty < y1; ++ty) {
         int c0, c1;
         reach_row(rr, (int)ty, (int)x0, (int)x1, c0, c1);
         area += (uint32_t)(c1 - c0);
+        if (c1 > c0) {
+          ya = min(ya, ty);
+          yb = ty + 1u;
+        }
       }
       if (area == 0) break;
+      a.rowrange[e] = ya | (yb << 16);
     }
     a.splats[2 * e + 0] = s0;
     a.splats[2 * e + 1] = s1;
@@ -522,6 +529,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
   a.sh_degree = g.sh_degree;
   a.batch = b;
   a.tight = tight ? 1 : 0;
+  a.rowrange = reinterpret_cast<uint32_t*>(ws + L.rowrange);
   a.block_tiles = reinterpret_cast<uint32_t*>(ws + L.block_tiles);
   a.splats = reinterpret_cast<float4*>(ws + L.splats);
   a.colors = reinterpret_cast<float4*>(ws + L.colors);

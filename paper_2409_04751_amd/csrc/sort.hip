@@ -351,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
 // single-block pass folds them afterwards (thousands of blocks on three
 // addresses would serialise as global atomics).
 __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* tiles, const uint32_t* depth_keys,
-                                                         const uint2* rects, const float4* splats, int tight,
+                                                         const uint2* rects, const uint32_t* rowrange, int tight,
                                                          const uint32_t* pos, uint32_t n, uint32_t* keys, uint32_t* ids,
                                                          uint32_t* rx, uint32_t* ry, uint4* block_stats) {
   __shared__ unsigned long long s_k, s_r;
@@ -370,17 +370,10 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* tiles, 
     const uint2 r = rects[i];
     const uint32_t key = depth_keys[i];
     uint32_t ya = r.x >> 16, yb = r.y >> 16;
-    if (tight) {
-      // the rows the reach ellipse spans, a row of margin each side: a row
-      // outside them is empty for reach_row (its dy range misses [-ry, ry])
-      const SplatReach sr = splat_reach(splats[2 * (size_t)i], splats[2 * (size_t)i + 1]);
-      if (sr.kind == 1) {
-        const float fy0 = (float)ya, fy1 = (float)yb;
-        const float lo = floorf((sr.my - sr.ry - kReachPad - 15.0f) * (1.0f / 16.0f)) - 1.0f;
-        const float hi = floorf((sr.my + sr.ry + kReachPad) * (1.0f / 16.0f)) + 2.0f;
-        ya = (uint32_t)fminf(fmaxf(lo, fy0), fy1);
-        yb = (uint32_t)fminf(fmaxf(hi, fy0), fy1);
-      }
+    if (tight) {  // the rows from the first to the last with a kept tile
+      const uint32_t rr = rowrange[i];
+      ya = rr & 0xFFFFu;
+      yb = rr >> 16;
     }
     keys[p] = key;
     ids[p] = i;
@@ -498,20 +491,24 @@ __device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32
 
 __device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
 
-// Rows to bin, one thread each (see launch_rows).  The block's rows belong
-// to at most kBlock entries (each entry has at least one row), whose row
-// bases it copies to LDS for a short binary search.
+// Rows to bin (see launch_rows): a block takes kRowsPerBlock consecutive
+// rows, four per thread, strided so that the stores coalesce.  They belong
+// to at most kRowsPerBlock entries (each entry has at least one row), whose
+// row bases the block copies to LDS for short binary searches; the block's
+// two searches of the row bases in memory are shared by its 1024 rows.
+constexpr int kRowsPerThread = 4;
+constexpr int kRowsPerBlock = kBlock * kRowsPerThread;
 __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
                                                       const uint32_t* row_base, uint32_t V, uint32_t R,
                                                       const float4* splats, int tight, uint32_t* row_cnt,
                                                       uint32_t* row_g, uint32_t* row_yc) {
-  __shared__ uint32_t s_base[kBlock];
+  __shared__ uint32_t s_base[kRowsPerBlock];
   __shared__ uint32_t s_first, s_count;
-  const uint32_t t0 = blockIdx.x * kBlock;
-  const uint32_t t1 = min(t0 + (uint32_t)kBlock, R);
+  const uint32_t t0 = blockIdx.x * kRowsPerBlock;
+  const uint32_t t1 = min(t0 + (uint32_t)kRowsPerBlock, R);
   if (threadIdx.x < 64) {
     const uint32_t first = wave_search_le(row_base, 0u, V, t0);
-    const uint32_t last = wave_search_le(row_base, first, min(V, first + (uint32_t)kBlock), t1 - 1u);
+    const uint32_t last = wave_search_le(row_base, first, min(V, first + (uint32_t)kRowsPerBlock), t1 - 1u);
     if (threadIdx.x == 0) {
       s_first = first;
       s_count = last - first + 1u;
@@ -519,24 +516,27 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
   }
   __syncthreads();
   const uint32_t first = s_first, m = s_count;
-  if (threadIdx.x < m) s_base[threadIdx.x] = row_base[first + threadIdx.x];
+  for (uint32_t k = threadIdx.x; k < m; k += kBlock) s_base[k] = row_base[first + k];
   __syncthreads();
-  const uint32_t t = t0 + threadIdx.x;
-  if (t >= R) return;
-  uint32_t lo = 0, hi = m;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_base[mid] <= t) lo = mid; else hi = mid;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const uint32_t t = t0 + (uint32_t)q * kBlock + threadIdx.x;
+    if (t >= t1) break;
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_base[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t j = first + lo;
+    const uint32_t g = ids[j], a = rx[j], b = ry[j];
+    const int x0 = (int)(a & 0xFFFFu), x1 = (int)(b & 0xFFFFu);
+    const int y = (int)(a >> 16) + (int)(t - s_base[lo]);
+    int c0 = x0, c1 = x1;
+    if (tight) reach_row(splat_reach(splats[2 * (size_t)g], splats[2 * (size_t)g + 1]), y, x0, x1, c0, c1);
+    row_cnt[t] = (uint32_t)(c1 - c0);
+    row_g[t] = g;
+    row_yc[t] = ((uint32_t)y << 16) | (uint32_t)c0;
   }
-  const uint32_t j = first + lo;
-  const uint32_t g = ids[j], a = rx[j], b = ry[j];
-  const int x0 = (int)(a & 0xFFFFu), x1 = (int)(b & 0xFFFFu);
-  const int y = (int)(a >> 16) + (int)(t - s_base[lo]);
-  int c0 = x0, c1 = x1;
-  if (tight) reach_row(splat_reach(splats[2 * (size_t)g], splats[2 * (size_t)g + 1]), y, x0, x1, c0, c1);
-  row_cnt[t] = (uint32_t)(c1 - c0);
-  row_g[t] = g;
-  row_yc[t] = ((uint32_t)y << 16) | (uint32_t)c0;
 }
 
 // Each thread emits 16 consecutive slots: it finds the row of its first slot
@@ -783,13 +783,14 @@ hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int
                                           first_hist_ready, key_bias);
 }
 
-hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects, const float4* splats,
-                          bool tight, const uint32_t* pos, int64_t n, uint32_t* keys, uint32_t* ids, uint32_t* rx,
-                          uint32_t* ry, uint32_t* counters, uint4* block_stats, hipStream_t s) {
+hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects,
+                          const uint32_t* rowrange, bool tight, const uint32_t* pos, int64_t n, uint32_t* keys,
+                          uint32_t* ids, uint32_t* rx, uint32_t* ry, uint32_t* counters, uint4* block_stats,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   ProfScope prof(s, kKCompact);
   const unsigned blocks = (unsigned)ceil_div(n, kBlock);
-  hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, s, tiles, depth_keys, rects, splats, tight ? 1 : 0,
+  hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, s, tiles, depth_keys, rects, rowrange, tight ? 1 : 0,
                      pos, (uint32_t)n, keys, ids, rx, ry, block_stats);
   hipLaunchKernelGGL(stats_reduce_kernel, dim3(1), dim3(kStatsThreads), 0, s, block_stats, blocks, counters);
   return hipGetLastError();
@@ -800,7 +801,7 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
                        uint32_t* row_yc, hipStream_t s) {
   if (V <= 0 || R <= 0) return hipSuccess;
   ProfScope prof(s, kKRows);
-  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)ceil_div(R, kBlock)), dim3(kBlock), 0, s, ids, rx, ry, row_base,
+  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)ceil_div(R, kRowsPerBlock)), dim3(kBlock), 0, s, ids, rx, ry, row_base,
                      (uint32_t)V, (uint32_t)R, splats, tight ? 1 : 0, row_cnt, row_g, row_yc);
   return hipGetLastError();
 }

@@ -54,7 +54,8 @@ def counter_means(path: str, kernel_substr: str, counter: str) -> tuple[float, i
 # profiler kernel names of the library's kernels, as they appear (demangled)
 # in rocprofv3 output, keyed by the names the library's event profiler uses
 KERNELS = {
-    "preprocess": "::preprocess_kernel(",
+    "preprocess": "::preprocess_fused_kernel<",
+    "preprocess_batch": "::preprocess_kernel<",
     "color": "::color_kernel<",
     "compact": "::compact_kernel(",
     "depth_sort_scatter": "::radix_scatter_kernel<3,",
@@ -66,7 +67,7 @@ KERNELS = {
     "blend_forward": "::blend_forward_kernel(",
     "blend_backward": "::blend_backward_kernel(",
     "sh_backward": "::sh_backward_kernel<",
-    "preprocess_backward": "::geometry_backward_kernel(",
+    "preprocess_backward": "::geometry_backward_kernel<",
 }
 
 

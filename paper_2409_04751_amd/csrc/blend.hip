@@ -111,14 +111,14 @@ constexpr int kPairThreads = 128;
 constexpr int kPairChunk = kPairThreads;
 
 struct HalfLists {
-  uint8_t idx[2][kPairChunk];
-  uint32_t wcount[2][2];  // [staging wave][half]
+  uint8_t idx[2][kPairChunk];  // [half][position]: staged entry, in entry order
+  uint32_t wcount[2][2];       // [staging wave][half]
 };
 
 // Per-half lists of the staged entries, in entry order; called by all threads
 // after thread t staged entry t with half mask m (0 for no entry); returns
-// the length of the calling wave's list.  Contains the barriers that publish
-// the staged records too.
+// the length of the calling wave's list (wave-uniform).  Contains the
+// barriers that publish the staged records too.
 __device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint64_t bal0 = __ballot(m & 1u), bal1 = __ballot((m >> 1) & 1u);
@@ -131,7 +131,73 @@ __device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
   if (m & 2u) Q.idx[1][(wave ? Q.wcount[0][1] : 0u) + lanes_below(bal1)] = (uint8_t)threadIdx.x;
   const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave]);
   __syncthreads();
-  return n;
+  return __builtin_amdgcn_readfirstlane(n);
+}
+
+// Walks the calling wave's list (forward or reverse entry order) and calls
+// body(entry, a, b, c) per listed entry until it returns true.  The list is
+// read four indices per LDS word, and the next entry's staged records are
+// fetched before the body of the current one runs, so the body does not wait
+// on a chain of dependent LDS reads.  Index and records are wave-uniform.
+template <bool kReverse, bool kColor, class Body>
+__device__ inline void walk_half_list(const HalfLists& Q, uint32_t wave, int cnt, const float4* sa,
+                                      const float4* sb, const float2* sc, Body&& body) {
+  if (cnt <= 0) return;
+  const uint32_t* words = reinterpret_cast<const uint32_t*>(Q.idx[wave]);
+  int j = kReverse ? cnt - 1 : 0;
+  uint32_t word = __builtin_amdgcn_readfirstlane(words[j >> 2]);
+  // the word of the next group of four, fetched one group ahead
+  const int jg = kReverse ? (j >> 2) - 1 : (j >> 2) + 1;
+  uint32_t word_next = (jg >= 0 && 4 * jg < cnt) ? words[jg] : 0u;
+  int idx = (int)((word >> (8 * (j & 3))) & 0xFFu);
+  float4 na = sa[idx], nb = sb[idx];
+  float2 nc = kColor ? sc[idx] : make_float2(0.0f, 0.0f);
+  for (int step = 0; step < cnt; ++step) {
+    const int cur = idx;
+    const float4 ga = na, gb = nb;
+    const float2 gc = nc;
+    if (step + 1 < cnt) {
+      const int jn = kReverse ? j - 1 : j + 1;
+      if ((jn >> 2) != (j >> 2)) {
+        word = __builtin_amdgcn_readfirstlane(word_next);
+        const int g2 = kReverse ? (jn >> 2) - 1 : (jn >> 2) + 1;
+        word_next = (g2 >= 0 && 4 * g2 < cnt) ? words[g2] : 0u;
+      }
+      j = jn;
+      idx = (int)((word >> (8 * (j & 3))) & 0xFFu);
+      na = sa[idx];
+      nb = sb[idx];
+      if (kColor) nc = sc[idx];
+    }
+    if (body(cur, ga, gb, gc)) break;
+  }
+}
+
+// Front-to-back step of one pixel, branch-free: a pixel that is done, or that
+// the splat does not reach (alpha < 1/255), or that the splat would take
+// below the transmittance floor (which makes it done) adds w = 0 and keeps
+// T and last, exactly as if it had been skipped.  The blend backward's
+// re-sweep runs the same arithmetic, so T and last agree bit for bit.
+template <bool kColorAcc>
+__device__ inline void front_step(float fi, float fj, const float4& ga, const float4& gb, const float2& gc,
+                                  uint32_t index, bool& done, float& T, uint32_t& last, float& C0, float& C1,
+                                  float& C2) {
+  float dx, dy, t;
+  const float q2 = exponent2(ga, gb, fi, fj, dx, dy, t);
+  const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
+  const float tn = T * (1.0f - alpha);
+  const bool pass = !done && q2 >= gb.y;
+  const bool stop = tn < kTmin;
+  const bool blend = pass && !stop;
+  done = done || (pass && stop);
+  if (kColorAcc) {
+    const float w = blend ? alpha * T : 0.0f;
+    C0 = __builtin_fmaf(gb.w, w, C0);
+    C1 = __builtin_fmaf(gc.x, w, C1);
+    C2 = __builtin_fmaf(gc.y, w, C2);
+  }
+  T = blend ? tn : T;
+  last = blend ? index + 1u : last;
 }
 
 // One block per tile of every view of the batch (tiles are numbered view by
@@ -177,31 +243,17 @@ __global__ __launch_bounds__(kPairThreads) void blend_forward_kernel(BlendArgs a
       m = half_mask(ta, tb);
     }
     const int cnt = build_half_lists(m, Q);
-    if (!(done[0] && done[1])) {
-      for (int jj = 0; jj < cnt; ++jj) {
-        const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
-        const float4 ga = sa[e], gb = sb[e];
+    if (__ballot(!(done[0] && done[1])) != 0ull) {
+      const uint32_t first = base - r.x;
+      walk_half_list<false, true>(Q, wave, cnt, sa, sb, sc,
+                                  [&](int e, const float4& ga, const float4& gb, const float2& gc) {
+                                    const uint32_t index = first + (uint32_t)e;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          float dx, dy, t;
-          const float q2 = exponent2(ga, gb, fi, fj[q], dx, dy, t);
-          if (done[q] || !(q2 >= gb.y)) continue;
-          const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
-          const float tn = T[q] * (1.0f - alpha);
-          if (tn < kTmin) {
-            done[q] = true;
-            continue;
-          }
-          const float2 gc = sc[e];
-          const float w = alpha * T[q];
-          C0[q] = __builtin_fmaf(gb.w, w, C0[q]);
-          C1[q] = __builtin_fmaf(gc.x, w, C1[q]);
-          C2[q] = __builtin_fmaf(gc.y, w, C2[q]);
-          T[q] = tn;
-          last[q] = base - r.x + (uint32_t)e + 1u;
-        }
-        if (done[0] && done[1]) break;
-      }
+                                    for (int q = 0; q < 2; ++q)
+                                      front_step<true>(fi, fj[q], ga, gb, gc, index, done[q], T[q], last[q], C0[q],
+                                                       C1[q], C2[q]);
+                                    return __ballot(!(done[0] && done[1])) == 0ull;
+                                  });
     }
   }
   const size_t hw = (size_t)vp.width * vp.height;
@@ -290,21 +342,6 @@ struct BwdPixel {
   float B0, B1, B2;    // colour behind the current splat
 };
 
-// Front-to-back step of the re-sweep, with the forward's arithmetic.
-__device__ inline void resweep_step(BwdPixel& px, bool& done, const float4& ga, const float4& gb, uint32_t index) {
-  float dx, dy, t;
-  const float q2 = exponent2(ga, gb, px.fi, px.fj, dx, dy, t);
-  if (done || !(q2 >= gb.y)) return;
-  const float alpha = fminf(kAlphaMax, gb.z * __builtin_amdgcn_exp2f(q2));
-  const float tn = px.T * (1.0f - alpha);
-  if (tn < kTmin) {
-    done = true;
-    return;
-  }
-  px.T = tn;
-  px.last = index + 1u;
-}
-
 // Reverse step for one pixel, adding its 9 gradient terms to v.  One path
 // for every lane: a pixel the splat does not reach takes alpha = 0, which
 // leaves its transmittance and colour-behind exactly unchanged and adds
@@ -348,7 +385,7 @@ __device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx,
 __constant__ const float kGradScale[9] = {1.3862943611198906f, 1.3862943611198906f, -0.5f, -1.0f, -0.5f,
                                           1.0f, 1.0f, 1.0f, 1.0f};
 
-__global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdArgs a) {
+__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(7))) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ float4 sa[kPairChunk];
   __shared__ float4 sb[kPairChunk];
   __shared__ float2 sc[kPairChunk];
@@ -397,15 +434,18 @@ __global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdAr
         m = half_mask(ta, tb);
       }
       const int cnt = build_half_lists(m, Q);
-      if (!(done0 && done1)) {
-        for (int jj = 0; jj < cnt; ++jj) {
-          const int e = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
-          const float4 ga = sa[e], gb = sb[e];
-          const uint32_t index = base - r.x + (uint32_t)e;
-          resweep_step(P[0], done0, ga, gb, index);
-          resweep_step(P[1], done1, ga, gb, index);
-          if (done0 && done1) break;
-        }
+      if (__ballot(!(done0 && done1)) != 0ull) {
+        const uint32_t first = base - r.x;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;  // unused: the re-sweep accumulates no colour
+        walk_half_list<false, false>(Q, wave, cnt, sa, sb, sc,
+                                     [&](int e, const float4& ga, const float4& gb, const float2& gc) {
+                                       const uint32_t index = first + (uint32_t)e;
+                                       front_step<false>(P[0].fi, P[0].fj, ga, gb, gc, index, done0, P[0].T,
+                                                         P[0].last, c0, c1, c2);
+                                       front_step<false>(P[1].fi, P[1].fj, ga, gb, gc, index, done1, P[1].T,
+                                                         P[1].last, c0, c1, c2);
+                                       return __ballot(!(done0 && done1)) == 0ull;
+                                     });
       }
     }
   }
@@ -452,26 +492,25 @@ __global__ __launch_bounds__(kPairThreads) void blend_backward_kernel(BlendBwdAr
     }
     for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
     const int cnt = build_half_lists(m, Q);
-    for (int jj = cnt - 1; jj >= 0; --jj) {
-      const int idx = __builtin_amdgcn_readfirstlane(Q.idx[wave][jj]);
-      const uint32_t e = (uint32_t)(beg + idx);
-      if (e >= wlast) continue;  // past every pixel of this wave
-      const float4 ga = sa[idx], gb = sb[idx];
-      float dx0, dy0, t0, dx1, dy1, t1;
-      const float q20 = exponent2(ga, gb, P[0].fi, P[0].fj, dx0, dy0, t0);
-      const float q21 = exponent2(ga, gb, P[1].fi, P[1].fj, dx1, dy1, t1);
-      const bool pass0 = e < P[0].last && q20 >= gb.y;
-      const bool pass1 = e < P[1].last && q21 >= gb.y;
-      if (__ballot(pass0 || pass1) == 0ull) continue;  // wave-uniform
-      const float2 gc = sc[idx];
-      float v[9];
-      for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-      reverse_step(P[0], pass0, q20, dx0, dy0, t0, ga, gb, gc, v);
-      reverse_step(P[1], pass1, q21, dx1, dy1, t1, ga, gb, gc, v);
-      // wave-uniform: every lane takes part in the DPP exchanges
-      const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
-      if (rvalid) atomicAdd(&acc[rval][idx], part);
-    }
+    walk_half_list<true, true>(Q, wave, cnt, sa, sb, sc,
+                               [&](int idx, const float4& ga, const float4& gb, const float2& gc) {
+                                 const uint32_t e = (uint32_t)(beg + idx);
+                                 if (e >= wlast) return false;  // past every pixel of this wave
+                                 float dx0, dy0, t0, dx1, dy1, t1;
+                                 const float q20 = exponent2(ga, gb, P[0].fi, P[0].fj, dx0, dy0, t0);
+                                 const float q21 = exponent2(ga, gb, P[1].fi, P[1].fj, dx1, dy1, t1);
+                                 const bool pass0 = e < P[0].last && q20 >= gb.y;
+                                 const bool pass1 = e < P[1].last && q21 >= gb.y;
+                                 if (__ballot(pass0 || pass1) == 0ull) return false;  // wave-uniform
+                                 float v[9];
+                                 for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+                                 reverse_step(P[0], pass0, q20, dx0, dy0, t0, ga, gb, gc, v);
+                                 reverse_step(P[1], pass1, q21, dx1, dy1, t1, ga, gb, gc, v);
+                                 // wave-uniform: every lane takes part in the DPP exchanges
+                                 const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
+                                 if (rvalid) atomicAdd(&acc[rval][idx], part);
+                                 return false;
+                               });
     __syncthreads();
     if ((int)threadIdx.x < end - beg) {
       const uint32_t g = sid[threadIdx.x];

@@ -491,7 +491,16 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(7)
       m = half_mask(ta, tb);
     }
     for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
-    const int cnt = build_half_lists(m, Q);
+    int cnt = build_half_lists(m, Q);
+    {
+      // the list is in entry order: only its prefix below this wave's last
+      // contributor serves a pixel, so the reverse walk starts there
+      const int lim = (int)wlast - beg;
+      const uint8_t* li = Q.idx[wave];
+      const bool below0 = (int)lane < cnt && (int)li[lane] < lim;
+      const bool below1 = (int)lane + 64 < cnt && (int)li[lane + 64] < lim;
+      cnt = __builtin_popcountll(__ballot(below0)) + __builtin_popcountll(__ballot(below1));
+    }
     walk_half_list<true, true>(Q, wave, cnt, sa, sb, sc,
                                [&](int idx, const float4& ga, const float4& gb, const float2& gc) {
                                  const uint32_t e = (uint32_t)(beg + idx);

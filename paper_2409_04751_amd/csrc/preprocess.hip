@@ -197,59 +197,147 @@ __global__ __launch_bounds__(kBlock) void view_sums_kernel(const uint32_t* block
   if (threadIdx.x == 0) out[blockIdx.x] = s_sum;
 }
 
+// Tiles that reach_row keeps over the tile rows [y0, y0 + nr) of each
+// lane's splat, and the first and last of those rows with a kept tile, for a
+// whole wave: the wave's (lane, row) pairs are dealt out 64 at a time, so a
+// lane with a tall rect (the large splats) does not hold up the other 63.
+// Every lane of the wave takes part; lanes without rows pass nr = 0.  The
+// per-row evaluation is reach_row on the owner's own values, so the counts
+// equal the per-lane loop's (and the duplication's) exactly.
+struct RowCountLds {
+  uint32_t count[64], first[64], end[64];  // per lane of the wave
+};
+
+// Orders the LDS accesses of one wave's lanes: what a lane wrote before it
+// is visible to every lane of the wave after it (the wave executes in lock
+// step; the fences keep the compiler from reordering or forwarding).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t wave_bcast_u32(uint32_t v, uint32_t src) { return (uint32_t)__shfl((int)v, (int)src, 64); }
+__device__ inline float wave_bcast_f32(float v, uint32_t src) { return __shfl(v, (int)src, 64); }
+
+__device__ inline void wave_count_rows(const SplatReach& rr, uint32_t nr, uint32_t x0, uint32_t x1, uint32_t y0,
+                                       RowCountLds& L, uint32_t& area, uint32_t& ya, uint32_t& yb) {
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t incl = nr;  // inclusive prefix sum of nr over the wave
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+    if (lane >= (uint32_t)d) incl += t;
+  }
+  const uint32_t excl = incl - nr;
+  const uint32_t total = __builtin_amdgcn_readfirstlane(wave_bcast_u32(incl, 63u));
+  L.count[lane] = 0u;
+  L.first[lane] = 0xFFFFFFFFu;
+  L.end[lane] = 0u;
+  wave_sync();
+  const float kind = (float)rr.kind;
+  for (uint32_t base = 0; base < total; base += 64u) {
+    // owner of pair base + lane: the last lane whose pairs start at or
+    // before it (the exclusive prefixes do not decrease over the lanes, and
+    // a later lane without rows starts past it)
+    const uint32_t item = base + lane;
+    uint32_t own = 0;
+    for (uint32_t step = 32; step >= 1; step >>= 1) {
+      const uint32_t probe = own + step;
+      if (wave_bcast_u32(excl, probe) <= item) own = probe;
+    }
+    SplatReach ro;
+    ro.mx = wave_bcast_f32(rr.mx, own);
+    ro.my = wave_bcast_f32(rr.my, own);
+    ro.Pa = wave_bcast_f32(rr.Pa, own);
+    ro.da = wave_bcast_f32(rr.da, own);
+    ro.beta = wave_bcast_f32(rr.beta, own);
+    ro.ry = wave_bcast_f32(rr.ry, own);
+    ro.ds = wave_bcast_f32(rr.ds, own);
+    ro.kind = (int)wave_bcast_f32(kind, own);
+    const uint32_t ox0 = wave_bcast_u32(x0, own), ox1 = wave_bcast_u32(x1, own);
+    const uint32_t oy0 = wave_bcast_u32(y0, own), oexcl = wave_bcast_u32(excl, own);
+    if (item < total) {
+      const uint32_t ty = oy0 + (item - oexcl);
+      int c0, c1;
+      reach_row(ro, (int)ty, (int)ox0, (int)ox1, c0, c1);
+      if (c1 > c0) {
+        atomicAdd(&L.count[own], (uint32_t)(c1 - c0));
+        atomicMin(&L.first[own], ty);
+        atomicMax(&L.end[own], ty + 1u);
+      }
+    }
+  }
+  wave_sync();
+  area = L.count[lane];
+  ya = L.first[lane];
+  yb = L.end[lane];
+}
+
 // Geometry of entry e = (view vi, Gaussian i): cull, project, conic, radius,
 // tile rect, depth key.  A culled entry writes only its tile count (0) and an
-// all-ones depth key.  Returns the tile count.
+// all-ones depth key.  Returns the tile count.  Every lane of the wave calls
+// it (the tight tile count is shared across the wave); lanes past the last
+// Gaussian pass active = false and write nothing.
 template <int MC>
-__device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_t i, size_t e) {
+__device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_t i, size_t e, bool active,
+                                          RowCountLds& L) {
   const uint32_t n = a.n;
   const ViewParams& vp = a.batch.v[vi];
-  uint32_t key = 0xFFFFFFFFu, ntiles = 0;
-  Geometry G;
-  do {
-    if (!compute_geometry<MC>(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) break;
-    const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
-    const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
-    double rad = ceil(3.0 * sqrt(lam));
-    if (rad > kMaxRadius) rad = kMaxRadius;
-    const double gx = vp.tiles_x, gy = vp.tiles_y;
-    const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
-    const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile),
-                 vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
-    const uint32_t x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx), y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
-    const uint32_t x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx), y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
-    uint32_t area = (x1 - x0) * (y1 - y0);
-    if (area == 0) break;
-    const float o = a.opac[i];
-    const double A = G.conic[0], B = G.conic[1];
-    const float hx = (float)G.mu[0], hy = (float)G.mu[1];
-    const float4 s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-    const float4 s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
-                                  (float)(-log2(255.0 * (double)o)));
-    if (a.tight) {  // the tiles of the rect the splat's pixels can lie in
-      const SplatReach rr = splat_reach(s0, s1);
-      area = 0;
-      uint32_t ya = y1, yb = y0;  // rows with a kept tile: [ya, yb)
-      for (uint32_t ty = y0; ty < y1; ++ty) {
-        int c0, c1;
-        reach_row(rr, (int)ty, (int)x0, (int)x1, c0, c1);
-        area += (uint32_t)(c1 - c0);
-        if (c1 > c0) {
-          ya = min(ya, ty);
-          yb = ty + 1u;
-        }
+  bool keep = false;
+  uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, area = 0;
+  float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+  double rad = 0.0, dist = 0.0;
+  if (active) {
+    Geometry G;
+    if (compute_geometry<MC>(a.means, a.scales, a.quats, a.opac, i, n, vp, false, G)) {
+      const double mid = 0.5 * (G.Sp[0] + G.Sp[2]);
+      const double lam = mid + sqrt(fmax(0.1, mid * mid - G.det));
+      rad = ceil(3.0 * sqrt(lam));
+      if (rad > kMaxRadius) rad = kMaxRadius;
+      const double gx = vp.tiles_x, gy = vp.tiles_y;
+      const double vx0 = floor((G.mu[0] - rad) / kTile), vy0 = floor((G.mu[1] - rad) / kTile);
+      const double vx1 = floor((G.mu[0] + rad + (kTile - 1)) / kTile),
+                   vy1 = floor((G.mu[1] + rad + (kTile - 1)) / kTile);
+      x0 = (uint32_t)fmin(fmax(vx0, 0.0), gx);
+      y0 = (uint32_t)fmin(fmax(vy0, 0.0), gy);
+      x1 = (uint32_t)fmin(fmax(vx1, 0.0), gx);
+      y1 = (uint32_t)fmin(fmax(vy1, 0.0), gy);
+      area = (x1 - x0) * (y1 - y0);
+      if (area != 0) {
+        keep = true;
+        const float o = a.opac[i];
+        const double A = G.conic[0], B = G.conic[1];
+        const float hx = (float)G.mu[0], hy = (float)G.mu[1];
+        s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
+        s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
+                         (float)(-log2(255.0 * (double)o)));
+        dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
       }
-      if (area == 0) break;
-      a.rowrange[e] = ya | (yb << 16);
     }
+  }
+  if (a.tight) {  // the tiles of the rect the splat's pixels can lie in
+    SplatReach rr;
+    if (keep) {
+      rr = splat_reach(s0, s1);
+    } else {
+      rr.mx = rr.my = rr.Pa = rr.da = rr.beta = rr.ry = rr.ds = 0.0f;
+      rr.kind = 0;
+    }
+    uint32_t ya = 0, yb = 0;
+    wave_count_rows(rr, keep ? y1 - y0 : 0u, x0, x1, y0, L, area, ya, yb);
+    if (keep && area == 0) keep = false;
+    if (keep) a.rowrange[e] = ya | (yb << 16);
+  }
+  if (!active) return 0;
+  uint32_t key = 0xFFFFFFFFu, ntiles = 0;
+  if (keep) {
     a.splats[2 * e + 0] = s0;
     a.splats[2 * e + 1] = s1;
     a.rects[e] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
     a.radii[e] = (int32_t)rad;
-    const double dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
     key = __float_as_uint((float)dist);
     ntiles = area;
-  } while (false);
+  }
   a.depth_keys[e] = key;
   a.tiles[e] = ntiles;
   return ntiles;
@@ -289,9 +377,9 @@ __device__ inline uint32_t entry_color(const PreArgs& a, uint32_t vi, uint32_t i
 // only for the Gaussians the view keeps).
 template <int DEG, int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_fused_kernel(PreArgs a) {
+  __shared__ RowCountLds rows_lds[kBlock / 64];
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
-  const uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i);
+  const uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i, i < a.n, rows_lds[threadIdx.x >> 6]);
   if (ntiles == 0) return;
   float c[48];
   load_sh<DEG>(a.sh, i, a.n, c);
@@ -312,10 +400,10 @@ __device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i
 
 template <int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
+  __shared__ RowCountLds rows_lds[kBlock / 64];
   uint32_t vi, i;
   entry_of_block((uint32_t)a.batch.count, vi, i);
-  if (i >= a.n) return;
-  entry_geometry<MC>(a, vi, i, (size_t)vi * a.n + i);
+  entry_geometry<MC>(a, vi, i, (size_t)vi * a.n + i, i < a.n, rows_lds[threadIdx.x >> 6]);
 }
 
 // Also leaves each block's tile total in block_tiles[view][block] (a plain

@@ -69,6 +69,18 @@ def test_backward_unnormalised_quaternions_ragged():
     _check(scene, _posed(2), cam)
 
 
+def test_backward_long_unsaturated_lists():
+    """Faint splats: pixels stay above the transmittance floor for hundreds
+    of entries, so the backward's re-sweep and reverse pass both span many
+    staged chunks of the tile lists (the opaque scenes finish in the first)."""
+    scene = synth.room_scene(30_000, 9, 0.01, 1)
+    scene.opacity = np.random.default_rng(5).uniform(0.01, 0.04, scene.n).astype(np.float32)
+    cam = synth.fisheye_camera(96, 64, 190.0)
+    pose = synth.identity_pose()
+    assert oracle.render(scene, pose, cam)["last"].max() > 4 * 128
+    _check(scene, pose, cam, bg=(0.2, 0.1, 0.0))
+
+
 def test_saved_state_matches_recompute():
     """The backward that reads the forward's saved per-pixel T and last
     contributor equals the one that recomputes them."""

@@ -211,7 +211,7 @@ def serving_train_bench(n: int, rate: float, count: int, train_seconds: float):
 
     def train_view(k):
         img = R.rasterize(*leaves, 3, poses[k % len(poses)], cam, (0.0, 0.0, 0.0), ws)
-        loss = (img - targets[k % 4]).abs().mean()
+        loss = R.l1_loss(img, targets[k % 4])
         loss.backward()
 
     def optimizer_step():
@@ -309,7 +309,7 @@ def main() -> int:
 
     def step():
         img = R.rasterize(*leaves, deg, pose, cam, bg, ws)
-        loss = (img - target).abs().mean()
+        loss = R.l1_loss(img, target)
         grads = torch.autograd.grad(loss, leaves)
         return loss, grads
 

@@ -226,6 +226,29 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
                         void* stream);
 
 /*
+ * L1 photometric loss of a rendered image against a target, the L1 term of
+ * the 3DGS objective the paper trains with (Sec. 5.1):
+ *   L = (1 / count) sum_j |image_j - target_j|,
+ *   dL/dimage_j = sign(image_j - target_j) * dL_dloss[0] / count
+ * (sign 0 where the two are equal; the quotient dL_dloss[0] / count is
+ * rounded once to float, then multiplied by the sign).
+ *
+ * fgs_l1_loss: image, target device float32 [count] (any layout, the same
+ * for both), 16-byte aligned; partials device scratch of FGS_L1_PARTIALS
+ * doubles (caller-owned, overwritten); loss device float32 scalar, written
+ * as the mean.  The sum runs in double over a fixed grid, so the loss is
+ * bit-deterministic.
+ * fgs_l1_loss_backward: dL_dloss device float32 scalar (the upstream
+ * gradient); dL_dimage device float32 [count], 16-byte aligned, overwritten.
+ * Both only enqueue work on the stream.  FGS_ERR_ARG for a null pointer,
+ * count <= 0 or a misaligned image; FGS_ERR_OVERFLOW past 2^31 - 1 values.
+ */
+#define FGS_L1_PARTIALS 1024
+int fgs_l1_loss(const float* image, const float* target, int64_t count, double* partials, float* loss, void* stream);
+int fgs_l1_loss_backward(const float* image, const float* target, int64_t count, const float* dL_dloss,
+                         float* dL_dimage, void* stream);
+
+/*
  * Per-kernel timing with HIP events, for benchmarks and tracing.  While
  * enabled, every kernel launch of the library is bracketed by two events
  * recorded on the stream it is launched on; fgs_profile_read waits for the

@@ -26,6 +26,7 @@ FGS_MODEL_STEREOGRAPHIC = 5
 FGS_SAVE_PIXEL_STATE = 1
 FGS_RECT_BINNING = 2
 FGS_MAX_BATCH = 8
+FGS_L1_PARTIALS = 1024
 
 c_size = ctypes.c_size_t
 
@@ -90,6 +91,10 @@ SIGNATURES = {
                                   ctypes.POINTER(fgs_camera), ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, c_size,
                                   ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p], ctypes.c_int),
+    "fgs_l1_loss": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p], ctypes.c_int),
+    "fgs_l1_loss_backward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p], ctypes.c_int),
     "fgs_profile_enable": ([ctypes.c_int32], ctypes.c_int),
     "fgs_profile_read": ([ctypes.POINTER(fgs_profile)], ctypes.c_int),
 }
@@ -183,6 +188,14 @@ def fgs_render_forward_batch(g: fgs_gaussians, poses, cams, bgs, workspace: int,
     rc = lib().fgs_render_forward_batch(ctypes.byref(g), nv, P, C, B, workspace, workspace_bytes, O, kv,
                                         ctypes.byref(kt), stream)
     return rc, [int(x) for x in kv], int(kt.value)
+
+
+def fgs_l1_loss(image: int, target: int, count: int, partials: int, loss: int, stream: int) -> None:
+    check(lib().fgs_l1_loss(image, target, count, partials, loss, stream))
+
+
+def fgs_l1_loss_backward(image: int, target: int, count: int, dL_dloss: int, dL_dimage: int, stream: int) -> None:
+    check(lib().fgs_l1_loss_backward(image, target, count, dL_dloss, dL_dimage, stream))
 
 
 def fgs_profile_enable(on: bool) -> None:

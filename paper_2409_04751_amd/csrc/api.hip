@@ -245,8 +245,7 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint32_t* partials = U(L.partials);
   uint32_t* hist = U(L.hist);
 
-  HIP_TRY(launch_fill_u32(counters, 0u, kNumCounters, s), "clear counters");
-  HIP_TRY(launch_fill_u32(counters + kCountFlags, flags, 1, s), "store flags");
+  HIP_TRY(launch_clear_but_one(counters, kNumCounters, kCountFlags, flags, s), "clear counters, store flags");
   const bool tight = (flags & FGS_RECT_BINNING) == 0;
   HIP_TRY(launch_preprocess(*g, b, tight, ws, L, s), "preprocess");
   // stable compaction of the visible (view, Gaussian) entries; offsets holds
@@ -435,3 +434,28 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
 }
 
 }  // extern "C"
+
+namespace {
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+}  // namespace
+
+extern "C" int fgs_l1_loss(const float* image, const float* target, int64_t count, double* partials, float* loss,
+                           void* stream) {
+  if (!image || !target || !partials || !loss || count <= 0) return fail(FGS_ERR_ARG, "fgs_l1_loss: bad argument");
+  if (count > 0x7FFFFFFFll) return fail(FGS_ERR_OVERFLOW, "fgs_l1_loss: more than 2^31 - 1 values");
+  if (!aligned16(image) || !aligned16(target)) return fail(FGS_ERR_ARG, "fgs_l1_loss: images must be 16-byte aligned");
+  const hipError_t e = launch_l1_loss(image, target, count, partials, loss, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_l1_loss");
+}
+
+extern "C" int fgs_l1_loss_backward(const float* image, const float* target, int64_t count, const float* dL_dloss,
+                                    float* dL_dimage, void* stream) {
+  if (!image || !target || !dL_dloss || !dL_dimage || count <= 0)
+    return fail(FGS_ERR_ARG, "fgs_l1_loss_backward: bad argument");
+  if (count > 0x7FFFFFFFll) return fail(FGS_ERR_OVERFLOW, "fgs_l1_loss_backward: more than 2^31 - 1 values");
+  if (!aligned16(image) || !aligned16(target) || !aligned16(dL_dimage))
+    return fail(FGS_ERR_ARG, "fgs_l1_loss_backward: images must be 16-byte aligned");
+  const hipError_t e =
+      launch_l1_grad(image, target, count, dL_dloss, dL_dimage, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_l1_loss_backward");
+}

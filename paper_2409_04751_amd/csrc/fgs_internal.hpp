@@ -68,6 +68,7 @@ enum KernelId {
   kKShBackward,
   kKColor,
   kKRows,
+  kKLoss,
   kKNumKernels
 };
 const char* kernel_name(int id);
@@ -222,6 +223,9 @@ hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, 
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 
+// p[0 .. count) = 0 except p[at] = v, in one launch
+hipError_t launch_clear_but_one(uint32_t* p, int64_t count, int64_t at, uint32_t v, hipStream_t s);
+
 hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
                                 const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
                                 uint32_t* pixel_last,
@@ -235,5 +239,12 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
 
 hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& v, const char* ws,
                                       const Layout& L, const fgs_grads& out, hipStream_t s);
+
+// L1 loss of an image against a target (FGS_L1_PARTIALS block partials, then
+// the mean into *loss) and its gradient sign(image - target) * dl[0] / count.
+hipError_t launch_l1_loss(const float* image, const float* target, int64_t count, double* partials, float* loss,
+                          hipStream_t s);
+hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, const float* dl, float* out,
+                          hipStream_t s);
 
 }  // namespace fgs

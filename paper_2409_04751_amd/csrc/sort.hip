@@ -659,6 +659,13 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, uint32_t 
   if (j < count) p[j] = v;
 }
 
+// p[0 .. count) = 0 except p[at] = v
+__global__ __launch_bounds__(kBlock) void fill_u32_but_one_kernel(uint32_t* p, uint32_t count, uint32_t at,
+                                                                  uint32_t v) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < count) p[j] = j == at ? v : 0u;
+}
+
 template <int P, int IPT>
 hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                            uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
@@ -707,6 +714,14 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
 }
 
 }  // namespace
+
+hipError_t launch_clear_but_one(uint32_t* p, int64_t count, int64_t at, uint32_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  ProfScope prof(s, kKFill);
+  hipLaunchKernelGGL(fill_u32_but_one_kernel, dim3((unsigned)ceil_div(count, kBlock)), dim3(kBlock), 0, s, p,
+                     (uint32_t)count, (uint32_t)at, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;

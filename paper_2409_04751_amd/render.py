@@ -156,3 +156,37 @@ def rasterize(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg
     """Differentiable fisheye render of one view, [3, H, W]."""
     return _FisheyeRasterize.apply(means, scales, quats, opacities, sh, sh_degree, pose, cam, tuple(bg),
                                    workspace if workspace is not None else Workspace(means.device))
+
+
+class _L1Loss(torch.autograd.Function):
+    """mean |image - target| in the library's kernels: one deterministic
+    two-stage sum forward, one streaming pass for the gradient."""
+
+    @staticmethod
+    def forward(ctx, image, target):
+        for t in (image, target):
+            if not t.is_contiguous() or t.dtype != torch.float32 or not t.is_cuda:
+                raise ValueError("l1_loss takes contiguous float32 device tensors")
+        if image.shape != target.shape:
+            raise ValueError("l1_loss: image and target differ in shape")
+        dev = image.device
+        partials = torch.empty(L.FGS_L1_PARTIALS, dtype=torch.float64, device=dev)
+        loss = torch.empty((), dtype=torch.float32, device=dev)
+        L.fgs_l1_loss(image.data_ptr(), target.data_ptr(), image.numel(), partials.data_ptr(), loss.data_ptr(),
+                      _stream_handle(dev))
+        ctx.save_for_backward(image, target)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        image, target = ctx.saved_tensors
+        g = g.to(torch.float32).contiguous()
+        out = torch.empty_like(image)
+        L.fgs_l1_loss_backward(image.data_ptr(), target.data_ptr(), image.numel(), g.data_ptr(), out.data_ptr(),
+                               _stream_handle(image.device))
+        return out, None
+
+
+def l1_loss(image: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """L1 photometric loss (mean absolute difference), differentiable in image."""
+    return _L1Loss.apply(image, target)

@@ -68,6 +68,7 @@ KERNELS = {
     "blend_backward": "::blend_backward_kernel(",
     "sh_backward": "::sh_backward_kernel<",
     "preprocess_backward": "::geometry_backward_kernel<",
+    "loss": "::l1_",
 }
 
 

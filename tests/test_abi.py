@@ -96,3 +96,12 @@ def test_backward_rejects_null_gradients():
     grads = L.fgs_grads(None, None, None, None, None, None)
     rc = L.fgs_render_backward(g, pose, cam, (0, 0, 0), 1, 1 << 30, 1, grads, 0)
     assert rc == L.FGS_ERR_ARG
+
+
+def test_l1_loss_rejects_bad_arguments_without_launching():
+    # null pointers and empty sizes are caught on the host
+    assert L.lib().fgs_l1_loss(None, None, 16, None, None, None) == L.FGS_ERR_ARG
+    assert L.lib().fgs_l1_loss_backward(None, None, 0, None, None, None) == L.FGS_ERR_ARG
+    # misaligned (host-side pointer arithmetic only; nothing is dereferenced)
+    assert L.lib().fgs_l1_loss(16, 17, 16, 32, 48, None) == L.FGS_ERR_ARG
+    assert L.lib().fgs_l1_loss(16, 32, 1 << 31, 48, 64, None) == L.FGS_ERR_OVERFLOW

@@ -1,0 +1,53 @@
+"""The library's L1 loss: the gradient bit for bit against sign(C - T) times
+the correctly rounded quotient of the upstream gradient and the element
+count (fp64 on the host), and within one ulp of torch's float32 autograd of
+mean |C - T| (which may multiply by a rounded reciprocal instead); the loss
+to the rounding of a float sum; image sizes with and without a ragged
+float4 tail."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2409_04751_amd import render as R  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape", [(3, 37, 53), (3, 64, 96), (3, 1168, 1752), (1, 1, 1)])
+@pytest.mark.parametrize("upstream", [1.0, -3.5])
+def test_l1_loss_matches_torch(shape, upstream):
+    print(f"case shape={shape} upstream={upstream}", flush=True)
+    rng = np.random.default_rng(sum(shape))
+    img = rng.uniform(0, 1, shape).astype(np.float32)
+    tgt = rng.uniform(0, 1, shape).astype(np.float32)
+    eq = rng.random(shape) < 0.05
+    tgt[eq] = img[eq]  # exact ties: zero gradient there
+    a = torch.from_numpy(img).cuda().requires_grad_(True)
+    b = torch.from_numpy(img).cuda().requires_grad_(True)
+    t = torch.from_numpy(tgt).cuda()
+    ours = R.l1_loss(a, t)
+    ref = (b - t).abs().mean()
+    (ours * upstream).backward()
+    (ref * upstream).backward()
+    torch.cuda.synchronize()
+    exact = np.abs(img.astype(np.float64) - tgt.astype(np.float64)).mean()
+    assert abs(float(ours.detach()) - exact) <= 1e-6 * max(exact, 1e-30)
+    q = np.float32(np.float64(np.float32(upstream)) / np.float64(img.size))
+    want = np.sign(img - tgt).astype(np.float32) * q
+    got = a.grad.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert np.array_equal(np.signbit(got[want == 0]), np.signbit(want[want == 0]))
+    ref_g = b.grad.cpu().numpy()
+    assert np.all(np.abs(got - ref_g) <= np.abs(ref_g) * 2.0 ** -23)
+    assert int((a.grad == 0).sum()) >= int(eq.sum())
+
+
+def test_l1_loss_is_deterministic():
+    print("case determinism 3x1168x1752", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    img = torch.rand((3, 1168, 1752), device="cuda", generator=g)
+    tgt = torch.rand((3, 1168, 1752), device="cuda", generator=g)
+    vals = [R.l1_loss(img, tgt) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(v, vals[0]) for v in vals)

@@ -100,8 +100,9 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
     fisheye_terms(G.P, need_m);
     if (!(G.P.theta <= v.theta_max)) return false;
     if (G.P.lz > 0.0) {
-      G.mu[0] = v.cx + v.fx * G.P.theta * x / G.P.lz;
-      G.mu[1] = v.cy + v.fy * G.P.theta * y / G.P.lz;
+      const double t = G.P.theta / G.P.lz;
+      G.mu[0] = v.cx + v.fx * t * x;
+      G.mu[1] = v.cy + v.fy * t * y;
     } else {
       G.mu[0] = v.cx;
       G.mu[1] = v.cy;
@@ -115,7 +116,8 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   }
   // Sigma = M M^T, M = R S
   G.qnorm = sqrt(q2);
-  for (int a = 0; a < 4; ++a) G.qn[a] = (double)qf[a] / G.qnorm;
+  const double iq = 1.0 / G.qnorm;
+  for (int a = 0; a < 4; ++a) G.qn[a] = (double)qf[a] * iq;
   quat_to_rot(G.qn, G.Rq);
   for (int a = 0; a < 3; ++a) G.s[a] = (double)sf[a];
   double M[9];
@@ -143,9 +145,10 @@ __device__ inline bool compute_geometry(const float* means, const float* scales,
   G.Sp[2] = TS[3] * G.T[3] + TS[4] * G.T[4] + TS[5] * G.T[5] + kDilation;
   G.det = G.Sp[0] * G.Sp[2] - G.Sp[1] * G.Sp[1];
   if (!(G.det > 0.0)) return false;
-  G.conic[0] = G.Sp[2] / G.det;
-  G.conic[1] = -G.Sp[1] / G.det;
-  G.conic[2] = G.Sp[0] / G.det;
+  const double idet = 1.0 / G.det;
+  G.conic[0] = G.Sp[2] * idet;
+  G.conic[1] = -G.Sp[1] * idet;
+  G.conic[2] = G.Sp[0] * idet;
   return true;
 }
 
@@ -175,7 +178,8 @@ __device__ inline void view_dir(const float* means, uint32_t i, uint32_t n, cons
                                 double vdir[3], double& vlen) {
   for (int a = 0; a < 3; ++a) vdir[a] = (double)means[a * n + i] - campos[a];
   vlen = sqrt(vdir[0] * vdir[0] + vdir[1] * vdir[1] + vdir[2] * vdir[2]);
-  for (int a = 0; a < 3; ++a) dir[a] = (float)(vdir[a] / vlen);
+  const double il = 1.0 / vlen;
+  for (int a = 0; a < 3; ++a) dir[a] = (float)(vdir[a] * il);
 }
 
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
@@ -306,11 +310,12 @@ __device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_
       if (area != 0) {
         keep = true;
         const float o = a.opac[i];
-        const double A = G.conic[0], B = G.conic[1];
+        const double A = G.conic[0], B = G.conic[1], iA = 1.0 / A;
         const float hx = (float)G.mu[0], hy = (float)G.mu[1];
         s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-        s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B / A), (float)(-0.5 * kLog2e / (G.det * A)),
-                         (float)(-log2(255.0 * (double)o)));
+        // D = C - B^2 / A = 1 / (det' A), det' the determinant of Sigma'
+        s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B * iA), (float)(-0.5 * kLog2e / (G.det * A)),
+                         -__log2f(255.0f * o));
         dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
       }
     }

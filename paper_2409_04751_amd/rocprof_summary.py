@@ -5,6 +5,14 @@
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
         --copy-bytes 1073741824 --out profiles/traffic_<workload>.json
     python -m paper_2409_04751_amd.rocprof_summary counters C.csv --counters SQ_WAVES ...
+    python -m paper_2409_04751_amd.rocprof_summary marks KERNEL_TRACE.csv --match preprocess_kernel
+    python -m paper_2409_04751_amd.rocprof_summary window KERNEL_TRACE.csv --begin I --end J --count preprocess_kernel
+
+`marks` lists the launch indices (in start-time order) of the kernels whose
+name contains a string; `window` sums the launches [I, J) of a kernel trace
+per kernel, with the span from the first start to the last end and the
+share of it the GPU was busy, per occurrence of the `--count` kernel (per
+batch, per view).
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two
 separate `rocprofv3 --pmc` runs) into HBM bytes per launch of each library
@@ -98,6 +106,32 @@ def traffic(args) -> dict:
     return rec
 
 
+def trace_launches(path: str) -> list[tuple[str, int, int]]:
+    """(short kernel name, start ns, end ns) of a rocprofv3 `*_kernel_trace.csv`,
+    in start order."""
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].replace("fgs::(anonymous namespace)::", "").replace("void ", "")
+            out.append((name.split("(")[0], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out.sort(key=lambda x: x[1])
+    return out
+
+
+def window(launches, begin: int, end: int, count: str) -> dict:
+    sub = launches[begin:end]
+    agg: dict[str, list] = {}
+    for name, t0, t1 in sub:
+        a = agg.setdefault(name, [0, 0])
+        a[0] += 1
+        a[1] += t1 - t0
+    busy = sum(a[1] for a in agg.values())
+    span = sub[-1][2] - sub[0][1]
+    units = sum(1 for name, _, _ in sub if count in name)
+    return dict(launches=len(sub), span_ms=span / 1e6, busy_ms=busy / 1e6, busy_frac=busy / span, units=units,
+                kernels=sorted(((n, a[0], a[1] / 1e6) for n, a in agg.items()), key=lambda x: -x[2]))
+
+
 def counter_table(path: str, counters: list[str]) -> dict:
     """Mean per dispatch of each counter for each library kernel."""
     out = {}
@@ -130,7 +164,29 @@ def main(argv=None) -> int:
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--counters", nargs="+", required=True)
+    m = sub.add_parser("marks")
+    m.add_argument("csv")
+    m.add_argument("--match", required=True)
+    w = sub.add_parser("window")
+    w.add_argument("csv")
+    w.add_argument("--begin", type=int, required=True)
+    w.add_argument("--end", type=int, required=True)
+    w.add_argument("--count", required=True)
+    w.add_argument("--top", type=int, default=20)
     args = ap.parse_args(argv)
+    if args.cmd == "marks":
+        print(" ".join(str(i) for i, (name, _, _) in enumerate(trace_launches(args.csv)) if args.match in name))
+        return 0
+    if args.cmd == "window":
+        r = window(trace_launches(args.csv), args.begin, args.end, args.count)
+        u = max(r["units"], 1)
+        print(f"launches [{args.begin}, {args.end}): {r['launches']}; span {r['span_ms']:.3f} ms; GPU busy "
+              f"{r['busy_ms']:.3f} ms ({r['busy_frac']:.2f}); {r['units']} x {args.count}: "
+              f"{r['busy_ms'] / u:.3f} ms busy each")
+        print(f"{'kernel':<46} {'calls':>6} {'total_ms':>10} {'per unit ms':>12}")
+        for name, calls, ms in r["kernels"][:args.top]:
+            print(f"{name[:46]:<46} {calls:>6} {ms:>10.3f} {ms / u:>12.3f}")
+        return 0
     if args.cmd == "stats":
         rows = kernel_stats(args.csv)
         total = sum(r["total_ns"] for r in rows)

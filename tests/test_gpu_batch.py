@@ -150,3 +150,26 @@ def test_batch_of_large_views_equals_single_views():
     for (img, _, K), out, k in zip(refs, outs, kv):
         assert K == k
         assert torch.equal(out, img)
+
+
+def test_batch_with_empty_and_tiny_views_equals_single_views():
+    """A batch mixing ordinary views with one whose Gaussians are all behind
+    the camera (no entry, no pair: background only) and a 1x1 and a 17x3
+    view (one tile row; ragged tiles): every image equals its single-view
+    render, the empty one is the background exactly."""
+    scene = synth.room_scene(20_000, 13, 0.01, 3)
+    gs = to_gpu(scene)
+    base = _views(13, 3)
+    away = synth.Pose(np.eye(3, dtype=np.float32), np.array([0.0, 0.0, -100.0], np.float32))
+    views = [base[0], (away, synth.fisheye_camera(96, 64, 180.0), (0.25, 0.5, 0.75)), base[1],
+             (base[2][0], synth.fisheye_camera(1, 1, 180.0), (0.0, 0.0, 0.0)),
+             (base[2][0], synth.fisheye_camera(17, 3, 190.0), (0.1, 0.1, 0.1)), base[2]]
+    print("case batch of 6 with an empty view, a 1x1 and a 17x3 view", flush=True)
+    outs, kv, kt = _batch(gs, views)
+    assert kv[1] == 0 and kt == sum(kv)
+    bg = torch.tensor((0.25, 0.5, 0.75), device="cuda").view(3, 1, 1).expand(3, 64, 96)
+    assert torch.equal(outs[1], bg)
+    for (pose, cam, b), img, k in zip(views, outs, kv):
+        ref, _, K = gpu_forward(gs, pose, cam, b)
+        assert K == k
+        assert torch.equal(img, ref)

@@ -287,11 +287,22 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
     const bool valid = idx < count;
     const uint32_t key = my_key[it];
     const uint32_t digit = ((key - key_bias) >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const uint64_t bal = __ballot((digit >> b) & 1u);
-      peers &= ((digit >> b) & 1u) ? bal : ~bal;
+    // lanes with the same digit: per bit, the ballot of that bit, taken as
+    // is where the lane's bit is 1 and complemented where it is 0 (m is 0 or
+    // all ones), kept as two 32-bit halves
+    const uint64_t vb = __ballot(valid);
+    uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if (b < bits) {  // uniform
+        const uint32_t bit = (digit >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        const uint32_t m = bit - 1u;
+        plo &= (uint32_t)bal ^ m;
+        phi &= (uint32_t)(bal >> 32) ^ m;
+      }
     }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
     uint32_t rank = 0xFFFFFFFFu;
     if (valid) {
       const uint32_t before = wave_count[wave][digit];

@@ -231,7 +231,7 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
  *   L = (1 / count) sum_j |image_j - target_j|,
  *   dL/dimage_j = sign(image_j - target_j) * dL_dloss[0] / count
  * (sign 0 where the two are equal; the quotient dL_dloss[0] / count is
- * rounded once to float, then multiplied by the sign).
+ * taken in double and rounded to float, then multiplied by the sign).
  *
  * fgs_l1_loss: image, target device float32 [count] (any layout, the same
  * for both), 16-byte aligned; partials device scratch of FGS_L1_PARTIALS

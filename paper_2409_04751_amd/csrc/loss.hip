@@ -63,9 +63,10 @@ __device__ inline float l1_sign(float a, float b) {
 
 __global__ __launch_bounds__(kBlock) void l1_grad_kernel(const float* img, const float* tgt, uint32_t count,
                                                          const float* dl, float* out) {
-  // the mean's backward: the upstream gradient over the element count, in
-  // float, then times the sign (exact)
-  const float w = dl[0] / (float)count;
+  // the mean's backward: the upstream gradient over the element count
+  // (exact in double for any count, rounded once to float), then times the
+  // sign (exact)
+  const float w = (float)((double)dl[0] / (double)count);
   const uint32_t n4 = count / 4u;
   const float4* a4 = reinterpret_cast<const float4*>(img);
   const float4* b4 = reinterpret_cast<const float4*>(tgt);

@@ -203,27 +203,32 @@ def serving_train_bench(n: int, rate: float, count: int, train_seconds: float):
     scene = synth.room_scene(n, 5, 0.01, 3)
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     leaves = [f(a).requires_grad_(True) for a in (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
-    opt = torch.optim.Adam(leaves, lr=1e-4)
+    # one Adam per parameter tensor (Adam is elementwise, so this is the same
+    # update as one optimizer over all of them), stepped one tensor per phase
+    opts = [torch.optim.Adam([p], lr=1e-4) for p in leaves]
     cam = synth.fisheye_camera(1752, 1168, 180.0)
     poses = synth.random_poses(64, 7, tuple(x + 1.0 for x in synth.ROOM_LO), tuple(x - 1.0 for x in synth.ROOM_HI))
     targets = [f(synth.target_image(cam.width, cam.height, 100 + k)) for k in range(4)]
     ws = R.Workspace(dev)
 
-    def train_view(k):
+    def train_view(k):  # two phases: forward and loss, then backward
         img = R.rasterize(*leaves, 3, poses[k % len(poses)], cam, (0.0, 0.0, 0.0), ws)
         loss = R.l1_loss(img, targets[k % 4])
+        yield
         loss.backward()
 
-    def optimizer_step():
-        opt.step()
-        opt.zero_grad(set_to_none=False)
+    def optimizer_step():  # one phase per parameter tensor
+        for o in opts:
+            o.step()
+            o.zero_grad(set_to_none=False)
+            yield
 
     srv = S.RenderServer(*[x.detach() for x in leaves], 3, workspace_bytes=16 << 30)
     warm = S.poisson_trace(rate, 16, seed=98)
     srv.serve(warm, "batched")
     for k in range(4):
-        train_view(k)
-    optimizer_step()
+        S.run_phases(train_view(k))
+    S.run_phases(optimizer_step())
     torch.cuda.synchronize()
     trace = S.poisson_trace(rate, count, seed=11)
     srv.batches = srv.splits = 0
@@ -235,8 +240,8 @@ def serving_train_bench(n: int, rate: float, count: int, train_seconds: float):
     steps = 0
     while time.perf_counter() - t0 < train_seconds:
         for k in range(4):
-            train_view(k)
-        optimizer_step()
+            S.run_phases(train_view(k))
+        S.run_phases(optimizer_step())
         torch.cuda.synchronize()
         steps += 1
     train_only = steps / (time.perf_counter() - t0)

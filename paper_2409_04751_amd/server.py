@@ -63,6 +63,22 @@ def poisson_trace(rate: float, count: int, seed: int = 3, resolutions=((512, 512
     return out
 
 
+def _phases(result):
+    """The phases of a training callable's result, one per next(): a
+    generator runs up to each of its yields and then to its end; anything
+    else has already run when the callable returned."""
+    if hasattr(result, "__next__"):
+        for _ in result:
+            yield
+    yield
+
+
+def run_phases(result) -> None:
+    """Runs every phase of a training callable's result."""
+    for _ in _phases(result):
+        pass
+
+
 class RenderServer:
     def __init__(self, means, scales, quats, opacities, sh, sh_degree: int, max_batch: int = L.FGS_MAX_BATCH,
                  workspace_bytes: int = 12 << 30, kpp_prior: float = 8.0):
@@ -142,14 +158,30 @@ class RenderServer:
     # -- open-loop replay ----------------------------------------------------
     def serve_with_training(self, trace: list[Request], train_view, optimizer_step, views_per_step: int = 4) -> dict:
         """Batched serving of `trace` with training in the gaps.  Requests
-        have priority; when the queue is empty, `train_view(k)` runs the k-th
-        training view (forward + backward) and after every `views_per_step`
+        have priority: whenever the queue is empty, one phase of training
+        work runs, and the queue is checked again.  `train_view(k)` runs the
+        k-th training view (forward + backward); after every `views_per_step`
         views `optimizer_step()` updates the parameters in place (the server
-        renders the same tensors, so requests see the scene as trained so far)."""
+        renders the same tensors, so requests see the scene as trained so
+        far).  Either may be a generator function, whose yields split its
+        work into phases (say the forward, then the backward; or one
+        parameter tensor's update at a time): a request then waits for at
+        most one phase rather than a whole view or step."""
         pending: collections.deque = collections.deque()
         lat = np.zeros(len(trace))
-        nxt = done = views = steps = 0
+        nxt = done = 0
+        count = dict(views=0, steps=0)
         stream = torch.cuda.current_stream(self.device)
+
+        def training():  # one training phase per next()
+            while True:
+                yield from _phases(train_view(count["views"]))
+                count["views"] += 1
+                if count["views"] % views_per_step == 0:
+                    yield from _phases(optimizer_step())
+                    count["steps"] += 1
+
+        work = training()
         t0 = time.perf_counter()
         while done < len(trace):
             now = time.perf_counter() - t0
@@ -157,11 +189,7 @@ class RenderServer:
                 pending.append(trace[nxt])
                 nxt += 1
             if not pending:
-                train_view(views)
-                views += 1
-                if views % views_per_step == 0:
-                    optimizer_step()
-                    steps += 1
+                next(work)
                 stream.synchronize()
                 continue
             batch = self.admit(pending)
@@ -175,6 +203,7 @@ class RenderServer:
                 lat[r.rid] = t_done - r.arrival
             done += len(batch)
         span = time.perf_counter() - t0
+        views, steps = count["views"], count["steps"]
         return dict(mode="batched+training", requests=len(trace), p50_ms=float(np.percentile(lat, 50) * 1e3),
                     p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
                     views_per_s=len(trace) / span, span_s=span, offered_rate=len(trace) / trace[-1].arrival,

@@ -312,10 +312,12 @@ def main() -> int:
     bg = (0.0, 0.0, 0.0)
     stats = {}
 
+    one = torch.ones((), dtype=torch.float32, device=dev)  # dL/dL, made once
+
     def step():
         img = R.rasterize(*leaves, deg, pose, cam, bg, ws)
         loss = R.l1_loss(img, target)
-        grads = torch.autograd.grad(loss, leaves)
+        grads = torch.autograd.grad(loss, leaves, grad_outputs=one)
         return loss, grads
 
     for _ in range(args.warmup):

@@ -670,6 +670,12 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t* p, uint32_t 
   if (j < count) p[j] = v;
 }
 
+// 16 bytes per thread for a 16-byte aligned array; count4 groups of four
+__global__ __launch_bounds__(kBlock) void fill_u32x4_kernel(uint4* p, uint32_t v, uint32_t count4) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < count4) p[j] = make_uint4(v, v, v, v);
+}
+
 // p[0 .. count) = 0 except p[at] = v
 __global__ __launch_bounds__(kBlock) void fill_u32_but_one_kernel(uint32_t* p, uint32_t count, uint32_t at,
                                                                   uint32_t v) {
@@ -737,8 +743,14 @@ hipError_t launch_clear_but_one(uint32_t* p, int64_t count, int64_t at, uint32_t
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   ProfScope prof(s, kKFill);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(count, kBlock)), dim3(kBlock), 0, s, p, v,
-                     (uint32_t)count);
+  const int64_t c4 = (reinterpret_cast<uintptr_t>(p) & 15u) == 0 ? count / 4 : 0;
+  if (c4 > 0)
+    hipLaunchKernelGGL(fill_u32x4_kernel, dim3((unsigned)ceil_div(c4, kBlock)), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint4*>(p), v, (uint32_t)c4);
+  const int64_t rest = count - 4 * c4;
+  if (rest > 0)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(rest, kBlock)), dim3(kBlock), 0, s, p + 4 * c4, v,
+                       (uint32_t)rest);
   return hipGetLastError();
 }
 

@@ -64,13 +64,18 @@ def poisson_trace(rate: float, count: int, seed: int = 3, resolutions=((512, 512
 
 
 def _phases(result):
-    """The phases of a training callable's result, one per next(): a
-    generator runs up to each of its yields and then to its end; anything
-    else has already run when the callable returned."""
+    """The phases of a training callable's result, one per next(), each
+    yielding whether it finished the callable's work: a generator runs up to
+    each of its yields and then to its end; anything else has already run
+    when the callable returned."""
     if hasattr(result, "__next__"):
-        for _ in result:
-            yield
-    yield
+        while True:
+            try:
+                next(result)
+            except StopIteration:
+                break
+            yield False
+    yield True
 
 
 def run_phases(result) -> None:
@@ -175,11 +180,13 @@ class RenderServer:
 
         def training():  # one training phase per next()
             while True:
-                yield from _phases(train_view(count["views"]))
-                count["views"] += 1
+                for last in _phases(train_view(count["views"])):
+                    count["views"] += last
+                    yield
                 if count["views"] % views_per_step == 0:
-                    yield from _phases(optimizer_step())
-                    count["steps"] += 1
+                    for last in _phases(optimizer_step()):
+                        count["steps"] += last
+                        yield
 
         work = training()
         t0 = time.perf_counter()

@@ -97,6 +97,53 @@ def test_server_batched_matches_serial_images():
         assert res["p99_ms"] >= res["p50_ms"] > 0
 
 
+def test_server_trains_in_phases_between_requests():
+    """serve_with_training on a small scene: every request is served, the
+    training views (a forward phase, then a backward phase) and per-tensor
+    Adam phases run in the gaps, and the parameters the server renders are
+    the ones being trained."""
+    scene = synth.room_scene(20_000, 15, 0.01, 3)
+    leaves = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda().requires_grad_(True)
+              for a in (scene.means, scene.scales, scene.quats, scene.opacity, scene.sh)]
+    before = [x.detach().clone() for x in leaves]
+    opts = [torch.optim.Adam([p], lr=1e-3) for p in leaves]
+    cam = synth.fisheye_camera(128, 96, 180.0)
+    poses = synth.random_poses(4, 7, tuple(x + 1.0 for x in synth.ROOM_LO), tuple(x - 1.0 for x in synth.ROOM_HI))
+    target = torch.rand((3, cam.height, cam.width), device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    ws = R.Workspace()
+    phases = []
+
+    def train_view(k):
+        img = R.rasterize(*leaves, 3, poses[k % len(poses)], cam, (0.0, 0.0, 0.0), ws)
+        loss = R.l1_loss(img, target)
+        phases.append("forward")
+        yield
+        loss.backward()
+        phases.append("backward")
+
+    def optimizer_step():
+        for o in opts:
+            o.step()
+            o.zero_grad(set_to_none=False)
+            phases.append("adam")
+            yield
+
+    srv = S.RenderServer(*[x.detach() for x in leaves], 3, workspace_bytes=1 << 30)
+    trace = S.poisson_trace(200.0, 60, seed=6, resolutions=((96, 64), (128, 128)))
+    print("case serve_with_training 20k Gaussians, 60 requests at 200/s", flush=True)
+    res = srv.serve_with_training(trace, train_view, optimizer_step, views_per_step=2)
+    torch.cuda.synchronize()
+    assert res["requests"] == len(trace) and res["p99_ms"] >= res["p50_ms"] > 0
+    assert res["train_views"] >= 2 and res["train_steps"] >= 1
+    # phases alternate forward / backward per view, and an optimizer step is
+    # one phase per tensor after every two views
+    assert phases[:2] == ["forward", "backward"]
+    k = phases.index("adam")
+    assert phases[k:k + len(opts)] == ["adam"] * len(opts)
+    assert phases[:k].count("backward") == 2
+    assert any(not torch.equal(a.detach(), b) for a, b in zip(leaves, before))
+
+
 def test_server_splits_a_batch_that_overflows():
     scene = synth.room_scene(30_000, 14, 0.01, 3)
     gs = to_gpu(scene)

@@ -1,6 +1,7 @@
 """Host logic of the server's training phases (no GPU): a generator's work
-runs one phase per step, up to each yield and then to its end; a plain
-callable counts as one phase that ran when it was called."""
+runs one phase per step, up to each yield and then to its end, and the
+phase that finishes it says so; a plain callable counts as one phase that
+ran when it was called."""
 import pytest
 
 pytest.importorskip("torch")
@@ -17,9 +18,9 @@ def test_generator_runs_one_phase_per_step():
         log.append("backward")
 
     ph = S._phases(view())
-    next(ph)
+    assert next(ph) is False
     assert log == ["forward"]
-    next(ph)
+    assert next(ph) is True  # the phase that finishes the view
     assert log == ["forward", "backward"]
     with pytest.raises(StopIteration):
         next(ph)
@@ -29,7 +30,7 @@ def test_plain_callable_is_one_phase():
     log = []
     ph = S._phases(log.append("step"))
     assert log == ["step"]
-    next(ph)
+    assert next(ph) is True
     with pytest.raises(StopIteration):
         next(ph)
 

@@ -172,7 +172,10 @@ int fgs_workspace_layout(int64_t n, int32_t width, int32_t height, size_t bytes,
  * out_rgb: device [3][H][W].
  * k_out: host, may be NULL; receives the number of intersections K.
  * flags: 0 or FGS_SAVE_PIXEL_STATE.
- * Synchronises `stream` once, after the binning scan, to read K.  If K
+ * Waits for `stream` once, after the compaction, to read V, K and the depth
+ * range: the counts are copied to a small pinned host buffer (one per calling
+ * thread, allocated on its first call and kept for the life of the process)
+ * and the stream is polled until they have arrived.  If K
  * exceeds the workspace's capacity it returns FGS_ERR_WORKSPACE with *k_out
  * = K and out_rgb untouched; the caller grows the workspace
  * (fgs_workspace_bytes(n, w, h, K, ...)) and calls again.

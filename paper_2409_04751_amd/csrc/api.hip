@@ -1,6 +1,7 @@
 // C ABI of libfgs: argument checks, workspace layout and the launch order of
 // the forward and backward passes.  All device memory comes from the caller.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -205,6 +206,34 @@ void export_layout(const Layout& L, fgs_layout* out) {
   out->counters = L.counters;
 }
 
+// The forward's one read-back: the counters go to a small pinned host
+// buffer (one per host thread, allocated on first use and kept), and the
+// host polls the stream until they have arrived rather than sleeping in a
+// stream synchronisation, so the launches that depend on them follow with
+// less delay.  After a few seconds of polling it falls back to a plain
+// synchronisation, which also reports any error of the stream.
+hipError_t read_counters(const uint32_t* counters, uint32_t* out, hipStream_t s) {
+  thread_local uint32_t* pinned = nullptr;
+  if (!pinned) {
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, kNumCounters * sizeof(uint32_t), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    pinned = static_cast<uint32_t*>(p);
+  }
+  hipError_t e = hipMemcpyAsync(pinned, counters, kNumCounters * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      e = hipStreamSynchronize(s);
+      break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  std::memcpy(out, pinned, kNumCounters * sizeof(uint32_t));
+  return hipSuccess;
+}
+
 #define HIP_TRY(expr, where)                          \
   do {                                                \
     hipError_t e_ = (expr);                           \
@@ -260,8 +289,7 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
                          U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters, reinterpret_cast<uint4*>(hist), s),
           "compact");
   uint32_t host_counters[kNumCounters];
-  HIP_TRY(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s), "read counts");
-  HIP_TRY(hipStreamSynchronize(s), "sync for counts");
+  HIP_TRY(read_counters(counters, host_counters, s), "read counts");
   const int64_t V = host_counters[kCountVisible];
   uint64_t K64;
   std::memcpy(&K64, &host_counters[kCountK64], sizeof(K64));

@@ -14,7 +14,7 @@
  *     read during the call only.
  *   - `stream` is a hipStream_t passed as void*; NULL means the default
  *     stream.  Work is enqueued on it; calls return before it finishes except
- *     where stated (fgs_render_forward reads one counter back).
+ *     where stated (the forward calls wait once, to read their counts back).
  *   - Parameter layout is structure-of-arrays float32, plane-major:
  *       means [3][n], scales [3][n] (activated, > 0), quats [4][n] (w,x,y,z;
  *       any non-zero norm, normalised inside), opacities [n] (activated, in
@@ -204,7 +204,7 @@ int fgs_batch_workspace_bytes(int64_t n, int32_t nviews, const fgs_camera* cams,
  * nviews device pointers, view v's image [3][H_v][W_v].  k_views (host
  * [nviews]) and k_total (host) may be NULL; they receive the intersections
  * per view and in total, also when FGS_ERR_WORKSPACE is returned, so a
- * server can split the batch.  Synchronises `stream` once, like
+ * server can split the batch.  Waits for `stream` once, like
  * fgs_render_forward.  The workspace is the batch layout
  * (fgs_batch_workspace_bytes), not usable by fgs_render_backward.
  */

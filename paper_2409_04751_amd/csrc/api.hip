@@ -241,8 +241,10 @@ hipError_t read_counters(const uint32_t* counters, uint32_t* out, hipStream_t s)
   } while (0)
 
 // Shared forward of 1..kMaxViews views: preprocess of every (view, Gaussian),
-// compaction, depth sort, tile-count scan, K read-back, duplication, tile
-// sort, ranges and one blend launch over the tiles of all views.
+// visibility scan and compaction (which also sum K and R and find the
+// depth-key range), the one read-back of those counts, depth sort, row
+// numbering, rows, row-count scan, duplication, tile sort, ranges and one
+// blend launch over the tiles of all views.
 int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, const fgs_camera* cams,
                  const float* bgs, uint32_t flags, void* workspace, size_t workspace_bytes, float* const* out_rgb,
                  int64_t* k_views, int64_t* k_total, hipStream_t s) {

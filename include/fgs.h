@@ -50,14 +50,14 @@ extern "C" {
  * incidence theta = atan2(|(x_c, y_c)|, z_c) on its azimuth's ray at
  * distance f r(theta) from (c_x, c_y); Sec. 3.2 lists the four fisheye
  * projections, and the pinhole is the textbook r = tan theta.  The panorama
- * is the equirectangular projection of Sec. 5.4 ("Extension to Other
+ * is the equirectangular projection of Sec. 5.3 (paragraph "Extension to Other
  * Cameras Models"): x_p = c_x + f_x atan2(x_c, z_c),
  * y_p = c_y + f_y atan2(y_c, |(x_c, z_c)|); the paper's image of width w and
  * height h has f_x = w / (2 pi), f_y = h / pi, c = (w/2, h/2).  Splats are
  * not wrapped across the panorama's left/right seam. */
 #define FGS_MODEL_EQUIDISTANT 0   /* r = theta (Sec. 3.2) */
 #define FGS_MODEL_PINHOLE 1       /* r = tan theta */
-#define FGS_MODEL_PANORAMA 2      /* equirectangular (Sec. 5.4) */
+#define FGS_MODEL_PANORAMA 2      /* equirectangular (Sec. 5.3) */
 #define FGS_MODEL_EQUISOLID 3     /* r = 2 sin(theta / 2) */
 #define FGS_MODEL_ORTHOGRAPHIC 4  /* r = sin theta */
 #define FGS_MODEL_STEREOGRAPHIC 5 /* r = 2 tan(theta / 2) */
@@ -105,9 +105,12 @@ typedef struct fgs_gaussians {
   int32_t sh_degree; /* 0..3 */
 } fgs_gaussians;
 
-/* Gradient outputs, same layouts as fgs_gaussians.  Every element is
- * WRITTEN (culled Gaussians get 0), not accumulated.  means2d, if not NULL,
- * receives dL/dmu_p as [2][n] (pixel units). */
+/* Gradient outputs, same layouts as fgs_gaussians.  With accumulate = 0
+ * every element is WRITTEN (culled Gaussians get 0); with accumulate = 1 the
+ * view's gradient is ADDED to the values already there (culled Gaussians
+ * keep them), so the views of a training step share one set of buffers.
+ * means2d, if not NULL, receives (or accumulates) dL/dmu_p as [2][n]
+ * (pixel units). */
 typedef struct fgs_grads {
   float* means;
   float* scales;
@@ -115,6 +118,7 @@ typedef struct fgs_grads {
   float* opacities;
   float* sh;
   float* means2d;
+  int32_t accumulate;
 } fgs_grads;
 
 /* Byte offsets of the arrays inside a workspace, for inspection.  All

@@ -42,7 +42,8 @@ class _Cam(ctypes.Structure):
 
 
 class _Tol(ctypes.Structure):
-    _fields_ = [("tol_alpha", ctypes.c_double), ("tol_T", ctypes.c_double), ("tol_clamp", ctypes.c_double)]
+    _fields_ = [("tol_alpha", ctypes.c_double), ("tol_T", ctypes.c_double), ("tol_clamp", ctypes.c_double),
+                ("err_scale", ctypes.c_double)]
 
 
 _lib = None
@@ -145,28 +146,58 @@ def sh_basis(degree: int, d) -> np.ndarray:
 
 # -- pipeline --------------------------------------------------------------
 
+# tie bits: 1 the radius or rect (fp64 decisions) within 1e-9 of a boundary;
+# 2 another rounding of the float record keeps other tiles (fp32 recipe);
+# 4 the fp64 tight rule's tiles move with its margins (rule only)
+TIE_RECT, TIE_RECORD, TIE_RULE = 1, 2, 4
+
+_BIN_MODE = {"rect": 0, "tight": 1, "tight64": 2}
+
+
 def preprocess(scene, pose, cam, binning: str = "tight") -> dict:
     """binning "tight": each Gaussian keeps only the tiles of its 3-sigma rect
-    that its (margin-grown) alpha >= 1/255 ellipse reaches; "rect": every tile
-    of the rect (vanilla lists).  Images and gradients are the same."""
-    assert binning in ("tight", "rect")
+    that its (margin-grown) alpha >= 1/255 ellipse reaches, decided by the
+    binary32 key recipe from the float record of the splat; "tight64": the
+    same rule decided in fp64 (its definition); "rect": every tile of the rect
+    (vanilla lists).  Images and gradients are the same."""
+    assert binning in _BIN_MODE
     n = scene.n
     o = dict(
         visible=np.zeros(n, np.uint8), mu_p=np.zeros((n, 2)), conic=np.zeros((n, 3)), rgb=np.zeros((n, 3)),
         clamped=np.zeros(n, np.uint8), radius=np.zeros(n, np.int32), rect=np.zeros((n, 4), np.int32),
-        depth=np.zeros(n, np.float32), tiles=np.zeros(n, np.uint32), tie=np.zeros(n, np.uint8))
+        depth=np.zeros(n, np.float32), tiles=np.zeros(n, np.uint32), tie=np.zeros(n, np.uint8),
+        cov2d=np.zeros((n, 3)))
     means, scales, quats, opac, sh, R, t = _params(scene, pose)
     c = _cam(cam)
     lib().orc_preprocess(ctypes.c_int64(n), _p(means), _p(scales), _p(quats), _p(opac), _p(sh),
                          ctypes.c_int(scene.sh_degree), _p(R), _p(t), ctypes.byref(c), _p(o["visible"]),
                          _p(o["mu_p"]), _p(o["conic"]), _p(o["rgb"]), _p(o["clamped"]), _p(o["radius"]),
-                         _p(o["rect"]), _p(o["depth"]), _p(o["tiles"]), _p(o["tie"]))
+                         _p(o["rect"]), _p(o["depth"]), _p(o["tiles"]), _p(o["tie"]), _p(o["cov2d"]))
     o["opacity"] = opac
     o["binning"] = binning
     if binning == "tight":
+        lib().orc_tighten32(ctypes.c_int64(n), _p(o["visible"]), _p(o["mu_p"]), _p(o["conic"]), _p(o["cov2d"]),
+                            _p(opac), _p(o["rect"]), _p(o["tiles"]), _p(o["tie"]))
+    elif binning == "tight64":
         lib().orc_tighten(ctypes.c_int64(n), _p(o["visible"]), _p(o["mu_p"]), _p(o["conic"]), _p(opac),
                           _p(o["rect"]), _p(o["tiles"]), _p(o["tie"]))
     return o
+
+
+def tight_alternatives(pre: dict, i: int, max_alt: int = 64) -> list:
+    """Kept tile columns per rect row of Gaussian i under the binary32 recipe,
+    one [rows, 2] array per rounding of its float record that the renderer's
+    fp64 geometry could produce (one array unless a value is near a float
+    rounding midpoint)."""
+    rect = np.ascontiguousarray(pre["rect"][i], dtype=np.int32)
+    rows = int(rect[3] - rect[1])
+    out = np.zeros((max_alt, max(rows, 1), 2), np.int32)
+    cnt = lib().orc_tight32_alternatives(_p(np.ascontiguousarray(pre["mu_p"][i])),
+                                         _p(np.ascontiguousarray(pre["conic"][i])),
+                                         _p(np.ascontiguousarray(pre["cov2d"][i])),
+                                         ctypes.c_double(float(pre["opacity"][i])), _p(rect), ctypes.c_int(max_alt),
+                                         _p(out))
+    return [out[k, :rows] for k in range(cnt)]
 
 
 def bin_and_sort(pre: dict, cam) -> dict:
@@ -177,12 +208,14 @@ def bin_and_sort(pre: dict, cam) -> dict:
     ranges = np.zeros((cam.tiles_x * cam.tiles_y, 2), np.uint32)
     lib().orc_bin(ctypes.c_int64(n), _p(pre["visible"]), _p(pre["rect"]), _p(pre["depth"]),
                   ctypes.c_int32(cam.width), ctypes.c_int32(cam.height), ctypes.c_int64(k), _p(keys), _p(vals),
-                  _p(ranges), ctypes.c_int(1 if pre.get("binning", "rect") == "tight" else 0), _p(pre["mu_p"]),
-                  _p(pre["conic"]), _p(pre["opacity"]))
+                  _p(ranges), ctypes.c_int(_BIN_MODE[pre.get("binning", "rect")]), _p(pre["mu_p"]),
+                  _p(pre["conic"]), _p(pre["cov2d"]), _p(pre["opacity"]))
     return dict(K=int(k), keys=keys[:k], vals=vals[:k], ranges=ranges)
 
 
-DEFAULT_TOL = (1e-5, 1e-4, 1e-5)
+# flag bands: no fixed margin, twice the binary32 error bound of each
+# decision (fgs_oracle.c, "Ambiguity flags")
+DEFAULT_TOL = (0.0, 0.0, 0.0, 2.0)
 
 
 def blend(pre: dict, bins: dict, cam, bg=(0.0, 0.0, 0.0), tol=DEFAULT_TOL) -> dict:
@@ -245,6 +278,26 @@ def preprocess_backward(scene, pose, cam, pre: dict, g2d: dict) -> dict:
                                   _p(np.ascontiguousarray(g2d["conic"])), _p(np.ascontiguousarray(g2d["opacity"])),
                                   _p(np.ascontiguousarray(g2d["rgb"])), _p(out["means"]), _p(out["scales"]),
                                   _p(out["quats"]), _p(out["opacity"]), _p(out["sh"]))
+    return out
+
+
+def chain_error_scale(scene, pose, cam, pre: dict, g2d_abs) -> dict:
+    """The rounding-error scale of each parameter gradient: the preprocess
+    backward is linear in the nine 2D gradients of a Gaussian, dL/dp = M g2d,
+    so an error of g2d bounded by its operand magnitudes `g2d_abs` [n, 9]
+    (mu_x, mu_y, A, B, C, o, r, g, b) reaches dL/dp as at most |M| g2d_abs.
+    |M| is taken column by column, one backward per unit 2D gradient."""
+    n = scene.n
+    out = None
+    for k in range(9):
+        unit = np.zeros((n, 9))
+        unit[:, k] = 1.0
+        g2d = dict(mu_p=np.ascontiguousarray(unit[:, 0:2]), conic=np.ascontiguousarray(unit[:, 2:5]),
+                   opacity=np.ascontiguousarray(unit[:, 5]), rgb=np.ascontiguousarray(unit[:, 6:9]))
+        col = preprocess_backward(scene, pose, cam, pre, g2d)
+        w = np.asarray(g2d_abs)[:, k]
+        term = {b: np.abs(v) * w for b, v in col.items()}
+        out = term if out is None else {b: out[b] + term[b] for b in out}
     return out
 
 

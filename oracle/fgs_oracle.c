@@ -19,10 +19,10 @@
  *                                      theta terms; read as f times the whole entry)
  *   Sec. 4.3                          dJ/dx_c, dJ/dy_c, dJ/dz_c via S1..S8 (entry
  *                                      [0][2] of dJ/dy_c printed with f_y; read as f_x)
- *   Sec. 3.2 (model list), Sec. 5.4   other camera models: the equisolid-angle,
+ *   Sec. 3.2 (model list), Sec. 5.3   other camera models: the equisolid-angle,
  *                                      orthographic and stereographic fisheyes Sec. 3.2
  *                                      names, the pinhole, and the panorama projection of
- *                                      Sec. 5.4 "Extension to Other Cameras Models"; their
+ *                                      Sec. 5.3, paragraph "Extension to Other Cameras Models"; their
  *                                      J and dJ are the first and second derivatives of
  *                                      the projection, taken by forward-mode
  *                                      differentiation (the paper prints only the
@@ -41,6 +41,7 @@
  *   series of their closed forms (the closed forms are 0/0 on the axis).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -60,7 +61,7 @@ typedef struct {
  *   equidistant r = theta (Sec. 3.2), pinhole r = tan theta,
  *   equisolid angle r = 2 sin(theta / 2), orthographic r = sin theta,
  *   stereographic r = 2 tan(theta / 2)  (the fisheye models Sec. 3.2 lists).
- * The panorama (Sec. 5.4) maps longitude atan2(x_c, z_c) and latitude
+ * The panorama (Sec. 5.3) maps longitude atan2(x_c, z_c) and latitude
  * atan2(y_c, |(x_c, z_c)|) linearly to x and y. */
 enum { MODEL_EQUIDISTANT = 0, MODEL_PINHOLE = 1, MODEL_PANORAMA = 2, MODEL_EQUISOLID = 3, MODEL_ORTHOGRAPHIC = 4,
        MODEL_STEREOGRAPHIC = 5 };
@@ -500,12 +501,13 @@ static double tie_dist(double v) { return fabs(v - nearbyint(v)); }
  *   visible u8, mu_p [n][2], conic [n][3] (A, B, C with q = -(A dx^2 + C dy^2)/2 - B dx dy),
  *   rgb [n][3], clamped u8 (bit c = channel c clamped at 0), radius i32,
  *   rect [n][4] (x0, y0, x1, y1, tile units, half-open), depth f32 (|mu_c|),
- *   tiles u32, tie u8 (1 = radius or rect decision within 1e-9 of a boundary).
+ *   tiles u32, tie u8 (1 = radius or rect decision within 1e-9 of a boundary),
+ *   cov2d [n][3] (the dilated 2D covariance Sigma': xx, xy, yy).
  */
 void orc_preprocess(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
                     const double* sh, int sh_degree, const double* Rw, const double* tw, const orc_camera* cam,
                     uint8_t* visible, double* mu_p, double* conic, double* rgb, uint8_t* clamped,
-                    int32_t* radius, int32_t* rect, float* depth, uint32_t* tiles, uint8_t* tie) {
+                    int32_t* radius, int32_t* rect, float* depth, uint32_t* tiles, uint8_t* tie, double* cov2d) {
   const int gx = (cam->width + TILE - 1) / TILE, gy = (cam->height + TILE - 1) / TILE;
   double campos[3];
   for (int a = 0; a < 3; ++a) campos[a] = -(Rw[0 * 3 + a] * tw[0] + Rw[1 * 3 + a] * tw[1] + Rw[2 * 3 + a] * tw[2]);
@@ -514,7 +516,7 @@ void orc_preprocess(int64_t n, const double* means, const double* scales, const 
     visible[i] = 0; radius[i] = 0; tiles[i] = 0; clamped[i] = 0; tie[i] = 0; depth[i] = 0;
     for (int a = 0; a < 4; ++a) rect[i * 4 + a] = 0;
     for (int a = 0; a < 2; ++a) mu_p[i * 2 + a] = 0;
-    for (int a = 0; a < 3; ++a) { conic[i * 3 + a] = 0; rgb[i * 3 + a] = 0; }
+    for (int a = 0; a < 3; ++a) { conic[i * 3 + a] = 0; rgb[i * 3 + a] = 0; cov2d[i * 3 + a] = 0; }
     geom g;
     dual Sig[9];
     if (!geometry(i, n, means, scales, quats, opac, Rw, tw, cam, &g, Sig)) continue;
@@ -557,6 +559,9 @@ void orc_preprocess(int64_t n, const double* means, const double* scales, const 
     mu_p[i * 2 + 0] = g.mu_p[0];
     mu_p[i * 2 + 1] = g.mu_p[1];
     for (int a = 0; a < 3; ++a) conic[i * 3 + a] = g.conic[a];
+    cov2d[i * 3 + 0] = g.Sp[0];
+    cov2d[i * 3 + 1] = g.Sp[1];
+    cov2d[i * 3 + 2] = g.Sp[3];
     radius[i] = (int32_t)rad;
     for (int a = 0; a < 4; ++a) rect[i * 4 + a] = rc[a];
     depth[i] = (float)sqrt((g.pc[0] * g.pc[0] + g.pc[1] * g.pc[1]) + g.pc[2] * g.pc[2]);
@@ -616,9 +621,10 @@ static void tight_row(const double* mu, const double* con, double opac, int ty, 
 }
 
 /* Counts the kept tiles of every visible Gaussian into tiles[] (a Gaussian
- * with none becomes invisible) and flags as a tie any whose count or
- * intervals move when the margins move by 1e-4 (relative) / 4e-3 px (well
- * beyond the float rounding of the library's evaluation). */
+ * with none becomes invisible) and flags (tie bit 4) any whose count or
+ * intervals move when the margins move by 1e-4 (relative) / 4e-3 px, well
+ * beyond what a binary32 evaluation of the rule can move them: outside those
+ * Gaussians any such evaluation keeps the same tiles as this one. */
 void orc_tighten(int64_t n, uint8_t* visible, const double* mu_p, const double* conic, const double* opac,
                  const int32_t* rect, uint32_t* tiles, uint8_t* tie) {
 #pragma omp parallel for schedule(dynamic, 4096)
@@ -629,7 +635,7 @@ void orc_tighten(int64_t n, uint8_t* visible, const double* mu_p, const double* 
     const double P = log2(255.0 * opac[i]);
     if (fabs(P) < 1e-9 || fabs(P - kTightP0) < 1e-9 ||
         fabs(fabs(con[1] / con[0]) - kTightBeta) < 1e-6 * kTightBeta)
-      tie[i] = 1;
+      tie[i] |= 4;
     const int kind = tight_kind(con, opac[i]);
     int64_t count = 0;
     if (kind == 2) {
@@ -640,13 +646,244 @@ void orc_tighten(int64_t n, uint8_t* visible, const double* mu_p, const double* 
         tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow, kTightPad, &a0, &a1);
         tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow * (1 + 1e-4), kTightPad + 4e-3, &b0, &b1);
         tight_row(&mu_p[i * 2], con, opac[i], ty, rc[0], rc[2], kTightGrow * (1 - 1e-4), kTightPad - 4e-3, &d0, &d1);
-        if (a1 - a0 != b1 - b0 || a1 - a0 != d1 - d0 || (a1 > a0 && (a0 != b0 || a0 != d0))) tie[i] = 1;
+        if (a1 - a0 != b1 - b0 || a1 - a0 != d1 - d0 || (a1 > a0 && (a0 != b0 || a0 != d0))) tie[i] |= 4;
         count += a1 - a0;
       }
     }
     tiles[i] = (uint32_t)count;
     if (count == 0) visible[i] = 0;
   }
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP32 key recipe of the tight binning.                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * The rule above decides in exact arithmetic (here fp64).  A renderer that
+ * decides in binary32 from a float record of the splat keeps the same tiles
+ * except where a margin lands within float rounding of a tile edge.  This
+ * mode fixes one such float evaluation completely, so that its decisions are
+ * reproducible bit for bit by any IEEE binary32 implementation of the same
+ * steps (each step one correctly rounded operation, nothing contracted):
+ *
+ *   record, the fp64 values rounded once to float:
+ *     mx = hi + lo (float add) with hi = f(mu_x), lo = f(mu_x - hi); my alike;
+ *     a = f(A log2(e) / 2);  beta = f(B / A);  d = f((C - B^2 / A) log2(e) / 2);
+ *     P = f(log2(255 o32)), 255 o32 the float product of the float opacity;
+ *   setup:  P < 0 (or NaN): no tile;  P <= 1e-6, |beta| > 1e3, a or d not
+ *     positive: the whole rect;  else Pg = P * 1.0201, ia = 1 / a,
+ *     Pa = Pg * ia, da = d * ia, ry = sqrt(Pg * (1 / d)),
+ *     ds = beta * sqrt((a * Pg) * (1 / (d * fma(beta * beta, a, d))));
+ *     the whole rect again if ry, |ds|, Pa or da exceeds 1e30 or is NaN;
+ *   per tile row ty of the rect [x0, x1):  with pad = 0.125,
+ *     lo_y = max((my - (16 ty + 15)) - pad, -ry), hi_y = min((my - 16 ty) + pad, ry),
+ *     none if !(lo_y <= hi_y);  ya = min(max(ds, lo_y), hi_y),
+ *     yb = min(max(-ds, lo_y), hi_y), sa = sqrt(max(0, Pa - (da * ya) * ya)),
+ *     sb likewise at yb, xhi = ((mx + beta * ya) + sa) + pad,
+ *     xlo = ((mx + beta * yb) - sb) - pad; the whole row if !(xhi >= xlo);
+ *     columns [clamp(ceil((xlo - 15) * (1/16))), clamp(floor(xhi * (1/16)) + 1))
+ *     clamped to [x0, x1] in float, kept if the interval is not empty.
+ *
+ * The record's dy is mean minus pixel (dy = my - py), as in the blend's
+ * exponent; the ellipse is |a| t^2 + |d| dy^2 <= P in log2 units with
+ * t = dx + beta dy, the alpha >= 1/255 region of Eq. 3's weights, grown and
+ * padded as above.
+ *
+ * Ties.  The renderer's fp64 geometry is another evaluation of the same
+ * formulas, so its record may round the other way where the fp64 value lies
+ * within a few fp64 ulps of a float rounding midpoint.  Each record value
+ * within kRecTie (relative) of a midpoint gets both neighbours; a Gaussian
+ * is a tie if any combination of them keeps other tiles.
+ */
+static const double kRecTie = 1e-9;
+
+typedef struct { float mx, my, a, beta, d, P; } rec32;
+
+/* The float of the fp64 value v and, if v lies within kRecTie of the
+ * midpoint between two floats, the other of the two (else alt = f). */
+static void round_both(double v, double rel, float* f, float* alt) {
+  *f = (float)v;
+  *alt = *f;
+  if (!isfinite(*f)) return;
+  const float up = nextafterf(*f, INFINITY), dn = nextafterf(*f, -INFINITY);
+  const double mup = 0.5 * ((double)*f + (double)up), mdn = 0.5 * ((double)*f + (double)dn);
+  const double tol = rel * fabs(v);
+  if (fabs(v - mup) <= tol) *alt = up;
+  else if (fabs(v - mdn) <= tol) *alt = dn;
+}
+
+static float mean32(float hi, double mu) { return hi + (float)(mu - (double)hi); }
+
+typedef struct { float mx, my, Pa, da, beta, ry, ds; int kind; } reach32;
+
+static reach32 reach32_setup(const rec32* r) {
+  reach32 z;
+  z.mx = r->mx; z.my = r->my; z.beta = r->beta;
+  z.Pa = z.da = z.ry = z.ds = 0.0f;
+  const float a = r->a, d = r->d, P = r->P;
+  if (!(P >= 0.0f)) { z.kind = 0; return z; }
+  z.kind = 2;
+  if (P <= 1e-6f || !(fabsf(r->beta) <= 1e3f) || !(a > 0.0f) || !(d > 0.0f)) return z;
+  const float Pg = P * 1.0201f;
+  const float ia = 1.0f / a;
+  z.Pa = Pg * ia;
+  z.da = d * ia;
+  z.ry = sqrtf(Pg * (1.0f / d));
+  const float bb = r->beta * r->beta;
+  const float den = d * fmaf(bb, a, d);
+  const float aP = a * Pg;
+  z.ds = r->beta * sqrtf(aP * (1.0f / den));
+  if (!(z.ry <= 1e30f) || !(fabsf(z.ds) <= 1e30f) || !(z.Pa <= 1e30f) || !(z.da <= 1e30f)) return z;
+  z.kind = 1;
+  return z;
+}
+
+static void reach32_row(const reach32* z, int ty, int x0, int x1, int* c0, int* c1) {
+  *c0 = *c1 = x0;
+  if (z->kind != 1) {
+    if (z->kind == 2) *c1 = x1;
+    return;
+  }
+  const float pad = 0.125f;
+  const float lo_y = fmaxf((z->my - (float)(TILE * ty + TILE - 1)) - pad, -z->ry);
+  const float hi_y = fminf((z->my - (float)(TILE * ty)) + pad, z->ry);
+  if (!(lo_y <= hi_y)) return;
+  const float ya = fminf(fmaxf(z->ds, lo_y), hi_y), yb = fminf(fmaxf(-z->ds, lo_y), hi_y);
+  const float sa = sqrtf(fmaxf(0.0f, z->Pa - (z->da * ya) * ya));
+  const float sb = sqrtf(fmaxf(0.0f, z->Pa - (z->da * yb) * yb));
+  const float xhi = ((z->mx + z->beta * ya) + sa) + pad;
+  const float xlo = ((z->mx + z->beta * yb) - sb) - pad;
+  if (!(xhi >= xlo)) { *c1 = x1; return; }
+  const float fx0 = (float)x0, fx1 = (float)x1;
+  const int lo = (int)fminf(fmaxf(ceilf((xlo - 15.0f) * 0.0625f), fx0), fx1);
+  const int hi = (int)fminf(fmaxf(floorf(xhi * 0.0625f) + 1.0f, fx0), fx1);
+  if (hi > lo) { *c0 = lo; *c1 = hi; }
+}
+
+/* The record's six values (mx, my, a, beta, d, P) from the fp64 splat, each
+ * with its alternative rounding (equal to it unless near a midpoint).
+ * C - B^2 / A equals 1 / Sigma'_yy exactly, which is how it is taken here
+ * (the difference cancels for thin splats).  A = Sigma'_yy / det(Sigma')
+ * inherits the conditioning of the determinant, (|xx yy| + xy^2) / det, so
+ * its tie band widens with it. */
+static void record32_both(const double* mu, const double* con, const double* cov, double opac, float v[6],
+                          float alt[6]) {
+  const double l2e = 1.4426950408889634;
+  const double A = con[0], B = con[1];
+  const double det = cov[0] * cov[2] - cov[1] * cov[1];
+  const double cond = (fabs(cov[0] * cov[2]) + cov[1] * cov[1]) / det;
+  float hx, hx2, hy, hy2;
+  round_both(mu[0], kRecTie, &hx, &hx2);
+  round_both(mu[1], kRecTie, &hy, &hy2);
+  v[0] = mean32(hx, mu[0]); alt[0] = mean32(hx2, mu[0]);
+  v[1] = mean32(hy, mu[1]); alt[1] = mean32(hy2, mu[1]);
+  round_both(0.5 * l2e * A, kRecTie + 1e-14 * cond, &v[2], &alt[2]);
+  round_both(B / A, kRecTie, &v[3], &alt[3]);
+  round_both(0.5 * l2e / cov[2], kRecTie, &v[4], &alt[4]);
+  const float o32 = (float)opac;
+  const float p255 = 255.0f * o32;
+  round_both(log2((double)p255), kRecTie, &v[5], &alt[5]);
+}
+
+static rec32 rec_of(const float v[6]) {
+  rec32 r = {v[0], v[1], v[2], v[3], v[4], v[5]};
+  return r;
+}
+
+/* Kept tiles of one Gaussian under the recipe: total count, and first and
+ * last + 1 kept tile row (ya = yb = 0 if none); cols[2 * (ty - y0) + k] the
+ * row's interval if cols != NULL. */
+static int64_t recipe_tiles(const rec32* r, const int32_t* rc, int* ya, int* yb, int* cols) {
+  const reach32 z = reach32_setup(r);
+  int64_t count = 0;
+  *ya = *yb = 0;
+  for (int ty = rc[1]; ty < rc[3]; ++ty) {
+    int c0, c1;
+    reach32_row(&z, ty, rc[0], rc[2], &c0, &c1);
+    if (cols) { cols[2 * (ty - rc[1])] = c0; cols[2 * (ty - rc[1]) + 1] = c1; }
+    if (c1 > c0) {
+      if (count == 0) *ya = ty;
+      *yb = ty + 1;
+      count += c1 - c0;
+    }
+  }
+  return count;
+}
+
+/* Counts the kept tiles of every visible Gaussian under the fp32 recipe (a
+ * Gaussian with none becomes invisible); tie[i] |= 2 if another rounding of
+ * its record keeps other tiles. */
+void orc_tighten32(int64_t n, uint8_t* visible, const double* mu_p, const double* conic, const double* cov2d,
+                   const double* opac, const int32_t* rect, uint32_t* tiles, uint8_t* tie) {
+#pragma omp parallel
+  {
+    int cap = 0;
+    int* ref = NULL;
+    int* oth = NULL;
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < n; ++i) {
+      if (!visible[i]) continue;
+      const int32_t* rc = &rect[i * 4];
+      const int rows = rc[3] - rc[1];
+      if (2 * rows > cap) {
+        cap = 2 * rows;
+        ref = (int*)realloc(ref, sizeof(int) * (size_t)cap);
+        oth = (int*)realloc(oth, sizeof(int) * (size_t)cap);
+      }
+      float v[6], alt[6];
+      record32_both(&mu_p[i * 2], &conic[i * 3], &cov2d[i * 3], opac[i], v, alt);
+      rec32 r = rec_of(v);
+      int ya, yb;
+      const int64_t count = recipe_tiles(&r, rc, &ya, &yb, ref);
+      int near[6], m = 0;
+      for (int k = 0; k < 6; ++k)
+        if (alt[k] != v[k]) near[m++] = k;
+      for (int combo = 1; combo < (1 << m); ++combo) {
+        float w[6];
+        for (int k = 0; k < 6; ++k) w[k] = v[k];
+        for (int b = 0; b < m; ++b)
+          if (combo & (1 << b)) w[near[b]] = alt[near[b]];
+        rec32 ra = rec_of(w);
+        int ya2, yb2;
+        recipe_tiles(&ra, rc, &ya2, &yb2, oth);
+        for (int row = 0; row < rows; ++row) {
+          const int* p = &ref[2 * row];
+          const int* q = &oth[2 * row];
+          if (p[0] == p[1] && q[0] == q[1]) continue; /* both empty */
+          if (p[0] != q[0] || p[1] != q[1]) tie[i] |= 2;
+        }
+      }
+      tiles[i] = (uint32_t)count;
+      if (count == 0) visible[i] = 0;
+    }
+    free(ref);
+    free(oth);
+  }
+}
+
+/* Kept tiles of Gaussian i under the recipe for every rounding of its record
+ * (up to 64 alternatives): out[alt][row][2] intervals over the rect's rows,
+ * returns the number of alternatives written (at most max_alt). */
+int orc_tight32_alternatives(const double* mu_p, const double* conic, const double* cov2d, double opac,
+                             const int32_t* rect, int max_alt, int32_t* out) {
+  float v[6], alt[6];
+  record32_both(mu_p, conic, cov2d, opac, v, alt);
+  int near[6], m = 0;
+  for (int k = 0; k < 6; ++k)
+    if (alt[k] != v[k]) near[m++] = k;
+  const int rows = rect[3] - rect[1];
+  int count = 0;
+  for (int combo = 0; combo < (1 << m) && count < max_alt; ++combo) {
+    float w[6];
+    for (int k = 0; k < 6; ++k) w[k] = v[k];
+    for (int b = 0; b < m; ++b)
+      if (combo & (1 << b)) w[near[b]] = alt[near[b]];
+    rec32 r = rec_of(w);
+    int ya, yb;
+    recipe_tiles(&r, rect, &ya, &yb, &out[(size_t)count * 2 * rows]);
+    ++count;
+  }
+  return count;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -669,13 +906,13 @@ static int cmp_pair(const void* a, const void* b) {
   return 0;
 }
 
-/* Emit one (key, id) pair per (Gaussian, tile of its rect -- with tight, per
- * kept tile), key =
+/* Emit one (key, id) pair per (Gaussian, tile of its rect; with tight = 1 per
+ * tile the fp32 recipe keeps, with tight = 2 per tile the fp64 rule keeps), key =
  * tile_id << 32 | float bits of depth, then sort by (key, id) and find
  * each tile's [start, end) in the sorted list.  ranges is [ntiles][2]. */
 void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float* depth, int32_t width,
              int32_t height, int64_t kcount, uint64_t* keys, uint32_t* vals, uint32_t* ranges, int tight,
-             const double* mu_p, const double* conic, const double* opac) {
+             const double* mu_p, const double* conic, const double* cov2d, const double* opac) {
   const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
   pair_t* p = (pair_t*)malloc(sizeof(pair_t) * (size_t)(kcount > 0 ? kcount : 1));
   int64_t k = 0;
@@ -683,13 +920,24 @@ void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float
     if (!visible[i]) continue;
     uint32_t bits;
     memcpy(&bits, &depth[i], 4);
-    const int kind = tight ? tight_kind(&conic[i * 3], opac[i]) : 2;
+    const int kind = tight == 2 ? tight_kind(&conic[i * 3], opac[i]) : 2;
+    reach32 z;
+    if (tight == 1) {
+      float v[6], alt[6];
+      record32_both(&mu_p[i * 2], &conic[i * 3], &cov2d[i * 3], opac[i], v, alt);
+      const rec32 r = rec_of(v);
+      z = reach32_setup(&r);
+    }
     for (int ty = rect[i * 4 + 1]; ty < rect[i * 4 + 3]; ++ty) {
       int c0 = rect[i * 4 + 0], c1 = rect[i * 4 + 2];
-      if (kind == 0) c1 = c0;
-      if (kind == 1)
-        tight_row(&mu_p[i * 2], &conic[i * 3], opac[i], ty, rect[i * 4 + 0], rect[i * 4 + 2], kTightGrow,
-                  kTightPad, &c0, &c1);
+      if (tight == 1) {
+        reach32_row(&z, ty, rect[i * 4 + 0], rect[i * 4 + 2], &c0, &c1);
+      } else {
+        if (kind == 0) c1 = c0;
+        if (kind == 1)
+          tight_row(&mu_p[i * 2], &conic[i * 3], opac[i], ty, rect[i * 4 + 0], rect[i * 4 + 2], kTightGrow,
+                    kTightPad, &c0, &c1);
+      }
       for (int tx = c0; tx < c1; ++tx) {
         p[k].key = ((uint64_t)(uint32_t)(ty * gx + tx) << 32) | bits;
         p[k].val = (uint32_t)i;
@@ -712,11 +960,35 @@ void orc_bin(int64_t n, const uint8_t* visible, const int32_t* rect, const float
 /* ------------------------------------------------------------------------ */
 /* Alpha blending (Eq. 3), per pixel of each 16x16 tile, front to back.      */
 /* ------------------------------------------------------------------------ */
+/*
+ * Ambiguity flags.  A renderer that evaluates the per-pixel decisions in
+ * binary32 takes them differently from this fp64 walk only where a compared
+ * value lies within its rounding error of the threshold.  Each decision is
+ * flagged when it lies within
+ *   fixed margin + err_scale * (a first-order bound of that rounding error)
+ * (relative).  The bound, with u = 2^-24:
+ *   alpha: the exponent q in binary32 has error <= 8 u (1 + |q|) from its own
+ *     operations (record values rounded once, a handful of products and sums
+ *     of like-signed terms, exp and the product o e^q included), plus
+ *     |dq/d delta| times the error of the pixel offset delta = mu_p - p, which
+ *     is formed tile-relative (the mean's float high part minus the tile
+ *     origin is exact, then the low part is added and the pixel's offset in
+ *     the tile subtracted: two roundings at magnitude <= |delta| + 16):
+ *     e_alpha = u (8 (1 + |q|) + sum_k |dq/d delta_k| (2 |delta_k| + 16));
+ *   T: each blended step multiplies T by 1 - alpha, whose relative error is
+ *     alpha / (1 - alpha) e_alpha plus one rounding, and rounds the product:
+ *     e_T accumulates alpha / (1 - alpha) e_alpha + 3 u per step.
+ * The transmittance stop of a step is flagged with the e_T of the value it
+ * compares, the alpha cut and the clamp with that pixel's e_alpha.
+ */
 typedef struct {
-  double tol_alpha; /* relative margin around 1/255 flagged as ambiguous */
-  double tol_T;     /* relative margin around the 1e-4 transmittance stop */
-  double tol_clamp; /* relative margin around the 0.99 alpha clamp */
+  double tol_alpha; /* fixed relative margin around 1/255 */
+  double tol_T;     /* fixed relative margin around the 1e-4 transmittance stop */
+  double tol_clamp; /* fixed relative margin around the 0.99 alpha clamp */
+  double err_scale; /* multiple of the binary32 error bound added to each margin (0: none) */
 } orc_tol;
+
+#define U32 5.9604644775390625e-08 /* 2^-24 */
 
 #define ALPHA_MIN (1.0 / 255.0)
 #define ALPHA_MAX 0.99
@@ -742,6 +1014,7 @@ static int walk_pixel(double px, double py, const uint32_t* ids, int64_t count, 
   *last = 0;
   *flag = 0;
   int64_t ev = 0;
+  double eT = 0.0; /* relative binary32 error bound of T */
   for (int64_t j = 0; j < count; ++j) {
     uint32_t g = ids[j];
     ++ev;
@@ -750,15 +1023,22 @@ static int walk_pixel(double px, double py, const uint32_t* ids, int64_t count, 
     double q = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy;
     if (fabs(q) < 1e-10) *flag |= 8;
     if (q > 0) continue;
+    double ea = 0.0;
+    if (tol->err_scale > 0) {
+      const double gx = A * dx + B * dy, gy = B * dx + Cc * dy;
+      ea = U32 * (8.0 * (1.0 + fabs(q)) + fabs(gx) * (2.0 * fabs(dx) + 16.0) + fabs(gy) * (2.0 * fabs(dy) + 16.0));
+    }
     double eq = exp(q);
     double raw = opac[g] * eq;
     double alpha = raw < ALPHA_MAX ? raw : ALPHA_MAX;
-    if (fabs(alpha - ALPHA_MIN) <= tol->tol_alpha * ALPHA_MIN) *flag |= 1;
+    if (fabs(alpha - ALPHA_MIN) <= (tol->tol_alpha + tol->err_scale * ea) * ALPHA_MIN) *flag |= 1;
     if (alpha < ALPHA_MIN) continue;
-    if (fabs(raw - ALPHA_MAX) <= tol->tol_clamp * ALPHA_MAX) *flag |= 4;
+    if (fabs(raw - ALPHA_MAX) <= (tol->tol_clamp + tol->err_scale * ea) * ALPHA_MAX) *flag |= 4;
     double tn = T * (1.0 - alpha);
-    if (fabs(tn - T_MIN) <= tol->tol_T * T_MIN) *flag |= 2;
+    const double etn = eT + alpha / (1.0 - alpha) * ea + 3.0 * U32;
+    if (fabs(tn - T_MIN) <= (tol->tol_T + tol->err_scale * etn) * T_MIN) *flag |= 2;
     if (tn < T_MIN) break;
+    eT = etn;
     for (int c = 0; c < 3; ++c) C[c] += rgb[g * 3 + c] * alpha * T;
     if (rec && nb < rec_cap) {
       rec[nb].id = g; rec[nb].alpha = alpha; rec[nb].T = T; rec[nb].eq = eq;
@@ -857,7 +1137,7 @@ void orc_blend_backward(int32_t width, int32_t height, const uint32_t* ranges, c
                         const float bg[3], const float* dL_dimg, double* g_mu_p, double* g_conic, double* g_opac,
                         double* g_rgb, double* g_abs) {
   const int gx = (width + TILE - 1) / TILE, gy = (height + TILE - 1) / TILE;
-  orc_tol tol = {0, 0, 0};
+  orc_tol tol = {0, 0, 0, 0};
 #pragma omp parallel
   {
     int64_t cap = 1 << 16;
@@ -1032,3 +1312,6 @@ void orc_preprocess_backward(int64_t n, const double* means, const double* scale
     g_opac[i] = g_opac2d[i];
   }
 }
+
+/* Threads of the OpenMP loops above (timing only; results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -49,7 +49,8 @@ class fgs_gaussians(ctypes.Structure):
 
 class fgs_grads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
-                ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("means2d", ctypes.c_void_p)]
+                ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("means2d", ctypes.c_void_p),
+                ("accumulate", ctypes.c_int32)]
 
 
 class fgs_layout(ctypes.Structure):

@@ -120,7 +120,7 @@ __device__ inline void fisheye_jacobian_vjp(const FisheyePoint& P, double fx, do
 // through theta and d: with F~ = (dF/dtheta) / l_z,
 //   grad F = F~ (z / d^2) (x, y, 0) - F~ (0, 0, l_z^2 / d^2) + (dF/dd) p / d.
 //
-// The panorama (Sec. 5.4) maps longitude atan2(x, z) and latitude
+// The panorama (Sec. 5.3) maps longitude atan2(x, z) and latitude
 // atan2(y, rho), rho = |(x, z)|, linearly: mu_p = c + (fx lon, fy lat).  Its
 // J rows are fx grad lon and fy grad lat; the backward takes the Hessians of
 // lon and lat against the two rows of dL/dJ.

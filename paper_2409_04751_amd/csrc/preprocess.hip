@@ -313,9 +313,11 @@ __device__ inline uint32_t entry_geometry(const PreArgs& a, uint32_t vi, uint32_
         const double A = G.conic[0], B = G.conic[1], iA = 1.0 / A;
         const float hx = (float)G.mu[0], hy = (float)G.mu[1];
         s0 = make_float4(hx, hy, (float)(G.mu[0] - (double)hx), (float)(G.mu[1] - (double)hy));
-        // D = C - B^2 / A = 1 / (det' A), det' the determinant of Sigma'
+        // D = C - B^2 / A = 1 / (det' A), det' the determinant of Sigma'.
+        // The alpha cut-off log2(1 / (255 o)) of the float product 255 o is
+        // taken in double and rounded once, like the other record values.
         s1 = make_float4((float)(-0.5 * kLog2e * A), (float)(B * iA), (float)(-0.5 * kLog2e / (G.det * A)),
-                         -__log2f(255.0f * o));
+                         (float)(-log2((double)(255.0f * o))));
         dist = sqrt((G.pc[0] * G.pc[0] + G.pc[1] * G.pc[1]) + G.pc[2] * G.pc[2]);
       }
     }
@@ -462,6 +464,7 @@ struct PreBwdArgs {
   float* g_opac;
   float* g_sh;
   float* g_means2d;
+  int accumulate;  // add to the gradient buffers instead of writing them
 };
 
 // Colour part of the backward, one thread per Gaussian: dL/dSH and the term
@@ -494,10 +497,17 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   sh_basis<DEG>(dir[0], dir[1], dir[2], Y);
   float gcol[3];
   for (int ch = 0; ch < 3; ++ch) gcol[ch] = (vis && !((mask >> ch) & 1u)) ? grgb[ch] : 0.0f;
+  if (a.accumulate) {
 #pragma unroll
-  for (int k = 0; k < nb; ++k)
+    for (int k = 0; k < nb; ++k)
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) a.g_sh[(size_t)(k * 3 + ch) * n + i] = Y[k] * gcol[ch];
+      for (int ch = 0; ch < 3; ++ch) a.g_sh[(size_t)(k * 3 + ch) * n + i] += Y[k] * gcol[ch];
+  } else {
+#pragma unroll
+    for (int k = 0; k < nb; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) a.g_sh[(size_t)(k * 3 + ch) * n + i] = Y[k] * gcol[ch];
+  }
   double gm[3] = {0.0, 0.0, 0.0};
   if constexpr (DEG > 0) {
     // sum over channels of dL/drgb_c times the colour's gradient in the direction
@@ -508,7 +518,10 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
     const double dd = (double)dir[0] * gd[0] + (double)dir[1] * gd[1] + (double)dir[2] * gd[2];
     for (int e = 0; e < 3; ++e) gm[e] = ((double)gd[e] - (double)dir[e] * dd) / vlen;
   }
-  for (int ch = 0; ch < 3; ++ch) a.g_means[ch * n + i] = vis ? (float)gm[ch] : 0.0f;
+  if (!a.accumulate)
+    for (int ch = 0; ch < 3; ++ch) a.g_means[ch * n + i] = vis ? (float)gm[ch] : 0.0f;
+  else if (vis && DEG > 0)
+    for (int ch = 0; ch < 3; ++ch) a.g_means[ch * n + i] += (float)gm[ch];
 }
 
 // Geometry part of the backward (Sec. 4.3): from dL/d(mu_p, conic, opacity)
@@ -523,12 +536,18 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
   const bool visible =
       a.tiles[i] != 0 && compute_geometry<MC>(a.means, a.scales, a.quats, a.opac, i, n, a.v, true, G);
   if (!visible) {
+    if (a.accumulate) return;
     for (int c = 0; c < 3; ++c) { a.g_means[c * n + i] = 0.0f; a.g_scales[c * n + i] = 0.0f; }
     for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = 0.0f;
     a.g_opac[i] = 0.0f;
     if (a.g_means2d) { a.g_means2d[i] = 0.0f; a.g_means2d[n + i] = 0.0f; }
     return;
   }
+  // written, or added to what earlier views left (the SH kernel has already
+  // put this view's view-direction term into g_means either way); a written
+  // buffer is never read, it may hold anything
+  const bool acc = a.accumulate != 0;
+  auto put = [acc](float* p, float v) { *p = acc ? *p + v : v; };
   const double gmu[2] = {a.grad2d[0 * (size_t)n + i], a.grad2d[1 * (size_t)n + i]};
   const double gA = a.grad2d[2 * (size_t)n + i], gB = a.grad2d[3 * (size_t)n + i], gC = a.grad2d[4 * (size_t)n + i];
   const float go = a.grad2d[5 * (size_t)n + i];
@@ -583,8 +602,8 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
     for (int c = 0; c < 3; ++c)
       dM[r * 3 + c] = 2.0 * (dS[r * 3 + 0] * M[0 * 3 + c] + dS[r * 3 + 1] * M[1 * 3 + c] + dS[r * 3 + 2] * M[2 * 3 + c]);
   for (int c = 0; c < 3; ++c)
-    a.g_scales[c * n + i] = (float)(dM[0 * 3 + c] * G.Rq[0 * 3 + c] + dM[1 * 3 + c] * G.Rq[1 * 3 + c] +
-                                    dM[2 * 3 + c] * G.Rq[2 * 3 + c]);
+    put(&a.g_scales[c * n + i], (float)(dM[0 * 3 + c] * G.Rq[0 * 3 + c] + dM[1 * 3 + c] * G.Rq[1 * 3 + c] +
+                                        dM[2 * 3 + c] * G.Rq[2 * 3 + c]));
   double dR[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * G.s[c];
@@ -599,11 +618,11 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
                  y * dR[7]);
   // through the normalisation q / |q|
   const double qd = G.qn[0] * gq[0] + G.qn[1] * gq[1] + G.qn[2] * gq[2] + G.qn[3] * gq[3];
-  for (int c = 0; c < 4; ++c) a.g_quats[c * n + i] = (float)((gq[c] - G.qn[c] * qd) / G.qnorm);
-  a.g_opac[i] = go;
+  for (int c = 0; c < 4; ++c) put(&a.g_quats[c * n + i], (float)((gq[c] - G.qn[c] * qd) / G.qnorm));
+  put(&a.g_opac[i], go);
   if (a.g_means2d) {
-    a.g_means2d[i] = (float)gmu[0];
-    a.g_means2d[n + i] = (float)gmu[1];
+    put(&a.g_means2d[i], (float)gmu[0]);
+    put(&a.g_means2d[n + i], (float)gmu[1]);
   }
 }
 
@@ -699,6 +718,7 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.g_opac = out.opacities;
   a.g_sh = out.sh;
   a.g_means2d = out.means2d;
+  a.accumulate = out.accumulate ? 1 : 0;
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
   {
     ProfScope prof(s, kKShBackward);

@@ -13,7 +13,16 @@
 // clamped to the row.
 //
 // Everything is evaluated in float from the stored record, so the count in
-// the preprocess and the walk in the duplication take the same decisions.
+// the preprocess and the walk in the duplication take the same decisions, and
+// each step is one correctly rounded operation (no contraction: the library
+// is built with -ffp-contract=off), in this order:
+//   P = -q2min, a = |A'|, d = |D'|; kind 0 if !(P >= 0); kind 2 if P <= 1e-6,
+//   !(|beta| <= 1e3), !(a > 0) or !(d > 0);
+//   Pg = P * 1.0201, ia = 1 / a, Pa = Pg * ia, da = d * ia,
+//   ry = sqrt(Pg * (1 / d)), ds = beta * sqrt((a * Pg) * (1 / (d * fma(beta * beta, a, d))));
+//   kind 2 if any of ry, |ds|, Pa, da is above 1e30 or not finite, else 1.
+// Per row (reach_row): dlo, dhi, the clamped peaks, s = sqrt(max(0, Pa - (da * y) * y)),
+// the x extremes and the columns, as written there.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,11 +39,13 @@ struct SplatReach {
   int kind;       // 0: no tile, 1: per-row intervals, 2: the whole rect
 };
 
-// v_sqrt_f32 / v_rcp_f32 (1 ulp): the decisions only need to agree between
-// the count and the walk, which both come through here; the margins dwarf
-// the rounding.
-__device__ inline float reach_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ inline float reach_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Correctly rounded square root and reciprocal (IEEE binary32, the HIP
+// defaults for sqrtf and /): with the plain correctly rounded +, *, fma,
+// floor and ceil below, every decision is a fixed function of the float
+// record, one that any IEEE float evaluation of the same steps reproduces bit
+// for bit.
+__device__ inline float reach_sqrt(float x) { return sqrtf(x); }
+__device__ inline float reach_rcp(float x) { return 1.0f / x; }
 
 // s0 = (mu_x hi, mu_y hi, mu_x lo, mu_y lo), s1 = (A', beta, D', q2min).
 __device__ inline SplatReach splat_reach(const float4& s0, const float4& s1) {

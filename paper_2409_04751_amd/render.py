@@ -53,11 +53,14 @@ def pose_struct(pose) -> L.fgs_pose:
 
 class Workspace:
     """Device scratch of one view, owned by PyTorch.  Keep it alive from a
-    forward to its backward; it grows when a view needs more intersections."""
+    forward to its backward; it grows when a view needs more intersections.
+    `generation` counts the forwards rendered into it: a backward checks that
+    no other forward has overwritten the state of its own."""
 
     def __init__(self, device=None):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buf: torch.Tensor | None = None
+        self.generation = 0
 
     @property
     def nbytes(self) -> int:
@@ -103,6 +106,7 @@ def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, ca
         ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, kcap))
     flags = (FGS_SAVE_PIXEL_STATE if save_pixel_state else 0) | (L.FGS_RECT_BINNING if binning == "rect" else 0)
     for _ in range(3):
+        ws.generation += 1
         rc, K = L.fgs_render_forward(g, p, c, bg, flags, ws.ptr, ws.nbytes, out.data_ptr(), _stream_handle(dev))
         if rc == L.FGS_ERR_WORKSPACE and K >= 0:
             ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, int(math.ceil(K * 1.15)) + 65536))
@@ -113,22 +117,45 @@ def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, ca
 
 
 def render_backward(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg, workspace: Workspace,
-                    dL_dimg: torch.Tensor, want_means2d: bool = False) -> dict:
-    """Gradients of one view for the workspace of its forward."""
+                    dL_dimg: torch.Tensor, want_means2d: bool = False, accumulate_into: dict | None = None) -> dict:
+    """Gradients of one view for the workspace of its forward.  With
+    accumulate_into (a dict of gradient tensors from an earlier call), the
+    view's gradients are added to those tensors, which are returned."""
     g = gaussians_struct(means, scales, quats, opacities, sh, sh_degree)
     if not dL_dimg.is_contiguous() or dL_dimg.dtype != torch.float32 or tuple(dL_dimg.shape) != (3, cam.height, cam.width):
         raise ValueError("dL_dimg must be contiguous float32 [3, H, W]")
-    out = dict(means=torch.empty_like(means), scales=torch.empty_like(scales), quats=torch.empty_like(quats),
-               opacities=torch.empty_like(opacities), sh=torch.empty_like(sh))
-    if want_means2d:
-        out["means2d"] = torch.empty((2, g.n), dtype=torch.float32, device=means.device)
+    if accumulate_into is not None:
+        out = accumulate_into
+        for k, ref in (("means", means), ("scales", scales), ("quats", quats), ("opacities", opacities), ("sh", sh)):
+            t = out[k]
+            if t.shape != ref.shape or t.dtype != torch.float32 or not t.is_contiguous() or t.device != ref.device:
+                raise ValueError(f"accumulated gradient {k} does not match its parameter")
+        if want_means2d and "means2d" not in out:
+            raise ValueError("accumulate_into has no means2d")
+    else:
+        out = dict(means=torch.empty_like(means), scales=torch.empty_like(scales), quats=torch.empty_like(quats),
+                   opacities=torch.empty_like(opacities), sh=torch.empty_like(sh))
+        if want_means2d:
+            out["means2d"] = torch.empty((2, g.n), dtype=torch.float32, device=means.device)
     gr = L.fgs_grads(out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(),
                      out["opacities"].data_ptr(), out["sh"].data_ptr(),
-                     out["means2d"].data_ptr() if want_means2d else None)
+                     out["means2d"].data_ptr() if want_means2d else None, 1 if accumulate_into is not None else 0)
     rc = L.fgs_render_backward(g, pose_struct(pose), camera_struct(cam), bg, workspace.ptr,
                                workspace.nbytes, dL_dimg.data_ptr(), gr, _stream_handle(means.device))
     L.check(rc)
     return out
+
+
+class WorkspaceReused(RuntimeError):
+    """A backward found its view's forward state overwritten by a later
+    forward on the same workspace."""
+
+
+def _check_generation(ws: Workspace, gen: int) -> None:
+    if ws.generation != gen:
+        raise WorkspaceReused(
+            "the workspace of this view was used by another forward before its backward "
+            f"(generation {ws.generation}, expected {gen}); give every view of a step its own Workspace")
 
 
 class _FisheyeRasterize(torch.autograd.Function):
@@ -140,13 +167,14 @@ class _FisheyeRasterize(torch.autograd.Function):
     def forward(ctx, means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, workspace):
         img, ws, K = render_forward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, workspace)
         ctx.save_for_backward(means, scales, quats, opacities, sh)
-        ctx.meta = (sh_degree, pose, cam, bg, ws)
+        ctx.meta = (sh_degree, pose, cam, bg, ws, ws.generation)
         return img
 
     @staticmethod
     def backward(ctx, dL):
         means, scales, quats, opacities, sh = ctx.saved_tensors
-        sh_degree, pose, cam, bg, ws = ctx.meta
+        sh_degree, pose, cam, bg, ws, gen = ctx.meta
+        _check_generation(ws, gen)
         g = render_backward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, ws, dL.contiguous())
         return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None, None
 
@@ -156,6 +184,59 @@ def rasterize(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg
     """Differentiable fisheye render of one view, [3, H, W]."""
     return _FisheyeRasterize.apply(means, scales, quats, opacities, sh, sh_degree, pose, cam, tuple(bg),
                                    workspace if workspace is not None else Workspace(means.device))
+
+
+class _FisheyeRasterizeViews(torch.autograd.Function):
+    """B views of one scene: each forward keeps its lists and 2D records in
+    its own workspace (no per-pixel transmittance); the backward runs the
+    views' backwards into one set of gradient buffers, the first writing and
+    the others adding, so B views cost one set of parameter gradients."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacities, sh, sh_degree, poses, cams, bgs, workspaces):
+        imgs = []
+        gens = []
+        for v, (pose, cam, bg, ws) in enumerate(zip(poses, cams, bgs, workspaces)):
+            img, _, _ = render_forward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, ws)
+            imgs.append(img)
+            gens.append(ws.generation)
+        ctx.save_for_backward(means, scales, quats, opacities, sh)
+        ctx.meta = (sh_degree, poses, cams, bgs, workspaces, gens)
+        return tuple(imgs)
+
+    @staticmethod
+    def backward(ctx, *dLs):
+        means, scales, quats, opacities, sh = ctx.saved_tensors
+        sh_degree, poses, cams, bgs, workspaces, gens = ctx.meta
+        for ws, gen in zip(workspaces, gens):
+            _check_generation(ws, gen)
+        g = None
+        for pose, cam, bg, ws, dL in zip(poses, cams, bgs, workspaces, dLs):
+            if dL is None:
+                continue
+            g = render_backward(means, scales, quats, opacities, sh, sh_degree, pose, cam, bg, ws, dL.contiguous(),
+                                accumulate_into=g)
+        if g is None:
+            return (None,) * 10
+        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None, None, None
+
+
+def rasterize_views(means, scales, quats, opacities, sh, sh_degree: int, poses, cams, bgs=None,
+                    workspaces: list | None = None) -> tuple:
+    """Differentiable fisheye render of several views of one scene (a training
+    step's batch of poses); returns one [3, H_v, W_v] image per view.  Each
+    view needs its own Workspace (created if not given), since a view's
+    backward reads the state its forward left there."""
+    B = len(poses)
+    if len(cams) != B:
+        raise ValueError("one camera per pose")
+    bgs = [tuple(b) for b in bgs] if bgs is not None else [(0.0, 0.0, 0.0)] * B
+    if workspaces is None:
+        workspaces = [Workspace(means.device) for _ in range(B)]
+    if len(workspaces) != B or len({id(w) for w in workspaces}) != B:
+        raise ValueError("rasterize_views needs one distinct Workspace per view")
+    return _FisheyeRasterizeViews.apply(means, scales, quats, opacities, sh, sh_degree, list(poses), list(cams),
+                                        bgs, list(workspaces))
 
 
 class _L1Loss(torch.autograd.Function):

@@ -33,7 +33,7 @@ TILE = 16
 @dataclasses.dataclass(frozen=True)
 class Camera:
     """Intrinsics of one view.  model: 0 equidistant fisheye (Sec. 3.2),
-    1 pinhole, 2 panorama (Sec. 5.4), 3 equisolid-angle, 4 orthographic,
+    1 pinhole, 2 panorama (Sec. 5.3), 3 equisolid-angle, 4 orthographic,
     5 stereographic fisheye."""
 
     width: int
@@ -125,7 +125,7 @@ def fisheye_camera(width: int, height: int, fov_deg: float, near: float = 0.2, m
 
 
 def panorama_camera(width: int, height: int, near: float = 0.2, lat_max: float = 0.45 * math.pi) -> Camera:
-    """Equirectangular panorama (Sec. 5.4): longitude over the full width,
+    """Equirectangular panorama (Sec. 5.3): longitude over the full width,
     latitude over the full height: f_x = width / (2 pi), f_y = height / pi,
     c = (width/2, height/2).  Gaussians above |latitude| lat_max are culled
     (theta_max carries it)."""

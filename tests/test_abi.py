@@ -35,7 +35,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(L.fgs_camera) == 4 + 4 + 8 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(L.fgs_pose) == 12 * 8
     assert ctypes.sizeof(L.fgs_gaussians) == 5 * 8 + 8 + 8
-    assert ctypes.sizeof(L.fgs_grads) == 6 * 8
+    assert ctypes.sizeof(L.fgs_grads) == 6 * 8 + 8  # six pointers, int32 accumulate, padding
 
 
 def test_version_and_workspace_arithmetic():

@@ -3,7 +3,8 @@
 The upstream gradient is random with zeros on pixels whose alpha cut or
 transmittance stop the oracle flags as within margin of the threshold (there
 the two precisions may take different discrete decisions).  Bar:
-  * per parameter block ||gpu - oracle|| / ||oracle|| <= 1e-4;
+  * per parameter block ||gpu - oracle|| / ||oracle|| <= 1e-4, and every
+    element within 1e-4 max(|ref|, 1e-3 ||ref||_inf);
   * blend backward, every per-Gaussian 2D gradient element within
     1e-4 |ref| + 1e-5 sum_pixels |term| (the rounding scale of its float sum);
   * preprocess backward, every element within 1e-5 |ref| + 1e-6 |ref column|
@@ -117,3 +118,63 @@ def test_autograd_function_recomputes_and_matches_direct_backward():
     for leaf, k in zip(leaves, ("means", "scales", "quats", "opacities", "sh")):
         a, b = leaf.grad.cpu().numpy(), ref[k].cpu().numpy()
         assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * max(np.abs(b).max(), 1e-30)), k
+
+
+def test_accumulate_mode_adds_a_second_view():
+    """fgs_grads.accumulate = 1 adds a view's gradient to the buffers: view A
+    written then view B accumulated equals A + B computed from two written
+    backwards, to fp32 accuracy (the blend's float atomics vary the last bits
+    of each run), and Gaussians culled in view B keep A's values."""
+    scene = synth.room_scene(20_000, 12, 0.01, 3)
+    cam = synth.fisheye_camera(160, 128, 200.0)
+    poses = [_posed(6), _posed(7)]
+    gs = to_gpu(scene)
+    rng = np.random.default_rng(4)
+    sep, wss = [], []
+    ups = [torch.from_numpy(rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda() for _ in poses]
+    for pose, g in zip(poses, ups):
+        _, ws, _ = gpu_forward(gs, pose, cam)
+        wss.append(ws)
+        sep.append(R.render_backward(*_params(gs), pose, cam, (0, 0, 0), ws, g, want_means2d=True))
+    acc = R.render_backward(*_params(gs), poses[0], cam, (0, 0, 0), wss[0], ups[0], want_means2d=True)
+    acc = R.render_backward(*_params(gs), poses[1], cam, (0, 0, 0), wss[1], ups[1], want_means2d=True,
+                            accumulate_into=acc)
+    torch.cuda.synchronize()
+    for k in ("scales", "quats", "opacities", "sh", "means2d"):
+        # the blend's float atomics make each view's own 2D gradients vary in
+        # their last bits from run to run, so compare to fp32 accuracy
+        torch.testing.assert_close(acc[k], sep[0][k] + sep[1][k], rtol=1e-5, atol=1e-6 * float(acc[k].abs().max()))
+    torch.testing.assert_close(acc["means"], sep[0]["means"] + sep[1]["means"], rtol=1e-5,
+                               atol=1e-6 * float(acc["means"].abs().max()))
+
+
+def test_rasterize_views_autograd_matches_oracle():
+    """Three views of different size and field of view through the multi-view
+    autograd function; a linear loss whose per-view weights are zero on the
+    pixels the oracle flags.  The summed parameter gradients against the
+    oracle's, every element."""
+    from parity import _stack2d_abs, check_blocks_elementwise, check_blocks_rel_l2
+
+    scene = synth.room_scene(20_000, 13, 0.01, 3)
+    cams = [synth.fisheye_camera(160, 128, 200.0), synth.fisheye_camera(96, 96, 150.0),
+            synth.fisheye_camera(130, 70, 185.0)]
+    poses = [_posed(8), _posed(9), _posed(10)]
+    gs = to_gpu(scene)
+    leaves = [gs[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacities", "sh")]
+    imgs = R.rasterize_views(*leaves, scene.sh_degree, poses, cams)
+    rng = np.random.default_rng(7)
+    total, scale = None, None
+    loss = 0.0
+    for img, pose, cam in zip(imgs, poses, cams):
+        ora = oracle.render(scene, pose, cam)
+        w = masked_upstream(ora, rng, cam)
+        loss = loss + (img * torch.from_numpy(w).cuda()).sum()
+        go = oracle.render_backward(scene, pose, cam, ora, w, abs_sums=True)
+        sc = oracle.chain_error_scale(scene, pose, cam, ora["pre"], _stack2d_abs(go.pop("g2d")))
+        total = go if total is None else {k: total[k] + go[k] for k in total}
+        scale = sc if scale is None else {k: scale[k] + sc[k] for k in scale}
+    loss.backward()
+    torch.cuda.synchronize()
+    grads = dict(means=leaves[0].grad, scales=leaves[1].grad, quats=leaves[2].grad, opacities=leaves[3].grad,
+                 sh=leaves[4].grad)
+    print(check_blocks_rel_l2(grads, total), check_blocks_elementwise(grads, total, err_scale=scale), flush=True)

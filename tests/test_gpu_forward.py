@@ -31,7 +31,7 @@ def _full_check(scene, pose, cam, bg=(0.0, 0.0, 0.0), save=False, binning="tight
     check_k(K, ora["pre"], ora["bins"])
     st = read_state(ws, scene.n, cam, K)
     compare_preprocess(st, ora["pre"])
-    compare_tile_lists(st, ora["bins"], ora["pre"])
+    compare_tile_lists(st, ora["bins"], ora["pre"], cam)
     stats = image_tolerance_check(img.cpu().numpy(), ora)
     print(stats, flush=True)
     return img, ws, K, st, ora

@@ -53,7 +53,7 @@ def test_forward_matches_oracle(model):
     check_k(K, ora["pre"], ora["bins"])
     st = read_state(ws, scene.n, cam, K)
     compare_preprocess(st, ora["pre"])
-    compare_tile_lists(st, ora["bins"], ora["pre"])
+    compare_tile_lists(st, ora["bins"], ora["pre"], cam)
     print(image_tolerance_check(img.cpu().numpy(), ora), flush=True)
 
 

@@ -1,13 +1,13 @@
 """Pins for the oracle's other camera models.
 
 Sec. 3.2 lists the equisolid-angle, orthographic and stereographic fisheye
-projections besides the equidistant one; Sec. 5.4 extends the method to a
+projections besides the equidistant one; Sec. 5.3 extends the method to a
 panorama and prints its projection and J.  The oracle takes J and dJ/dmu_c
 of these models as the first and second derivatives of the projection (by
 forward-mode differentiation), so they are pinned here against:
   * central finite differences of the projection and of J;
   * the textbook pinhole Jacobian [[f/z, 0, -f x/z^2], [0, f/z, -f y/z^2]];
-  * the panorama J the paper prints (Sec. 5.4);
+  * the panorama J the paper prints (Sec. 5.3);
   * landmark points of each lens law (where a 90 or 45 degree ray lands) and
     of the equirectangular map (straight ahead, sideways, behind);
   * the small-angle limit, where every radial model is the equidistant one
@@ -132,7 +132,7 @@ def test_radial_models_are_equidistant_near_the_axis(model):
 
 
 def _paper_panorama_jacobian(p, W, H):
-    """The J of the panorama as printed in Sec. 5.4 (image width W, height H)."""
+    """The J of the panorama as printed in Sec. 5.3 (image width W, height H)."""
     x, y, z = p
     r2 = x * x + z * z
     l2 = x * x + y * y + z * z

@@ -141,7 +141,9 @@ typedef struct fgs_layout {
   size_t tile_keys;    /* uint32 [K]: sorted tile id per intersection */
   size_t tile_ids;     /* uint32 [K]: Gaussian id per sorted intersection */
   size_t ranges;       /* uint32 [tiles][2]: [start, end) of each tile's run */
-  size_t grad2d;       /* float [9][n]: backward scratch (dL/d mu_p xy, conic A B C, opacity, rgb) */
+  size_t grad2d;       /* float [slot][9]: backward scratch, per Gaussian dL/d mu_p xy, conic A B C,
+                          opacity, rgb; Gaussian g at slot (g & ~63) | (9 g & 63) (a permutation
+                          inside each group of 64), n rounded up to a multiple of 64 slots */
   size_t pixel_T;      /* float [H][W]: final transmittance (FGS_SAVE_PIXEL_STATE) */
   size_t pixel_last;   /* uint32 [H][W]: 1 + list index of the last blended Gaussian */
   size_t counters;     /* uint32 [18]: [0] K, [1] visible count, [2] forward flags, [3..10] K per view,
@@ -254,6 +256,30 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
 int fgs_l1_loss(const float* image, const float* target, int64_t count, double* partials, float* loss, void* stream);
 int fgs_l1_loss_backward(const float* image, const float* target, int64_t count, const float* dL_dloss,
                          float* dL_dimage, void* stream);
+
+/*
+ * Spatial order of a scene, for storing a resident scene once (not part of
+ * the per-view path).  The paper's rasterizer reads each Gaussian's
+ * parameters, SH coefficients included, from structure-of-arrays planes; a
+ * view culls whole regions (behind the fisheye, outside the image), and with
+ * the Gaussians in random order every cache line of every plane still holds
+ * some visible Gaussian.  Sorting the scene by the Morton code of its means
+ * (a 1024^3 grid over their bounding box) puts culled Gaussians in long runs
+ * whose lines the preprocess then skips.
+ *
+ * fgs_spatial_order: means device [3][n]; order device uint32 [n] receives
+ * the permutation (order[j] = the Gaussian at position j), ties and
+ * non-finite means (sorted last) in id order; workspace device scratch of
+ * fgs_spatial_order_workspace_bytes(n) bytes.  Enqueues work only.
+ * fgs_gather_planes: out[p][j] = in[p][order[j]] for `planes` planes of
+ * length n (device, in != out): apply the order to every parameter array.
+ * Images and gradients of the reordered scene equal the original's (the
+ * gradients reordered the same way) up to depth ties, broken by the new ids.
+ */
+int fgs_spatial_order_workspace_bytes(int64_t n, size_t* bytes);
+int fgs_spatial_order(const float* means, int64_t n, uint32_t* order, void* workspace, size_t workspace_bytes,
+                      void* stream);
+int fgs_gather_planes(const float* in, float* out, int64_t planes, int64_t n, const uint32_t* order, void* stream);
 
 /*
  * Per-kernel timing with HIP events, for benchmarks and tracing.  While

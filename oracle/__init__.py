@@ -25,14 +25,23 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 TILE = 16
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: IEEE double, no FMA contraction, OpenMP."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc: IEEE double, no FMA contraction, OpenMP.
+    With sanitize, a separate copy instrumented with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only; loading it needs the ASan
+    runtime preloaded)."""
+    out = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        extra = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"])
+        cmd = ["gcc", *extra, "-std=c11", "-D_GNU_SOURCE", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class _Cam(ctypes.Structure):
@@ -50,11 +59,17 @@ _lib = None
 
 
 def lib():
+    """The oracle library; FGS_ORACLE_LIB=sanitized loads the instrumented
+    copy (built by build(sanitize=True))."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        _lib = ctypes.CDLL(_LIB)
+        if os.environ.get("FGS_ORACLE_LIB") == "sanitized":
+            path = _SAN_LIB
+        else:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        _lib = ctypes.CDLL(path)
         _lib.orc_count_pairs.restype = ctypes.c_int64
     return _lib
 

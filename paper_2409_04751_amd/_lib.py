@@ -96,6 +96,11 @@ SIGNATURES = {
                      ctypes.c_void_p], ctypes.c_int),
     "fgs_l1_loss_backward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_void_p], ctypes.c_int),
+    "fgs_spatial_order_workspace_bytes": ([ctypes.c_int64, ctypes.POINTER(c_size)], ctypes.c_int),
+    "fgs_spatial_order": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, c_size,
+                           ctypes.c_void_p], ctypes.c_int),
+    "fgs_gather_planes": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                           ctypes.c_void_p], ctypes.c_int),
     "fgs_profile_enable": ([ctypes.c_int32], ctypes.c_int),
     "fgs_profile_read": ([ctypes.POINTER(fgs_profile)], ctypes.c_int),
 }
@@ -197,6 +202,20 @@ def fgs_l1_loss(image: int, target: int, count: int, partials: int, loss: int, s
 
 def fgs_l1_loss_backward(image: int, target: int, count: int, dL_dloss: int, dL_dimage: int, stream: int) -> None:
     check(lib().fgs_l1_loss_backward(image, target, count, dL_dloss, dL_dimage, stream))
+
+
+def fgs_spatial_order_workspace_bytes(n: int) -> int:
+    out = c_size(0)
+    check(lib().fgs_spatial_order_workspace_bytes(n, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fgs_spatial_order(means: int, n: int, order: int, workspace: int, workspace_bytes: int, stream: int) -> None:
+    check(lib().fgs_spatial_order(means, n, order, workspace, workspace_bytes, stream))
+
+
+def fgs_gather_planes(src: int, dst: int, planes: int, n: int, order: int, stream: int) -> None:
+    check(lib().fgs_gather_planes(src, dst, planes, n, order, stream))
 
 
 def fgs_profile_enable(on: bool) -> None:

@@ -74,7 +74,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.drx_b = take(nv * 4);
   L.dry_b = take(nv * 4);
   L.offsets = take(nv * 4);
-  L.grad2d = take(nn * 9 * 4);
+  L.grad2d = take((size_t)grad_words((int64_t)nn) * 4);
   L.ranges = take((size_t)L.total_tiles * 8);
   L.pixel_T = take((size_t)L.total_pixels * 4);
   L.pixel_last = take((size_t)L.total_pixels * 4);
@@ -450,7 +450,7 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
   char* ws = static_cast<char*>(workspace);
   const ViewParams v = make_view(pose, cam, bg, 0u, 0u);
   float* grad2d = reinterpret_cast<float*>(ws + L.grad2d);
-  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * g->n, s), "clear grad2d");
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, grad_words(g->n), s), "clear grad2d");
   HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges),
                                 reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final),
                                 reinterpret_cast<const float4*>(ws + L.splats),
@@ -488,4 +488,32 @@ extern "C" int fgs_l1_loss_backward(const float* image, const float* target, int
   const hipError_t e =
       launch_l1_grad(image, target, count, dL_dloss, dL_dimage, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_l1_loss_backward");
+}
+
+extern "C" int fgs_spatial_order_workspace_bytes(int64_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(FGS_ERR_ARG, "fgs_spatial_order_workspace_bytes: bad argument");
+  if (n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "fgs_spatial_order_workspace_bytes: more than 2^31-1 Gaussians");
+  *bytes = spatial_order_workspace(n);
+  return FGS_OK;
+}
+
+extern "C" int fgs_spatial_order(const float* means, int64_t n, uint32_t* order, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  if (n < 0 || (n > 0 && (!means || !order || !workspace))) return fail(FGS_ERR_ARG, "fgs_spatial_order: bad argument");
+  if (n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "fgs_spatial_order: more than 2^31-1 Gaussians");
+  if (workspace_bytes < spatial_order_workspace(n))
+    return fail(FGS_ERR_WORKSPACE, "fgs_spatial_order: workspace smaller than fgs_spatial_order_workspace_bytes");
+  const hipError_t e =
+      launch_spatial_order(means, n, order, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_spatial_order");
+}
+
+extern "C" int fgs_gather_planes(const float* in, float* out, int64_t planes, int64_t n, const uint32_t* order,
+                                 void* stream) {
+  if (n < 0 || planes < 0 || (n > 0 && planes > 0 && (!in || !out || !order)))
+    return fail(FGS_ERR_ARG, "fgs_gather_planes: bad argument");
+  if (in == out && n > 0 && planes > 0) return fail(FGS_ERR_ARG, "fgs_gather_planes: in and out must differ");
+  if (n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "fgs_gather_planes: more than 2^31-1 Gaussians");
+  const hipError_t e = launch_gather_planes(in, out, planes, n, order, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_gather_planes");
 }

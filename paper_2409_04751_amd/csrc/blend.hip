@@ -18,6 +18,8 @@
 // Decisions (Eq. 3 plus the 3DGS cut-offs): skip when alpha < 1/255
 // (equivalently q2 < log2(1/(255 o))), alpha = min(0.99, o e^q), stop before
 // the Gaussian that would take T below 1e-4.
+#include <algorithm>
+
 #include "fgs_internal.hpp"
 
 namespace fgs {
@@ -27,6 +29,7 @@ constexpr float kTmin = 1e-4f;
 constexpr float kAlphaMax = 0.99f;
 
 struct BlendArgs {
+  uint32_t total_tiles;
   const uint2* ranges;
   const uint32_t* ids;
   const float4* splats;
@@ -200,15 +203,32 @@ __device__ inline void front_step(float fi, float fj, const float4& ga, const fl
   last = blend ? index + 1u : last;
 }
 
-// One block per tile of every view of the batch (tiles are numbered view by
-// view; the view of a block is found from the views' first tile ids).
-__global__ __launch_bounds__(kPairThreads) void blend_forward_kernel(BlendArgs a) {
-  __shared__ float4 sa[kPairChunk];
-  __shared__ float4 sb[kPairChunk];
-  __shared__ float2 sc[kPairChunk];
-  __shared__ HalfLists Q;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x);
+// The forward runs ONE wave per tile of every view of the batch (tiles are
+// numbered view by view; the view of a wave is found from the views' first
+// tile ids), each lane owning four pixels: column l & 15, rows (l >> 4) + 4k.
+// A wave stages 64 entries of its tile's list at a time (one per lane) in an
+// LDS region of its own, so there is no block barrier: a wave barrier makes
+// the staged records visible to its lanes.  The four pixels per lane are four
+// independent dependency chains per entry.
+constexpr int kFwdWaves = 4;  // tiles (waves) per block
+constexpr int kFwdThreads = 64 * kFwdWaves;
+constexpr int kFwdChunk = 64;
+
+struct FwdStage {
+  float4 sa[kFwdChunk];
+  float4 sb[kFwdChunk];
+  float2 sc[kFwdChunk];
+};
+
+// What a lane wrote to its wave's LDS before the call is visible to every
+// lane of the wave after it, and reads issued before it complete first.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void forward_tile(const BlendArgs& a, FwdStage& S, uint32_t gtile, uint32_t lane) {
   int vi = 0;
   while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
   const ViewParams& vp = a.batch.v[vi];
@@ -216,51 +236,58 @@ __global__ __launch_bounds__(kPairThreads) void blend_forward_kernel(BlendArgs a
   const int tx = tile % vp.tiles_x, ty = tile / vp.tiles_x;
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 r = a.ranges[gtile];
-  const int i = (int)(lane & 15u), j0 = (int)(8u * wave + (lane >> 4));
-  const float fi = (float)i, fj[2] = {(float)j0, (float)(j0 + 4)};
-  const int px = tx * kTile + i;
-  bool inside[2], done[2];
-  float T[2], C0[2], C1[2], C2[2];
-  uint32_t last[2];
-  for (int q = 0; q < 2; ++q) {
-    inside[q] = px < vp.width && ty * kTile + j0 + 4 * q < vp.height;
+  const float fi = (float)(lane & 15u);
+  const int px = tx * kTile + (int)(lane & 15u);
+  bool inside[4], done[4];
+  float fj[4], T[4], C0[4], C1[4], C2[4];
+  uint32_t last[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = (int)(lane >> 4) + 4 * q;
+    fj[q] = (float)j;
+    inside[q] = px < vp.width && ty * kTile + j < vp.height;
     done[q] = !inside[q];
     T[q] = 1.0f;
     C0[q] = C1[q] = C2[q] = 0.0f;
     last[q] = 0;
   }
-  for (uint32_t base = r.x; base < r.y; base += kPairChunk) {
-    if (__syncthreads_count(!(done[0] && done[1])) == 0) break;
-    const uint32_t k = base + threadIdx.x;
-    uint32_t m = 0;
+  for (uint32_t base = r.x; base < r.y; base += kFwdChunk) {
+    if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
+    const uint32_t k = base + lane;
     if (k < r.y) {
       float4 ta, tb;
       float2 tc;
       stage_splat(a.splats, a.colors, a.ids[k], x0, y0, ta, tb, tc);
-      sa[threadIdx.x] = ta;
-      sb[threadIdx.x] = tb;
-      sc[threadIdx.x] = tc;
-      m = half_mask(ta, tb);
+      S.sa[lane] = ta;
+      S.sb[lane] = tb;
+      S.sc[lane] = tc;
     }
-    const int cnt = build_half_lists(m, Q);
-    if (__ballot(!(done[0] && done[1])) != 0ull) {
-      const uint32_t first = base - r.x;
-      walk_half_list<false, true>(Q, wave, cnt, sa, sb, sc,
-                                  [&](int e, const float4& ga, const float4& gb, const float2& gc) {
-                                    const uint32_t index = first + (uint32_t)e;
+    wave_lds_sync();
+    const int cnt = (int)min((uint32_t)kFwdChunk, r.y - base);
+    const uint32_t first = base - r.x;
+    float4 na = S.sa[0], nb = S.sb[0];
+    float2 nc = S.sc[0];
+    for (int e = 0; e < cnt; ++e) {
+      const float4 ga = na, gb = nb;
+      const float2 gc = nc;
+      if (e + 1 < cnt) {
+        na = S.sa[e + 1];
+        nb = S.sb[e + 1];
+        nc = S.sc[e + 1];
+      }
 #pragma unroll
-                                    for (int q = 0; q < 2; ++q)
-                                      front_step<true>(fi, fj[q], ga, gb, gc, index, done[q], T[q], last[q], C0[q],
-                                                       C1[q], C2[q]);
-                                    return __ballot(!(done[0] && done[1])) == 0ull;
-                                  });
+      for (int q = 0; q < 4; ++q)
+        front_step<true>(fi, fj[q], ga, gb, gc, first + (uint32_t)e, done[q], T[q], last[q], C0[q], C1[q], C2[q]);
+      if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
     }
+    wave_lds_sync();  // this chunk's reads complete before the next staging overwrites it
   }
   const size_t hw = (size_t)vp.width * vp.height;
   float* out = a.out.rgb[vi];
-  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
     if (!inside[q]) continue;
-    const size_t p = (size_t)(ty * kTile + j0 + 4 * q) * vp.width + px;
+    const size_t p = (size_t)(ty * kTile + (int)(lane >> 4) + 4 * q) * vp.width + px;
     out[p] = __builtin_fmaf(T[q], vp.bg[0], C0[q]);
     out[hw + p] = __builtin_fmaf(T[q], vp.bg[1], C1[q]);
     out[2 * hw + p] = __builtin_fmaf(T[q], vp.bg[2], C2[q]);
@@ -271,19 +298,30 @@ __global__ __launch_bounds__(kPairThreads) void blend_forward_kernel(BlendArgs a
   }
 }
 
+__global__ __launch_bounds__(kFwdThreads) void blend_forward_kernel(BlendArgs a) {
+  __shared__ FwdStage stage[kFwdWaves];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  FwdStage& S = stage[wave];
+  // consecutive tiles in one block, neighbouring blocks on one XCD (tiles
+  // that gather the same splats share an L2)
+  const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x) * kFwdWaves + wave;
+  if (gtile < a.total_tiles) forward_tile(a, S, gtile, lane);
+}
+
+
 // ---------------------------------------------------------------------------
 struct BlendBwdArgs {
   const uint2* ranges;
   const uint32_t* ids;
   const float4* splats;
   const float4* colors;
-  int32_t width, height, tiles_x;
+  int32_t width, height, tiles_x, tiles_y;
   float bg[3];
   const float* dL;
   const float* pixel_T;
   const uint32_t* pixel_last;
   const uint32_t* counters;
-  float* grad2d;  // [9][n]
+  float* grad2d;  // [grad_slot(g)][9]
   uint32_t n;
 };
 
@@ -333,23 +371,23 @@ __device__ inline float row_reduce_scatter9(const float v[9], bool b3, bool b2, 
 
 // State of one pixel in the backward.
 struct BwdPixel {
-  float fi, fj;        // tile-relative position
+  float fj;            // tile-relative row (the column is the lane's)
   bool inside;
-  size_t p;            // index in the image
   float T;             // final transmittance, then transmittance in front of the current splat
   uint32_t last;       // 1 + list index of its last blended splat
   float G0, G1, G2;    // dL/dC
   float B0, B1, B2;    // colour behind the current splat
 };
 
-// Reverse step for one pixel, adding its 9 gradient terms to v.  One path
-// for every lane: a pixel the splat does not reach takes alpha = 0, which
-// leaves its transmittance and colour-behind exactly unchanged and adds
-// zeros, so the DPP exchange needs no branches.  Terms 0-4 are accumulated
-// without their constant factors (kGradScale), which are applied once per
-// splat when the block's sums are flushed.
-__device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx, float dy, float t, const float4& ga,
-                                    const float4& gb, const float2& gc, float v[9]) {
+// Reverse step for one pixel: recovers the transmittance in front of the
+// splat, adds the pixel's colour and opacity gradient terms to v[5..8],
+// updates the colour behind, and returns dL/dq (q the natural-log exponent)
+// for the mean and conic terms, which the caller accumulates as moments.  One
+// path for every lane: a pixel the splat does not reach takes alpha = 0,
+// which leaves its transmittance and colour-behind exactly unchanged and adds
+// zeros, so the lane exchanges need no branches.
+__device__ inline float reverse_step(BwdPixel& px, bool pass, float q2, const float4& gb, const float2& gc,
+                                     float v[9]) {
   const float eq = __builtin_amdgcn_exp2f(q2);
   const float raw = gb.z * eq;
   const float alpha = pass ? fminf(kAlphaMax, raw) : 0.0f;
@@ -367,176 +405,227 @@ __device__ inline void reverse_step(BwdPixel& px, bool pass, float q2, float dx,
   px.T = Ti;
   const float dl = (pass && raw < kAlphaMax) ? dLda : 0.0f;  // the clamp passes no gradient
   v[5] = __builtin_fmaf(dl, eq, v[5]);
-  const float g = dl * alpha;  // dL/dq of the natural exponent
-  const float azt = ga.z * t, bdy = gb.x * dy;  // products the exponent formed
-  v[0] = __builtin_fmaf(g, azt, v[0]);
-  v[1] = __builtin_fmaf(g, __builtin_fmaf(ga.w, azt, bdy), v[1]);
-  const float gdx = g * dx, gdy = g * dy;
-  v[2] = __builtin_fmaf(gdx, dx, v[2]);
-  v[3] = __builtin_fmaf(gdx, dy, v[3]);
-  v[4] = __builtin_fmaf(gdy, dy, v[4]);
+  return dl * alpha;
 }
 
-// Factors of the accumulated terms.  With q = -(A t^2 + D dy^2) / 2 and the
-// record's A' = -A/(2 ln2), D' = -D/(2 ln2): dL/dmu_x = -sum g A t =
-// 2 ln2 sum g A' t, dL/dmu_y = -sum g (beta A t + D dy) = 2 ln2 sum g (beta A' t
-// + D' dy), dL/dA = -sum g dx^2 / 2, dL/dB = -sum g dx dy (B enters q twice),
-// dL/dC = -sum g dy^2 / 2.
+// Sum over the 64 lanes of a wave, on every lane, with the two gfx950 lane
+// swaps (halves, then neighbouring 16-lane rows): no LDS round trip.
+__device__ inline float wave_rows_sum(float x) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// The mean and conic terms from the moments of g = dL/dq over the pixels.
+// With q = -(A t^2 + D dy^2) / 2 (natural log), t = dx + beta dy, and the
+// record's A' = -A/(2 ln2), D' = -D/(2 ln2): dq/dmu_x = -A t = 2 ln2 A' t,
+// dq/dmu_y = -(beta A t + D dy) = 2 ln2 (beta A' t + D' dy), dq/dA = -dx^2/2,
+// dq/dB = -dx dy (B enters q twice), dq/dC = -dy^2/2.  Per lane and entry the
+// moments sum_g g t, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2 over the
+// lane's four pixels share dx (one column); v[0] and v[1] take the record's
+// factors, the constants below are applied once per entry.
 __constant__ const float kGradScale[9] = {1.3862943611198906f, 1.3862943611198906f, -0.5f, -1.0f, -0.5f,
                                           1.0f, 1.0f, 1.0f, 1.0f};
 
-__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(7))) void blend_backward_kernel(BlendBwdArgs a) {
-  __shared__ float4 sa[kPairChunk];
-  __shared__ float4 sb[kPairChunk];
-  __shared__ float2 sc[kPairChunk];
-  __shared__ uint32_t sid[kPairChunk];
-  __shared__ float acc[9][kPairChunk];
-  __shared__ uint32_t s_maxlast;
-  __shared__ HalfLists Q;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  const int tile = (int)xcd_chunk(blockIdx.x, gridDim.x);
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+// The backward runs ONE wave per tile, each lane owning four pixels of the
+// tile: column l & 15, rows (l >> 4) + 4k, k = 0..3.  A wave shares nothing
+// with the other waves of its block (its LDS is its own), so there is no
+// block barrier anywhere: a wave stages 64 entries of its tile's list at a
+// time (one per lane), makes them visible to its own lanes with a wave
+// barrier, and walks them; the four pixels per lane are four independent
+// dependency chains per entry.  Per entry the wave's 9 gradient sums are
+// reduced in registers (a DPP reduce-scatter inside each 16-lane row, then
+// the four rows added with two lane exchanges) and added to the global
+// accumulators by the 9 lanes holding them: no LDS accumulators and no
+// flush phase.
+constexpr int kBwdWaves = 4;              // tiles (waves) per block
+constexpr int kBwdThreads = 64 * kBwdWaves;
+constexpr int kBwdChunk = 64;             // entries staged per step
+
+struct BwdStage {
+  float4 sa[kBwdChunk];
+  float4 sb[kBwdChunk];
+  float2 sc[kBwdChunk];
+  uint32_t sid[kBwdChunk];
+};
+
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_t tile, uint32_t lane) {
+  const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 r = a.ranges[tile];
   const size_t hw = (size_t)a.width * a.height;
   const bool saved = (a.counters[kCountFlags] & FGS_SAVE_PIXEL_STATE) != 0;
-  BwdPixel P[2];
-  for (int q = 0; q < 2; ++q) {
-    const int i = (int)(lane & 15u), j = (int)(8u * wave + (lane >> 4) + 4u * q);
-    const int px = tx * kTile + i, py = ty * kTile + j;
-    P[q].fi = (float)i;
-    P[q].fj = (float)j;
-    P[q].inside = px < a.width && py < a.height;
-    P[q].p = (size_t)py * a.width + px;
-    P[q].T = 1.0f;
-    P[q].last = 0;
+  const float fi = (float)(lane & 15u);
+  const int px = tx * kTile + (int)(lane & 15u);
+  BwdPixel P[4];
+  size_t pidx[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int j = (int)(lane >> 4) + 4 * k;
+    const int py = ty * kTile + j;
+    P[k].fj = (float)j;
+    P[k].inside = px < a.width && py < a.height;
+    pidx[k] = P[k].inside ? (size_t)py * a.width + px : 0;
+    P[k].T = 1.0f;
+    P[k].last = 0;
   }
 
   // ---- final transmittance and last contributor of each pixel ----
   if (saved) {
-    for (int q = 0; q < 2; ++q)
-      if (P[q].inside) {
-        P[q].T = a.pixel_T[P[q].p];
-        P[q].last = a.pixel_last[P[q].p];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (P[k].inside) {
+        P[k].T = a.pixel_T[pidx[k]];
+        P[k].last = a.pixel_last[pidx[k]];
       }
   } else {
-    bool done0 = !P[0].inside, done1 = !P[1].inside;
-    for (uint32_t base = r.x; base < r.y; base += kPairChunk) {
-      if (__syncthreads_count(!(done0 && done1)) == 0) break;
-      const uint32_t k = base + threadIdx.x;
-      uint32_t m = 0;
+    bool done[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) done[k] = !P[k].inside;
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;  // unused: the re-sweep accumulates no colour
+    for (uint32_t base = r.x; base < r.y; base += kBwdChunk) {
+      if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
+      const uint32_t k = base + lane;
       if (k < r.y) {
         float4 ta, tb;
         float2 tc;
         stage_splat(a.splats, a.colors, a.ids[k], x0, y0, ta, tb, tc);
-        sa[threadIdx.x] = ta;
-        sb[threadIdx.x] = tb;
-        m = half_mask(ta, tb);
+        S.sa[lane] = ta;
+        S.sb[lane] = tb;
       }
-      const int cnt = build_half_lists(m, Q);
-      if (__ballot(!(done0 && done1)) != 0ull) {
-        const uint32_t first = base - r.x;
-        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;  // unused: the re-sweep accumulates no colour
-        walk_half_list<false, false>(Q, wave, cnt, sa, sb, sc,
-                                     [&](int e, const float4& ga, const float4& gb, const float2& gc) {
-                                       const uint32_t index = first + (uint32_t)e;
-                                       front_step<false>(P[0].fi, P[0].fj, ga, gb, gc, index, done0, P[0].T,
-                                                         P[0].last, c0, c1, c2);
-                                       front_step<false>(P[1].fi, P[1].fj, ga, gb, gc, index, done1, P[1].T,
-                                                         P[1].last, c0, c1, c2);
-                                       return __ballot(!(done0 && done1)) == 0ull;
-                                     });
+      wave_lds_sync();
+      const int cnt = (int)min((uint32_t)kBwdChunk, r.y - base);
+      const uint32_t first = base - r.x;
+      float4 na = S.sa[0], nb = S.sb[0];
+      for (int e = 0; e < cnt; ++e) {
+        const float4 ga = na, gb = nb;
+        if (e + 1 < cnt) {
+          na = S.sa[e + 1];
+          nb = S.sb[e + 1];
+        }
+        const float2 gc = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          front_step<false>(fi, P[q].fj, ga, gb, gc, first + (uint32_t)e, done[q], P[q].T, P[q].last, c0, c1, c2);
+        if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
       }
+      wave_lds_sync();  // this chunk's reads complete before the next staging overwrites it
     }
   }
-  if (threadIdx.x == 0) s_maxlast = 0;
-  __syncthreads();
-  uint32_t wlast = max(P[0].last, P[1].last);  // this wave's largest last contributor
-  for (int d = 32; d >= 1; d >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, d, 64));
-  wlast = __builtin_amdgcn_readfirstlane(wlast);
-  if (lane == 0) atomicMax(&s_maxlast, wlast);
-  __syncthreads();
-  const uint32_t maxlast = s_maxlast;
+  const uint32_t maxlast = wave_max_u32(max(max(P[0].last, P[1].last), max(P[2].last, P[3].last)));
 
   // ---- reverse sweep ----
-  for (int q = 0; q < 2; ++q) {
-    P[q].G0 = P[q].G1 = P[q].G2 = 0.0f;
-    if (P[q].inside) {
-      P[q].G0 = a.dL[P[q].p];
-      P[q].G1 = a.dL[hw + P[q].p];
-      P[q].G2 = a.dL[2 * hw + P[q].p];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    P[k].G0 = P[k].G1 = P[k].G2 = 0.0f;
+    if (P[k].inside) {
+      P[k].G0 = a.dL[pidx[k]];
+      P[k].G1 = a.dL[hw + pidx[k]];
+      P[k].G2 = a.dL[2 * hw + pidx[k]];
     }
-    P[q].B0 = a.bg[0];
-    P[q].B1 = a.bg[1];
-    P[q].B2 = a.bg[2];
+    P[k].B0 = a.bg[0];
+    P[k].B1 = a.bg[1];
+    P[k].B2 = a.bg[2];
   }
-  // this lane's slot in the row reduce-scatter
-  const uint32_t rpos = threadIdx.x & 15u;
+  // this lane's slot in the row reduce-scatter; lanes of the first row hold
+  // the wave's totals after the rows are added
+  const uint32_t rpos = lane & 15u;
   const bool rb3 = (rpos >> 3) & 1u, rb2 = (rpos >> 2) & 1u, rb1 = (rpos >> 1) & 1u, rb0 = rpos & 1u;
   const int rval = (rb3 ? 5 : 0) + (rb2 ? 3 : 0) + (rb1 ? 2 : 0) + (rb0 ? 1 : 0);
-  const bool rvalid = (kRowValid >> rpos) & 1u;
-  for (int end = (int)maxlast; end > 0; end -= kPairChunk) {
-    const int beg = max(end - kPairChunk, 0);
-    __syncthreads();
-    uint32_t m = 0;
-    if (beg + (int)threadIdx.x < end) {
-      const uint32_t g = a.ids[r.x + beg + threadIdx.x];
-      sid[threadIdx.x] = g;
+  const bool writer = lane < 16u && ((kRowValid >> rpos) & 1u);
+  const float wscale = writer ? kGradScale[rval] : 0.0f;
+  // a Gaussian's nine sums are adjacent ([slot][9]), so the nine writer
+  // lanes' atomics go to one or two cache lines
+  float* const gout = a.grad2d + (writer ? rval : 0);
+  for (int end = (int)maxlast; end > 0; end -= kBwdChunk) {
+    const int beg = max(end - kBwdChunk, 0);
+    if (beg + (int)lane < end) {
+      const uint32_t g = a.ids[r.x + beg + lane];
       float4 ta, tb;
       float2 tc;
       stage_splat(a.splats, a.colors, g, x0, y0, ta, tb, tc);
-      sa[threadIdx.x] = ta;
-      sb[threadIdx.x] = tb;
-      sc[threadIdx.x] = tc;
-      m = half_mask(ta, tb);
+      S.sa[lane] = ta;
+      S.sb[lane] = tb;
+      S.sc[lane] = tc;
+      S.sid[lane] = g;
     }
-    for (int k = 0; k < 9; ++k) acc[k][threadIdx.x] = 0.0f;
-    int cnt = build_half_lists(m, Q);
-    {
-      // the list is in entry order: only its prefix below this wave's last
-      // contributor serves a pixel, so the reverse walk starts there
-      const int lim = (int)wlast - beg;
-      const uint8_t* li = Q.idx[wave];
-      const bool below0 = (int)lane < cnt && (int)li[lane] < lim;
-      const bool below1 = (int)lane + 64 < cnt && (int)li[lane + 64] < lim;
-      cnt = __builtin_popcountll(__ballot(below0)) + __builtin_popcountll(__ballot(below1));
-    }
-    walk_half_list<true, true>(Q, wave, cnt, sa, sb, sc,
-                               [&](int idx, const float4& ga, const float4& gb, const float2& gc) {
-                                 const uint32_t e = (uint32_t)(beg + idx);
-                                 if (e >= wlast) return false;  // past every pixel of this wave
-                                 float dx0, dy0, t0, dx1, dy1, t1;
-                                 const float q20 = exponent2(ga, gb, P[0].fi, P[0].fj, dx0, dy0, t0);
-                                 const float q21 = exponent2(ga, gb, P[1].fi, P[1].fj, dx1, dy1, t1);
-                                 const bool pass0 = e < P[0].last && q20 >= gb.y;
-                                 const bool pass1 = e < P[1].last && q21 >= gb.y;
-                                 if (__ballot(pass0 || pass1) == 0ull) return false;  // wave-uniform
-                                 float v[9];
-                                 for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-                                 reverse_step(P[0], pass0, q20, dx0, dy0, t0, ga, gb, gc, v);
-                                 reverse_step(P[1], pass1, q21, dx1, dy1, t1, ga, gb, gc, v);
-                                 // wave-uniform: every lane takes part in the DPP exchanges
-                                 const float part = row_reduce_scatter9(v, rb3, rb2, rb1, rb0);
-                                 if (rvalid) atomicAdd(&acc[rval][idx], part);
-                                 return false;
-                               });
-    __syncthreads();
-    if ((int)threadIdx.x < end - beg) {
-      const uint32_t g = sid[threadIdx.x];
-      for (int k = 0; k < 9; ++k) {
-        const float val = acc[k][threadIdx.x] * kGradScale[k];
-        if (val != 0.0f) atomicAdd(&a.grad2d[(size_t)k * a.n + g], val);
+    wave_lds_sync();
+    const int cnt = end - beg;
+    float4 na = S.sa[cnt - 1], nb = S.sb[cnt - 1];
+    float2 nc = S.sc[cnt - 1];
+    for (int idx = cnt - 1; idx >= 0; --idx) {
+      const float4 ga = na, gb = nb;
+      const float2 gc = nc;
+      if (idx > 0) {
+        na = S.sa[idx - 1];
+        nb = S.sb[idx - 1];
+        nc = S.sc[idx - 1];
+      }
+      const uint32_t e = (uint32_t)(beg + idx);
+      // the exponent as the forward forms it (bit for bit); dx is shared by
+      // the lane's four pixels, which lie in one column
+      const float dx = ga.x - fi;
+      float q2[4], dy[4];
+      bool pass[4];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dy[k] = ga.y - P[k].fj;
+        const float t = __builtin_fmaf(ga.w, dy[k], dx);
+        q2[k] = __builtin_fmaf(ga.z * t, t, (gb.x * dy[k]) * dy[k]);
+        pass[k] = e < P[k].last && q2[k] >= gb.y;
+        any = any || pass[k];
+      }
+      if (__ballot(any) == 0ull) continue;  // wave-uniform
+      float v[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+      float gs = 0.0f, gy = 0.0f, gyy = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float g = reverse_step(P[k], pass[k], q2[k], gb, gc, v);
+        const float gdy = g * dy[k];
+        gs += g;
+        gy += gdy;
+        gyy = __builtin_fmaf(gdy, dy[k], gyy);
+      }
+      const float gt = __builtin_fmaf(ga.w, gy, dx * gs);  // sum g t
+      v[0] = ga.z * gt;
+      v[1] = __builtin_fmaf(ga.w, v[0], gb.x * gy);
+      v[2] = (dx * dx) * gs;
+      v[3] = dx * gy;
+      v[4] = gyy;
+      // wave-uniform: every lane takes part in the exchanges
+      const float part = wave_rows_sum(row_reduce_scatter9(v, rb3, rb2, rb1, rb0));
+      if (writer) {
+        const float val = part * wscale;
+        if (val != 0.0f) atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
       }
     }
+    wave_lds_sync();
   }
+}
+
+__global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArgs a) {
+  __shared__ BwdStage stage[kBwdWaves];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  BwdStage& S = stage[wave];
+  const uint32_t tile = xcd_chunk(blockIdx.x, gridDim.x) * kBwdWaves + wave;
+  if (tile < (uint32_t)a.tiles_x * (uint32_t)a.tiles_y) backward_tile(a, S, tile, lane);
 }
 
 }  // namespace
 
 hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
                                 const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
-                                uint32_t* pixel_last,
-                                bool save, hipStream_t s) {
+                                uint32_t* pixel_last, bool save, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
   BlendArgs a;
   a.ranges = ranges;
@@ -548,8 +637,10 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
   a.save = save ? 1 : 0;
   a.out = out;
   a.batch = b;
+  a.total_tiles = (uint32_t)total_tiles;
   ProfScope prof(s, kKBlendForward);
-  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)total_tiles), dim3(kPairThreads), 0, s, a);
+  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)ceil_div(total_tiles, kFwdWaves)), dim3(kFwdThreads), 0, s,
+                     a);
   return hipGetLastError();
 }
 
@@ -565,6 +656,7 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.width = v.width;
   a.height = v.height;
   a.tiles_x = v.tiles_x;
+  a.tiles_y = v.tiles_y;
   for (int c = 0; c < 3; ++c) a.bg[c] = v.bg[c];
   a.dL = dL_dimg;
   a.pixel_T = pixel_T;
@@ -572,9 +664,9 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.counters = counters;
   a.grad2d = grad2d;
   a.n = (uint32_t)n;
-  const unsigned tiles = (unsigned)v.tiles_x * (unsigned)v.tiles_y;
+  const int64_t tiles = (int64_t)v.tiles_x * v.tiles_y;
   ProfScope prof(s, kKBlendBackward);
-  hipLaunchKernelGGL(blend_backward_kernel, dim3(tiles), dim3(kPairThreads), 0, s, a);
+  hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)ceil_div(tiles, kBwdWaves)), dim3(kBwdThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -32,6 +32,15 @@ __device__ inline uint32_t xcd_chunk(uint32_t b, uint32_t nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Slot of Gaussian g in the per-Gaussian gradient sums ([slot][9] floats):
+// ids are permuted inside each aligned group of 64 (g * 9 mod 64), so
+// Gaussians with adjacent ids -- neighbours in space when a scene is stored
+// in spatial order -- accumulate into cache lines about 2.5 lines apart, while
+// the 64 Gaussians of a wave still read one contiguous 2304-byte block.
+__host__ __device__ inline uint32_t grad_slot(uint32_t g) { return (g & ~63u) | ((g * 9u) & 63u); }
+// u32 words of the gradient sums for n Gaussians (whole groups of 64)
+inline int64_t grad_words(int64_t n) { return (n + 63) / 64 * 64 * 9; }
+
 // What a device-wide scan reads.
 enum ScanMode {
   kScanPlain = 0,     // in_a[i]
@@ -69,6 +78,7 @@ enum KernelId {
   kKColor,
   kKRows,
   kKLoss,
+  kKOrder,
   kKNumKernels
 };
 const char* kernel_name(int id);
@@ -228,9 +238,10 @@ hipError_t launch_clear_but_one(uint32_t* p, int64_t count, int64_t at, uint32_t
 
 hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const uint2* ranges, const uint32_t* ids,
                                 const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
-                                uint32_t* pixel_last,
-                                bool save, hipStream_t s);
+                                uint32_t* pixel_last, bool save, hipStream_t s);
 
+// grad2d: [grad_slot(g)][9] per-Gaussian sums (dL/d mu_p xy, conic A B C, opacity, rgb),
+// grad_words(n) zeroed words
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids,
                                  const float4* splats, const float4* colors, const float* dL_dimg,
                                  const float* pixel_T,
@@ -246,5 +257,14 @@ hipError_t launch_l1_loss(const float* image, const float* target, int64_t count
                           hipStream_t s);
 hipError_t launch_l1_grad(const float* image, const float* target, int64_t count, const float* dl, float* out,
                           hipStream_t s);
+// Spatial order of a scene (Morton code of the means, ties by id): the
+// permutation into `order` (device [n]), scratch `ws` of
+// spatial_order_workspace(n) bytes; and the gather of parameter planes by it.
+size_t spatial_order_workspace(int64_t n);
+hipError_t launch_spatial_order(const float* means, int64_t n, uint32_t* order, char* ws, hipStream_t s);
+hipError_t launch_gather_planes(const float* in, float* out, int64_t planes, int64_t n, const uint32_t* order,
+                                hipStream_t s);
+
+
 
 }  // namespace fgs

@@ -456,7 +456,7 @@ struct PreBwdArgs {
   int sh_degree;
   ViewParams v;
   const uint32_t* tiles;
-  const float* grad2d;  // [9][n]
+  const float* grad2d;  // [grad_slot(i)][9]
   const float4* colorjac;  // [n][3], from the forward
   float* g_means;
   float* g_scales;
@@ -483,7 +483,8 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
   // read: the forward left, per channel, the colour's gradient in the view
   // direction and the clamp mask.
   const bool vis = a.tiles[i] != 0;
-  const float grgb[3] = {a.grad2d[6 * (size_t)n + i], a.grad2d[7 * (size_t)n + i], a.grad2d[8 * (size_t)n + i]};
+  const float* g2 = a.grad2d + 9 * (size_t)grad_slot(i);
+  const float grgb[3] = {g2[6], g2[7], g2[8]};
   float4 J0 = make_float4(0.f, 0.f, 0.f, 0.f), J1 = J0, J2 = J0;
   if (vis) {
     J0 = a.colorjac[3 * (size_t)i + 0];
@@ -548,9 +549,10 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
   // buffer is never read, it may hold anything
   const bool acc = a.accumulate != 0;
   auto put = [acc](float* p, float v) { *p = acc ? *p + v : v; };
-  const double gmu[2] = {a.grad2d[0 * (size_t)n + i], a.grad2d[1 * (size_t)n + i]};
-  const double gA = a.grad2d[2 * (size_t)n + i], gB = a.grad2d[3 * (size_t)n + i], gC = a.grad2d[4 * (size_t)n + i];
-  const float go = a.grad2d[5 * (size_t)n + i];
+  const float* g2 = a.grad2d + 9 * (size_t)grad_slot(i);
+  const double gmu[2] = {g2[0], g2[1]};
+  const double gA = g2[2], gB = g2[3], gC = g2[4];
+  const float go = g2[5];
   // H = dL/dSigma' = -Q Gs Q with Gs = [[gA, gB/2], [gB/2, gC]]
   const double Q00 = G.conic[0], Q01 = G.conic[1], Q11 = G.conic[2];
   const double G00 = gA, G01 = 0.5 * gB, G11 = gC;

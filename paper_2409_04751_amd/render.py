@@ -239,6 +239,41 @@ def rasterize_views(means, scales, quats, opacities, sh, sh_degree: int, poses, 
                                         bgs, list(workspaces))
 
 
+def spatial_order(means: torch.Tensor) -> torch.Tensor:
+    """Permutation (int64 [N], on the device) that sorts a scene by the Morton
+    code of its means (fgs_spatial_order); ties in id order."""
+    if means.dim() != 2 or means.shape[0] != 3 or means.dtype != torch.float32 or not means.is_contiguous():
+        raise ValueError("means must be contiguous float32 [3, N]")
+    n = int(means.shape[1])
+    order = torch.empty(n, dtype=torch.int32, device=means.device)
+    ws = torch.empty(L.fgs_spatial_order_workspace_bytes(n), dtype=torch.uint8, device=means.device)
+    L.fgs_spatial_order(means.data_ptr(), n, order.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(means.device))
+    return order.long()
+
+
+def gather_planes(t: torch.Tensor, order: torch.Tensor) -> torch.Tensor:
+    """t[:, order] for a parameter array of planes [P, N] (or [N]) through
+    fgs_gather_planes."""
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("gather_planes takes contiguous float32 tensors")
+    n = int(t.shape[-1])
+    planes = 1 if t.dim() == 1 else int(t.shape[0])
+    idx = order.to(torch.int32).contiguous()
+    if idx.numel() != n:
+        raise ValueError("order and tensor differ in length")
+    out = torch.empty_like(t)
+    L.fgs_gather_planes(t.data_ptr(), out.data_ptr(), planes, n, idx.data_ptr(), _stream_handle(t.device))
+    return out
+
+
+def spatially_ordered(means, scales, quats, opacities, sh):
+    """The scene's parameter arrays permuted into Morton order of the means,
+    and the permutation: what a resident scene is stored as, so that a view's
+    culled Gaussians come in long runs of memory."""
+    order = spatial_order(means)
+    return tuple(gather_planes(t, order) for t in (means, scales, quats, opacities, sh)) + (order,)
+
+
 class _L1Loss(torch.autograd.Function):
     """mean |image - target| in the library's kernels: one deterministic
     two-stage sum forward, one streaming pass for the gradient."""

@@ -257,10 +257,14 @@ def check_blocks_elementwise(g_gpu: dict, g_ora: dict, rel=1e-4, floor=1e-3, err
 
 
 def read_grad2d(ws, n, cam):
-    """The blend backward's per-Gaussian accumulators [9][n]: mu_p x y,
+    """The blend backward's per-Gaussian accumulators [n][9]: mu_p x y,
     conic A B C, opacity, rgb."""
     lay = ws.layout(n, cam.width, cam.height)
-    g = ws.view(lay.grad2d, 9 * n, torch.float32).cpu().numpy().reshape(9, n).astype(np.float64)
+    groups = (n + 63) // 64
+    buf = ws.view(lay.grad2d, 9 * 64 * groups, torch.float32).cpu().numpy().reshape(64 * groups, 9)
+    ids = np.arange(n, dtype=np.int64)
+    slot = (ids & ~63) | ((ids * 9) & 63)  # the layout's permutation inside each group of 64
+    g = buf[slot].T.astype(np.float64)
     return dict(mu_p=np.ascontiguousarray(g[0:2].T), conic=np.ascontiguousarray(g[2:5].T),
                 opacity=np.ascontiguousarray(g[5]), rgb=np.ascontiguousarray(g[6:9].T))
 

@@ -258,6 +258,21 @@ int fgs_l1_loss_backward(const float* image, const float* target, int64_t count,
                          float* dL_dimage, void* stream);
 
 /*
+ * fgs_l1_loss without the partials argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation): the FGS_L1_PARTIALS
+ * partial sums live in an array the library holds on every GPU it runs on
+ * (8 KiB each, kept until the process ends), found on the first call on each
+ * device.  It allocates nothing and calls no allocating routine; every
+ * partial is written before it is read, so nothing needs clearing.  Same
+ * kernels, same result bit for bit, same errors as fgs_l1_loss; count is at
+ * most 2^31 - 1 (FGS_ERR_OVERFLOW beyond).  Calls that overlap on one GPU
+ * (two streams, or two host threads) share that array and race: serialise
+ * them.
+ */
+int fgs_l1_loss_noalloc(const float* image, const float* target, int64_t count, float* loss, void* stream);
+
+/*
  * Spatial order of a scene, for storing a resident scene once (not part of
  * the per-view path).  The paper's rasterizer reads each Gaussian's
  * parameters, SH coefficients included, from structure-of-arrays planes; a

@@ -96,6 +96,8 @@ SIGNATURES = {
                      ctypes.c_void_p], ctypes.c_int),
     "fgs_l1_loss_backward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_void_p], ctypes.c_int),
+    "fgs_l1_loss_noalloc": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+                            ctypes.c_int),
     "fgs_spatial_order_workspace_bytes": ([ctypes.c_int64, ctypes.POINTER(c_size)], ctypes.c_int),
     "fgs_spatial_order": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, c_size,
                            ctypes.c_void_p], ctypes.c_int),
@@ -198,6 +200,11 @@ def fgs_render_forward_batch(g: fgs_gaussians, poses, cams, bgs, workspace: int,
 
 def fgs_l1_loss(image: int, target: int, count: int, partials: int, loss: int, stream: int) -> None:
     check(lib().fgs_l1_loss(image, target, count, partials, loss, stream))
+
+
+def fgs_l1_loss_noalloc(image: int, target: int, count: int, loss: int, stream: int) -> int:
+    """Returns the library's status code (the caller checks it)."""
+    return lib().fgs_l1_loss_noalloc(image, target, count, loss, stream)
 
 
 def fgs_l1_loss_backward(image: int, target: int, count: int, dL_dloss: int, dL_dimage: int, stream: int) -> None:

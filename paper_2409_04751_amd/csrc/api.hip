@@ -490,6 +490,20 @@ extern "C" int fgs_l1_loss_backward(const float* image, const float* target, int
   return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_l1_loss_backward");
 }
 
+extern "C" int fgs_l1_loss_noalloc(const float* image, const float* target, int64_t count, float* loss,
+                                   void* stream) {
+  if (!image || !target || !loss || count <= 0) return fail(FGS_ERR_ARG, "fgs_l1_loss_noalloc: bad argument");
+  if (count > 0x7FFFFFFFll)
+    return fail(FGS_ERR_OVERFLOW, "fgs_l1_loss_noalloc: more than 2^31 - 1 values (the largest count it takes)");
+  if (!aligned16(image) || !aligned16(target))
+    return fail(FGS_ERR_ARG, "fgs_l1_loss_noalloc: images must be 16-byte aligned");
+  double* partials = nullptr;
+  hipError_t e = l1_static_partials(&partials);
+  if (e != hipSuccess) return hip_fail(e, "fgs_l1_loss_noalloc: device address of the partials array");
+  e = launch_l1_loss(image, target, count, partials, loss, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FGS_OK : hip_fail(e, "fgs_l1_loss_noalloc");
+}
+
 extern "C" int fgs_spatial_order_workspace_bytes(int64_t n, size_t* bytes) {
   if (!bytes || n < 0) return fail(FGS_ERR_ARG, "fgs_spatial_order_workspace_bytes: bad argument");
   if (n > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "fgs_spatial_order_workspace_bytes: more than 2^31-1 Gaussians");

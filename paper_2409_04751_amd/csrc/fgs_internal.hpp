@@ -265,6 +265,8 @@ hipError_t launch_spatial_order(const float* means, int64_t n, uint32_t* order, 
 hipError_t launch_gather_planes(const float* in, float* out, int64_t planes, int64_t n, const uint32_t* order,
                                 hipStream_t s);
 
-
+// Device address, on the current device, of the library's own array of
+// FGS_L1_PARTIALS doubles (looked up once per device and kept).
+hipError_t l1_static_partials(double** out);
 
 }  // namespace fgs

@@ -8,6 +8,7 @@
 // The gradient is one streaming pass: both images in with 128-bit loads, the
 // gradient out.
 #include <algorithm>
+#include <mutex>
 
 #include "fgs_internal.hpp"
 
@@ -81,7 +82,33 @@ __global__ __launch_bounds__(kBlock) void l1_grad_kernel(const float* img, const
   }
 }
 
+// Partial sums of fgs_l1_loss_noalloc: a file-scope device array, one copy per
+// GPU for the life of the process (the entry point allocates nothing).  Host
+// code never passes this name to a kernel: on the host it only stands for the
+// symbol, whose device address hipGetSymbolAddress returns per device.
+__device__ __align__(256) double scratch[kL1Blocks];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t l1_static_partials(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_l1_loss(const float* image, const float* target, int64_t count, double* partials, float* loss,
                           hipStream_t s) {

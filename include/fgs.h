@@ -228,11 +228,41 @@ int fgs_render_forward_batch(const fgs_gaussians* g, int32_t nviews, const fgs_p
  * preprocess backward then applies the chain of Sec. 4.2-4.3 (J_phi and
  * dJ/dmu_c) and the covariance / SH derivatives.  Overwrites the
  * workspace's grad2d scratch.  Gradients are deterministic up to the order of
- * float atomic additions.
+ * float atomic additions (fgs_render_backward_deterministic fixes that order).
  */
 int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
                         void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
                         void* stream);
+
+/*
+ * Bytes of scratch fgs_render_backward_deterministic needs for n Gaussians
+ * and up to k_capacity intersections (the K the view's forward reported):
+ * 36 bytes per intersection for the per-entry sums, 16 for sorting them by
+ * Gaussian, plus 8 per Gaussian and the sort's histograms.
+ */
+int fgs_deterministic_workspace_bytes(int64_t n, int64_t k_capacity, size_t* bytes);
+
+/*
+ * fgs_render_backward with a run-to-run deterministic result.  The blend
+ * backward stores each list entry's nine 2D-gradient sums (the reverse pass
+ * of Eq. 3 as in Sec. 4.2) instead of adding them to per-Gaussian
+ * accumulators with float atomics; the entries are then stably sorted by
+ * Gaussian id inside det_workspace and each Gaussian's sums added in an
+ * order fixed by their number (one wave per Gaussian: strided partial sums
+ * in list order, then a fixed butterfly).  The same inputs give
+ * bit-identical gradients on every call; they differ from
+ * fgs_render_backward's only by the order of the float additions.
+ * det_workspace: device, caller-owned, at least
+ *   fgs_deterministic_workspace_bytes(n, K) bytes for the forward's K (its
+ *   contents on entry do not matter; it holds nothing afterwards).
+ * Reads K back from the workspace once (one wait for `stream`); returns
+ * FGS_ERR_WORKSPACE, with the bytes needed in fgs_last_error(), if
+ * det_workspace is smaller.  Every other argument as fgs_render_backward.
+ */
+int fgs_render_backward_deterministic(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam,
+                                      const float bg[3], void* workspace, size_t workspace_bytes,
+                                      const float* dL_drgb, const fgs_grads* grads, void* det_workspace,
+                                      size_t det_workspace_bytes, void* stream);
 
 /*
  * L1 photometric loss of a rendered image against a target, the L1 term of

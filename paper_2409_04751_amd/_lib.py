@@ -86,6 +86,11 @@ SIGNATURES = {
     "fgs_render_backward": ([ctypes.POINTER(fgs_gaussians), ctypes.POINTER(fgs_pose), ctypes.POINTER(fgs_camera),
                              ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, c_size, ctypes.c_void_p,
                              ctypes.POINTER(fgs_grads), ctypes.c_void_p], ctypes.c_int),
+    "fgs_deterministic_workspace_bytes": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(c_size)], ctypes.c_int),
+    "fgs_render_backward_deterministic": ([ctypes.POINTER(fgs_gaussians), ctypes.POINTER(fgs_pose),
+                                           ctypes.POINTER(fgs_camera), ctypes.POINTER(ctypes.c_float),
+                                           ctypes.c_void_p, c_size, ctypes.c_void_p, ctypes.POINTER(fgs_grads),
+                                           ctypes.c_void_p, c_size, ctypes.c_void_p], ctypes.c_int),
     "fgs_batch_workspace_bytes": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(fgs_camera), ctypes.c_int64,
                                    ctypes.POINTER(c_size)], ctypes.c_int),
     "fgs_render_forward_batch": ([ctypes.POINTER(fgs_gaussians), ctypes.c_int32, ctypes.POINTER(fgs_pose),
@@ -174,6 +179,20 @@ def fgs_render_backward(g: fgs_gaussians, pose: fgs_pose, cam: fgs_camera, bg, w
                         dL_drgb: int, grads: fgs_grads, stream: int) -> int:
     return lib().fgs_render_backward(ctypes.byref(g), ctypes.byref(pose), ctypes.byref(cam), _bg(bg), workspace,
                                      workspace_bytes, dL_drgb, ctypes.byref(grads), stream)
+
+
+def fgs_deterministic_workspace_bytes(n: int, k_capacity: int) -> int:
+    out = c_size(0)
+    check(lib().fgs_deterministic_workspace_bytes(n, k_capacity, ctypes.byref(out)))
+    return int(out.value)
+
+
+def fgs_render_backward_deterministic(g: fgs_gaussians, pose: fgs_pose, cam: fgs_camera, bg, workspace: int,
+                                      workspace_bytes: int, dL_drgb: int, grads: fgs_grads, det_workspace: int,
+                                      det_workspace_bytes: int, stream: int) -> int:
+    return lib().fgs_render_backward_deterministic(ctypes.byref(g), ctypes.byref(pose), ctypes.byref(cam), _bg(bg),
+                                                   workspace, workspace_bytes, dL_drgb, ctypes.byref(grads),
+                                                   det_workspace, det_workspace_bytes, stream)
 
 
 def fgs_batch_workspace_bytes(n: int, cams, k_capacity: int) -> int:

@@ -434,15 +434,22 @@ int fgs_render_forward_batch(const fgs_gaussians* g, int32_t nviews, const fgs_p
                       reinterpret_cast<hipStream_t>(stream));
 }
 
-int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
-                        void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
-                        void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Backward of one view; with det_ws the 2D gradients go through the
+// deterministic per-entry store and segmented reduction instead of atomics.
+int backward_impl(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                  void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
+                  void* det_ws, size_t det_bytes, bool det, void* stream) {
   int rc = check_gaussians(g);
   if (rc == FGS_OK) rc = check_view(pose, cam, bg);
   if (rc != FGS_OK) return rc;
   if (!workspace || !dL_drgb || !grads) return fail(FGS_ERR_ARG, "null workspace, dL_drgb or grads");
   if (g->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->sh))
     return fail(FGS_ERR_ARG, "null gradient array");
+  if (det && !det_ws) return fail(FGS_ERR_ARG, "null deterministic workspace");
   const Layout L = fit_layout(g->n, 1, &cam->width, &cam->height, workspace_bytes);
   if (L.kcap < 0) return fail(FGS_ERR_WORKSPACE, "workspace smaller than the fixed part of the layout");
   if (g->n == 0) return FGS_OK;
@@ -450,17 +457,65 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
   char* ws = static_cast<char*>(workspace);
   const ViewParams v = make_view(pose, cam, bg, 0u, 0u);
   float* grad2d = reinterpret_cast<float*>(ws + L.grad2d);
-  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, grad_words(g->n), s), "clear grad2d");
-  HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges),
-                                reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final),
+  const uint32_t* ids = reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final);
+  float* part = nullptr;
+  int64_t K = 0;
+  if (det) {
+    // the forward's K, read back once: it sizes the per-entry sums
+    uint32_t host_counters[kNumCounters];
+    HIP_TRY(read_counters(reinterpret_cast<uint32_t*>(ws + L.counters), host_counters, s), "read counts");
+    uint64_t K64;
+    std::memcpy(&K64, &host_counters[kCountK64], sizeof(K64));
+    if (K64 > (uint64_t)L.kcap) return fail(FGS_ERR_WORKSPACE, "workspace holds no forward state of this view");
+    K = (int64_t)K64;
+    if (det_bytes < det_workspace_bytes(g->n, K)) {
+      char msg[160];
+      std::snprintf(msg, sizeof(msg), "deterministic workspace of %zu bytes, %zu needed for %lld intersections",
+                    det_bytes, det_workspace_bytes(g->n, K), (long long)K);
+      return fail(FGS_ERR_WORKSPACE, msg);
+    }
+    part = static_cast<float*>(det_ws);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(part), 0u, 9 * K, s), "clear per-entry sums");
+  } else {
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, grad_words(g->n), s), "clear grad2d");
+  }
+  HIP_TRY(launch_blend_backward(v, reinterpret_cast<const uint2*>(ws + L.ranges), ids,
                                 reinterpret_cast<const float4*>(ws + L.splats),
                                 reinterpret_cast<const float4*>(ws + L.colors), dL_drgb,
                                 reinterpret_cast<const float*>(ws + L.pixel_T),
                                 reinterpret_cast<const uint32_t*>(ws + L.pixel_last),
-                                reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, g->n, s),
+                                reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, part, g->n, s),
           "blend backward");
+  if (det)
+    HIP_TRY(launch_grad_segreduce(ids, K, g->n, bits_for(g->n), static_cast<char*>(det_ws), det_bytes, grad2d, s),
+            "deterministic reduction");
   HIP_TRY(launch_preprocess_backward(*g, v, ws, L, *grads, s), "preprocess backward");
   return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam, const float bg[3],
+                        void* workspace, size_t workspace_bytes, const float* dL_drgb, const fgs_grads* grads,
+                        void* stream) {
+  return backward_impl(g, pose, cam, bg, workspace, workspace_bytes, dL_drgb, grads, nullptr, 0, false, stream);
+}
+
+int fgs_deterministic_workspace_bytes(int64_t n, int64_t k_capacity, size_t* bytes) {
+  if (!bytes || n < 0 || k_capacity < 0) return fail(FGS_ERR_ARG, "fgs_deterministic_workspace_bytes: bad argument");
+  if (n > 0x7FFFFFFF || k_capacity > 0x7FFFFFFF) return fail(FGS_ERR_OVERFLOW, "size beyond 2^31-1");
+  *bytes = det_workspace_bytes(n, k_capacity);
+  return FGS_OK;
+}
+
+int fgs_render_backward_deterministic(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera* cam,
+                                      const float bg[3], void* workspace, size_t workspace_bytes,
+                                      const float* dL_drgb, const fgs_grads* grads, void* det_workspace,
+                                      size_t det_workspace_bytes, void* stream) {
+  return backward_impl(g, pose, cam, bg, workspace, workspace_bytes, dL_drgb, grads, det_workspace,
+                       det_workspace_bytes, true, stream);
 }
 
 }  // extern "C"

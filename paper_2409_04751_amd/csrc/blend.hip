@@ -322,6 +322,7 @@ struct BlendBwdArgs {
   const uint32_t* pixel_last;
   const uint32_t* counters;
   float* grad2d;  // [grad_slot(g)][9]
+  float* part;    // null, or [entry][9]: the sums stored per list entry instead
   uint32_t n;
 };
 
@@ -558,16 +559,12 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
     }
     wave_lds_sync();
     const int cnt = end - beg;
-    float4 na = S.sa[cnt - 1], nb = S.sb[cnt - 1];
-    float2 nc = S.sc[cnt - 1];
+    // the records are read where they are used: no registers held for the
+    // next entry, which keeps six waves per SIMD (the other waves hide the
+    // LDS latency)
     for (int idx = cnt - 1; idx >= 0; --idx) {
-      const float4 ga = na, gb = nb;
-      const float2 gc = nc;
-      if (idx > 0) {
-        na = S.sa[idx - 1];
-        nb = S.sb[idx - 1];
-        nc = S.sc[idx - 1];
-      }
+      const float4 ga = S.sa[idx], gb = S.sb[idx];
+      const float2 gc = S.sc[idx];
       const uint32_t e = (uint32_t)(beg + idx);
       // the exponent as the forward forms it (bit for bit); dx is shared by
       // the lane's four pixels, which lie in one column
@@ -606,14 +603,17 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       const float part = wave_rows_sum(row_reduce_scatter9(v, rb3, rb2, rb1, rb0));
       if (writer) {
         const float val = part * wscale;
-        if (val != 0.0f) atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
+        if (a.part)  // e counts from the tile's first entry
+          a.part[((size_t)r.x + e) * 9 + rval] = val;
+        else if (val != 0.0f)
+          atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
       }
     }
     wave_lds_sync();
   }
 }
 
-__global__ __launch_bounds__(kBwdThreads) void blend_backward_kernel(BlendBwdArgs a) {
+__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(6))) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ BwdStage stage[kBwdWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   BwdStage& S = stage[wave];
@@ -647,7 +647,7 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
                                  const float4* colors,
                                  const float* dL_dimg, const float* pixel_T, const uint32_t* pixel_last,
-                                 const uint32_t* counters, float* grad2d, int64_t n, hipStream_t s) {
+                                 const uint32_t* counters, float* grad2d, float* part, int64_t n, hipStream_t s) {
   BlendBwdArgs a;
   a.ranges = ranges;
   a.ids = ids;
@@ -663,6 +663,7 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.pixel_last = pixel_last;
   a.counters = counters;
   a.grad2d = grad2d;
+  a.part = part;
   a.n = (uint32_t)n;
   const int64_t tiles = (int64_t)v.tiles_x * v.tiles_y;
   ProfScope prof(s, kKBlendBackward);

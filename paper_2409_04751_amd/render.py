@@ -57,10 +57,22 @@ class Workspace:
     `generation` counts the forwards rendered into it: a backward checks that
     no other forward has overwritten the state of its own."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, deterministic: bool = False):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buf: torch.Tensor | None = None
         self.generation = 0
+        # backwards on this workspace reduce the 2D gradients in a fixed order
+        # (bit-identical from run to run) instead of with float atomics; they
+        # then need K x 52 bytes more scratch, kept in det_buf
+        self.deterministic = deterministic
+        self.det_buf: torch.Tensor | None = None
+        self.k = 0  # intersections of the last forward rendered into it
+
+    def ensure_det(self, n: int) -> None:
+        nbytes = L.fgs_deterministic_workspace_bytes(n, self.k)
+        if self.det_buf is None or self.det_buf.numel() < nbytes:
+            self.det_buf = None
+            self.det_buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
 
     @property
     def nbytes(self) -> int:
@@ -112,15 +124,19 @@ def render_forward(means, scales, quats, opacities, sh, sh_degree: int, pose, ca
             ws.ensure(L.fgs_workspace_bytes(g.n, cam.width, cam.height, int(math.ceil(K * 1.15)) + 65536))
             continue
         L.check(rc)
+        ws.k = K
         return out, ws, K
     raise L.FgsError(L.FGS_ERR_WORKSPACE, "workspace did not converge")
 
 
 def render_backward(means, scales, quats, opacities, sh, sh_degree: int, pose, cam, bg, workspace: Workspace,
-                    dL_dimg: torch.Tensor, want_means2d: bool = False, accumulate_into: dict | None = None) -> dict:
+                    dL_dimg: torch.Tensor, want_means2d: bool = False, accumulate_into: dict | None = None,
+                    deterministic: bool | None = None) -> dict:
     """Gradients of one view for the workspace of its forward.  With
     accumulate_into (a dict of gradient tensors from an earlier call), the
-    view's gradients are added to those tensors, which are returned."""
+    view's gradients are added to those tensors, which are returned.
+    deterministic (default: the workspace's setting) reduces the per-tile
+    sums in a fixed order, so repeated calls give identical bits."""
     g = gaussians_struct(means, scales, quats, opacities, sh, sh_degree)
     if not dL_dimg.is_contiguous() or dL_dimg.dtype != torch.float32 or tuple(dL_dimg.shape) != (3, cam.height, cam.width):
         raise ValueError("dL_dimg must be contiguous float32 [3, H, W]")
@@ -140,8 +156,16 @@ def render_backward(means, scales, quats, opacities, sh, sh_degree: int, pose, c
     gr = L.fgs_grads(out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(),
                      out["opacities"].data_ptr(), out["sh"].data_ptr(),
                      out["means2d"].data_ptr() if want_means2d else None, 1 if accumulate_into is not None else 0)
-    rc = L.fgs_render_backward(g, pose_struct(pose), camera_struct(cam), bg, workspace.ptr,
-                               workspace.nbytes, dL_dimg.data_ptr(), gr, _stream_handle(means.device))
+    det = workspace.deterministic if deterministic is None else deterministic
+    if det:
+        workspace.ensure_det(g.n)
+        rc = L.fgs_render_backward_deterministic(g, pose_struct(pose), camera_struct(cam), bg, workspace.ptr,
+                                                 workspace.nbytes, dL_dimg.data_ptr(), gr,
+                                                 int(workspace.det_buf.data_ptr()), int(workspace.det_buf.numel()),
+                                                 _stream_handle(means.device))
+    else:
+        rc = L.fgs_render_backward(g, pose_struct(pose), camera_struct(cam), bg, workspace.ptr,
+                                   workspace.nbytes, dL_dimg.data_ptr(), gr, _stream_handle(means.device))
     L.check(rc)
     return out
 

@@ -1,10 +1,13 @@
 """Summaries of rocprofv3 CSV output (kernel stats and PMC counters).
 
     python -m paper_2409_04751_amd.rocprof_summary stats KERNEL_STATS.csv
+    python -m paper_2409_04751_amd.rocprof_summary stats KERNEL_TRACE.csv --after preprocess_fused_kernel
     python -m paper_2409_04751_amd.rocprof_summary traffic \
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
         --copy-bytes 1073741824 --out profiles/traffic_<workload>.json
     python -m paper_2409_04751_amd.rocprof_summary counters C.csv --counters SQ_WAVES ...
+    python -m paper_2409_04751_amd.rocprof_summary table --trace KERNEL_TRACE.csv --pmc A.csv B.csv \
+        [--after preprocess_fused_kernel]
     python -m paper_2409_04751_amd.rocprof_summary marks KERNEL_TRACE.csv --match preprocess_kernel
     python -m paper_2409_04751_amd.rocprof_summary window KERNEL_TRACE.csv --begin I --end J --count preprocess_kernel
 
@@ -13,6 +16,25 @@ name contains a string; `window` sums the launches [I, J) of a kernel trace
 per kernel, with the span from the first start to the last end and the
 share of it the GPU was busy, per occurrence of the `--count` kernel (per
 batch, per view).
+
+`table` prints, per library kernel, the average duration in a rocprofv3
+kernel trace and the
+mean per dispatch of the SQ / TCC / GRBM counters found in the counter CSVs,
+with derived figures (cycles = duration x 2.4 GHz, the peak engine clock,
+so busy and occupancy figures are lower bounds when the clock runs lower;
+GRBM_GUI_ACTIVE / 8, the cycles of the counter window per XCD, runs
+longer than the kernel for short dispatches and is not used):
+  VALU busy   SQ_INSTS_VALU / (256 CUs x cycles): a CU issues at most one
+              wave64 VALU instruction per cycle (four SIMD16 units, four
+              cycles per wave64 instruction);
+  waves/SIMD  SQ_WAVE_CYCLES x 4 / (1024 SIMDs x cycles): resident waves per
+              SIMD averaged over the dispatch (SQ_WAVE_CYCLES counts
+              wave-cycles in units of four cycles);
+  wait        SQ_WAIT_ANY / SQ_WAVE_CYCLES: share of wave time spent waiting;
+  fp32 TFLOP/s  64 x (SQ_INSTS_VALU_FLOPS_FP32 + SQ_INSTS_VALU_FLOPS_FP32_TRANS)
+              / duration: the counters count the flops of each wave64
+              instruction once, not per lane;
+  atomics/s   TCC_ATOMIC / the rocprofv3 average duration.
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two
 separate `rocprofv3 --pmc` runs) into HBM bytes per launch of each library
@@ -44,13 +66,53 @@ def kernel_stats(path: str) -> list[dict]:
     return rows
 
 
-def counter_means(path: str, kernel_substr: str, counter: str) -> tuple[float, int]:
+def trace_stats(path: str, after: str | None = None) -> list[dict]:
+    """kernel_stats rows computed from a `*_kernel_trace.csv`, counting only
+    the launches from the first launch of `after` on."""
+    start = first_dispatch(path, after)
+    agg: dict[str, list] = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if int(r["Dispatch_Id"]) < start:
+                continue
+            a = agg.setdefault(r["Kernel_Name"], [0, 0])
+            a[0] += 1
+            a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    total = sum(a[1] for a in agg.values()) or 1
+    rows = [dict(name=k, calls=a[0], total_ns=float(a[1]), avg_ns=a[1] / a[0], pct=100.0 * a[1] / total)
+            for k, a in agg.items()]
+    rows.sort(key=lambda r: -r["total_ns"])
+    return rows
+
+
+def first_dispatch(path: str, kernel_substr: str | None) -> int:
+    """Dispatch id of the first launch of a kernel whose name contains
+    `kernel_substr` (0 if None): launches before it, such as a scene's
+    one-off set-up, are left out of the per-dispatch means."""
+    if not kernel_substr:
+        return 0
+    first = None
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if kernel_substr in r["Kernel_Name"]:
+                d = int(r["Dispatch_Id"])
+                first = d if first is None else min(first, d)
+    if first is None:
+        raise SystemExit(f"no kernel matching {kernel_substr!r} in {path}")
+    return first
+
+
+def counter_means(path: str, kernel_substr: str, counter: str, after: str | None = None) -> tuple[float, int]:
     """Mean value of `counter` per dispatch over kernels whose name contains
-    `kernel_substr`; returns (mean, dispatches)."""
+    `kernel_substr` (from the first launch of `after` on); returns (mean,
+    dispatches)."""
+    start = first_dispatch(path, after)
     per_dispatch: dict[str, float] = {}
     with open(path, newline="") as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] != counter or kernel_substr not in r["Kernel_Name"]:
+                continue
+            if int(r["Dispatch_Id"]) < start:
                 continue
             d = r["Dispatch_Id"]
             per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
@@ -90,8 +152,8 @@ def traffic(args) -> dict:
     kernels = {}
     for name, sub in KERNELS.items():
         try:
-            fk, nf = counter_means(args.fetch, sub, "FETCH_SIZE")
-            wk, nw = counter_means(args.write, sub, "WRITE_SIZE")
+            fk, nf = counter_means(args.fetch, sub, "FETCH_SIZE", args.after)
+            wk, nw = counter_means(args.write, sub, "WRITE_SIZE", args.after)
         except SystemExit:
             continue
         read_b = fk * 1024.0 * fetch_factor
@@ -147,12 +209,90 @@ def counter_table(path: str, counters: list[str]) -> dict:
     return out
 
 
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
+
+
+def trace_avg_ms(path: str, sub: str, after: str | None = None) -> float | None:
+    """Average duration (ms) of the launches in a rocprofv3 kernel trace whose
+    name contains `sub`, from the first launch of `after` on."""
+    start = first_dispatch(path, after)
+    calls = 0
+    total = 0
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if sub in r["Kernel_Name"] and int(r["Dispatch_Id"]) >= start:
+                calls += 1
+                total += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    return total / calls / 1e6 if calls else None
+
+
+def counter_rows(trace_csv: str, pmc_csvs: list[str], after: str | None = None) -> dict:
+    """Per library kernel: duration, raw counter means and derived figures."""
+    names = set()
+    for path in pmc_csvs:
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                names.add(r["Counter_Name"])
+    out = {}
+    for kname, sub in KERNELS.items():
+        ms = trace_avg_ms(trace_csv, sub, after)
+        if ms is None:
+            continue
+        raw = {}
+        for path in pmc_csvs:
+            for c in sorted(names):
+                if c in raw:
+                    continue
+                try:
+                    raw[c], _ = counter_means(path, sub, c, after)
+                except SystemExit:
+                    pass
+        if not raw:
+            continue
+        row = dict(ms=ms, raw=raw)
+        cyc = ms * 1e-3 * CLOCK_HZ
+        if "SQ_INSTS_VALU" in raw:
+            row["valu_busy"] = raw["SQ_INSTS_VALU"] / (256.0 * cyc)
+        if "SQ_WAVE_CYCLES" in raw:
+            row["waves_per_simd"] = raw["SQ_WAVE_CYCLES"] * 4.0 / (1024.0 * cyc)
+        if raw.get("SQ_WAVE_CYCLES", 0.0) > 0 and "SQ_WAIT_ANY" in raw:
+            row["wait"] = raw["SQ_WAIT_ANY"] / raw["SQ_WAVE_CYCLES"]
+        if "TCC_ATOMIC" in raw:
+            row["atomics_per_s"] = raw["TCC_ATOMIC"] / (ms * 1e-3)
+        if "SQ_INSTS_VALU_FLOPS_FP32" in raw:
+            fl = 64.0 * (raw["SQ_INSTS_VALU_FLOPS_FP32"] + raw.get("SQ_INSTS_VALU_FLOPS_FP32_TRANS", 0.0))
+            row["fp32_gflop"] = fl / 1e9
+            row["fp32_tflops"] = fl / (ms * 1e-3) / 1e12
+        out[kname] = row
+    return out
+
+
+def print_table(rows: dict) -> None:
+    cols = [("ms", "ms", "{:.4f}"), ("valu_busy", "VALU busy", "{:.2f}"),
+            ("waves_per_simd", "waves/SIMD", "{:.2f}"), ("wait", "wait", "{:.2f}"),
+            ("fp32_gflop", "fp32 GFLOP", "{:.3f}"), ("fp32_tflops", "fp32 TFLOP/s", "{:.1f}"),
+            ("atomics_per_s", "atomics/s", "{:.3e}")]
+    print(f"{'kernel':<20}" + "".join(f"{h:>13}" for _, h, _ in cols))
+    for k, r in rows.items():
+        print(f"{k:<20}" + "".join(f"{fmt.format(r[c]) if c in r else '-':>13}" for c, _, fmt in cols))
+    counters = sorted({c for r in rows.values() for c in r["raw"]})
+    print()
+    print("raw counter means per dispatch")
+    for i in range(0, len(counters), 6):
+        part = counters[i:i + 6]
+        print(f"{'kernel':<20}" + "".join(f"{c[-22:]:>24}" for c in part))
+        for k, r in rows.items():
+            print(f"{k:<20}" + "".join(f"{r['raw'][c]:>24.4e}" if c in r["raw"] else f"{'-':>24}" for c in part))
+        print()
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
-    s.add_argument("csv")
+    s.add_argument("csv", help="*_kernel_stats.csv, or a *_kernel_trace.csv (then --after applies)")
     s.add_argument("--top", type=int, default=30)
+    s.add_argument("--after", default=None, help="leave out launches before the first of this kernel")
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
@@ -161,9 +301,14 @@ def main(argv=None) -> int:
     t.add_argument("--source-sha", default=None)
     t.add_argument("--command", default=None)
     t.add_argument("--out", default=None)
+    t.add_argument("--after", default=None, help="leave out dispatches before the first of this kernel")
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--counters", nargs="+", required=True)
+    tb = sub.add_parser("table")
+    tb.add_argument("--trace", required=True, help="rocprofv3 *_kernel_trace.csv for the durations")
+    tb.add_argument("--pmc", nargs="+", required=True)
+    tb.add_argument("--after", default=None, help="leave out dispatches before the first of this kernel")
     m = sub.add_parser("marks")
     m.add_argument("csv")
     m.add_argument("--match", required=True)
@@ -188,13 +333,16 @@ def main(argv=None) -> int:
             print(f"{name[:46]:<46} {calls:>6} {ms:>10.3f} {ms / u:>12.3f}")
         return 0
     if args.cmd == "stats":
-        rows = kernel_stats(args.csv)
+        rows = trace_stats(args.csv, args.after) if args.csv.endswith("kernel_trace.csv") else kernel_stats(args.csv)
         total = sum(r["total_ns"] for r in rows)
         print(f"{'kernel':<70} {'calls':>6} {'total_ms':>10} {'avg_us':>10} {'pct':>6}")
         for r in rows[:args.top]:
             print(f"{r['name'][:70]:<70} {r['calls']:>6} {r['total_ns'] / 1e6:>10.3f} {r['avg_ns'] / 1e3:>10.2f} "
                   f"{r['pct']:>6.2f}")
         print(f"{'total':<70} {'':>6} {total / 1e6:>10.3f}")
+        return 0
+    if args.cmd == "table":
+        print_table(counter_rows(args.trace, args.pmc, args.after))
         return 0
     if args.cmd == "counters":
         print(json.dumps(counter_table(args.csv, args.counters), indent=1))

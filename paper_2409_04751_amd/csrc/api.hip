@@ -93,6 +93,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.colorjac = take(nn * 3 * sizeof(float4));
   L.row_off = take((size_t)kk * 4);
   L.rowrange = take(nv * 4);
+  L.block_first = take((size_t)(kk / std::min(kRowsPerBlock, kDupItems) + 2) * 4);
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
@@ -340,14 +341,17 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   // second buffers, which the sort first writes after the duplication.
   uint32_t* row_g = U(L.tvals_b);
   uint32_t* row_yc = U(L.tkeys_b);
-  HIP_TRY(launch_scan(d_rx, d_ry, nullptr, V, kScanRows, partials, nullptr, U(L.offsets), s), "row scan");
-  HIP_TRY(launch_rows(d_ids, d_rx, d_ry, U(L.offsets), V, R, reinterpret_cast<const float4*>(ws + L.splats), tight,
-                      U(L.row_off), row_g, row_yc, s),
+  HIP_TRY(launch_scan(d_rx, d_ry, nullptr, V, kScanRows, partials, nullptr, U(L.offsets), s, U(L.block_first),
+                      kRowsPerBlock),
+          "row scan");
+  HIP_TRY(launch_rows(d_ids, d_rx, d_ry, U(L.offsets), U(L.block_first), V, R,
+                      reinterpret_cast<const float4*>(ws + L.splats), tight, U(L.row_off), row_g, row_yc, s),
           "rows");
-  HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s),
+  HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s,
+                      U(L.block_first), kDupItems),
           "row count scan");
-  HIP_TRY(launch_duplicate(U(L.row_off), row_g, row_yc, R, K, b, n, L.tile_bits, hist, U(L.tkeys_a), U(L.tvals_a),
-                           s),
+  HIP_TRY(launch_duplicate(U(L.row_off), row_g, row_yc, U(L.block_first), R, K, b, n, L.tile_bits, hist,
+                           U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
   HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, true),

@@ -457,6 +457,9 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// STORE: the nine sums of each entry are stored at part[entry] (the
+// deterministic mode) instead of added to the Gaussian's accumulators
+template <bool STORE>
 __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_t tile, uint32_t lane) {
   const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
@@ -603,7 +606,7 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       const float part = wave_rows_sum(row_reduce_scatter9(v, rb3, rb2, rb1, rb0));
       if (writer) {
         const float val = part * wscale;
-        if (a.part)  // e counts from the tile's first entry
+        if constexpr (STORE)  // e counts from the tile's first entry
           a.part[((size_t)r.x + e) * 9 + rval] = val;
         else if (val != 0.0f)
           atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
@@ -613,12 +616,13 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
   }
 }
 
+template <bool STORE>
 __global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(6))) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ BwdStage stage[kBwdWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   BwdStage& S = stage[wave];
   const uint32_t tile = xcd_chunk(blockIdx.x, gridDim.x) * kBwdWaves + wave;
-  if (tile < (uint32_t)a.tiles_x * (uint32_t)a.tiles_y) backward_tile(a, S, tile, lane);
+  if (tile < (uint32_t)a.tiles_x * (uint32_t)a.tiles_y) backward_tile<STORE>(a, S, tile, lane);
 }
 
 }  // namespace
@@ -667,7 +671,12 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.n = (uint32_t)n;
   const int64_t tiles = (int64_t)v.tiles_x * v.tiles_y;
   ProfScope prof(s, kKBlendBackward);
-  hipLaunchKernelGGL(blend_backward_kernel, dim3((unsigned)ceil_div(tiles, kBwdWaves)), dim3(kBwdThreads), 0, s, a);
+  if (part)
+    hipLaunchKernelGGL(blend_backward_kernel<true>, dim3((unsigned)ceil_div(tiles, kBwdWaves)), dim3(kBwdThreads), 0,
+                       s, a);
+  else
+    hipLaunchKernelGGL(blend_backward_kernel<false>, dim3((unsigned)ceil_div(tiles, kBwdWaves)), dim3(kBwdThreads), 0,
+                       s, a);
   return hipGetLastError();
 }
 

@@ -50,6 +50,11 @@ enum ScanMode {
   kScanRows = 4,      // row count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
 };
 
+// Output slots (pairs) per duplication block, rows per rows-kernel block.
+constexpr int kDupItems = kBlock * kIptPayload1;
+constexpr int kRowsPerThread = 4;
+constexpr int kRowsPerBlock = kBlock * kRowsPerThread;
+
 // Key / payload planes of a radix sort: input in *_a, scratch in *_b.
 struct RadixBuffers {
   int payload;  // 1 or 3
@@ -133,6 +138,8 @@ struct Layout {
   size_t offsets, grad2d, ranges, pixel_T, pixel_last, counters;
   size_t row_off;  // [kcap]: per binned row its kept-tile count, then their exclusive scan
   size_t rowrange;  // tight binning, [entry]: first | (last + 1) << 16 of the rows with a kept tile
+  size_t block_first;  // [kcap / kRowsPerBlock + 2]: per rows-kernel block its first entry, then per
+                       // duplication block its first row
   // the rows' Gaussian and (y << 16 | first column) live in tvals_b / tkeys_b
   // until the tile sort needs them
   size_t hist, partials, block_tiles;
@@ -181,8 +188,14 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
 // Exclusive scan of u32 values read as `mode` says; the item count is
 // *d_count if d_count is non-null (device), capped by max_count (host).
 // Writes the total to *total (device) if non-null.  out may alias in_a.
+// With aux (device, [total / aux_block + 1]) the scan also records, for every
+// multiple m * aux_block below the total, the item i whose range
+// [out[i], out[i] + value[i]) holds it: aux[m] = i.  A kernel that takes
+// aux_block consecutive units of the scanned ranges per block finds its first
+// item there instead of searching the offsets.
 hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_t* d_count, int64_t max_count,
-                       int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s);
+                       int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s,
+                       uint32_t* aux = nullptr, uint32_t aux_block = 0);
 
 // Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
 // bits [0, bits), same item-count convention as launch_scan.  The result is
@@ -216,9 +229,10 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
 // [c0, c1) -- with tight binning from reach_row on the splat record, else the
 // whole rect row -- as row_cnt[t] = c1 - c0, row_g[t] = Gaussian (entry) id,
 // row_yc[t] = y << 16 | c0.
-hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base, int64_t V,
-                       int64_t R, const float4* splats, bool tight, uint32_t* row_cnt, uint32_t* row_g,
-                       uint32_t* row_yc, hipStream_t s);
+// first_entry[b]: the entry that holds row b * kRowsPerBlock (the row scan's aux)
+hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base,
+                       const uint32_t* first_entry, int64_t V, int64_t R, const float4* splats, bool tight,
+                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, hipStream_t s);
 
 // One (tile, id) pair per kept tile of each row, at the row's offset
 // row_off[t] (exclusive scan of the counts); K pairs in total, in depth
@@ -226,9 +240,10 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
 // (tile_bits key bits) into hist.  Ids are view-major (view * n +
 // Gaussian); the pair's key is the view's tile_base plus the tile index
 // inside the view.
-hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc, int64_t R,
-                            int64_t K, const ViewBatch& b, int64_t n, int tile_bits, uint32_t* hist, uint32_t* out_keys,
-                            uint32_t* out_vals, hipStream_t s);
+// first_row[b]: the row that holds pair b * kDupItems (the row-count scan's aux)
+hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
+                            const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
+                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);
 

@@ -67,6 +67,8 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* smem /* kW
 struct ScanIn {
   const uint32_t* a;  // values, flags, or rect x0|y0 plane
   const uint32_t* b;  // rect x1|y1 plane (kScanRectArea), or the gathered values (kScanGather)
+  uint32_t* aux;      // null, or the item holding each multiple of aux_block (launch_scan)
+  uint32_t aux_block;
 };
 
 template <int MODE>
@@ -198,6 +200,15 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(ScanIn in, uint32_t*
   for (int k = 0; k < kItemsPerThread; ++k) {
     res[k] = off;
     off += vals[k];
+  }
+  if (in.aux) {
+    // the item whose range [res, res + vals) holds a multiple of aux_block
+    // starts that block of the consuming kernel
+    const uint32_t ab = in.aux_block;
+    for (int k = 0; k < kItemsPerThread; ++k) {
+      if (base + k >= count) break;
+      for (uint32_t b = (res[k] + ab - 1u) / ab; b * ab < res[k] + vals[k]; ++b) in.aux[b] = base + k;
+    }
   }
   if (base + 16u <= count) {
     uint4* o4 = reinterpret_cast<uint4*>(out + base);
@@ -466,7 +477,6 @@ __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4
 // block stages its (tile, id) pairs in LDS and writes them out coalesced.
 // It also counts the first digit of the tile sort for its slots, which is
 // exactly that sort's first histogram.
-constexpr int kDupItems = kBlock * kIptPayload1;  // 4096
 
 
 struct TileMap {
@@ -482,48 +492,30 @@ __device__ inline void view_of(const TileMap& m, uint32_t id, uint32_t& base, ui
   tx = m.tiles_x[v];
 }
 
-// Largest j in [lo, hi) with a[j] <= x, for non-decreasing a with
-// a[lo] <= x; called by a whole wave, which probes 64 evenly spaced
-// positions per round (the probes at or below x form a prefix).
-__device__ inline uint32_t wave_search_le(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
-  const uint32_t lane = lane_id();
-  while (hi - lo > 1) {
-    const uint32_t step = (hi - lo + 63u) / 64u;
-    const uint32_t idx = lo + lane * step;
-    const uint64_t m = __ballot(idx < hi && a[idx] <= x);
-    const uint32_t nle = (uint32_t)__builtin_popcountll(m);  // >= 1 when a[lo] <= x
-    if (nle == 0u) break;  // a[lo] > x: outside the contract; stop at lo rather than leave [lo, hi)
-    const uint32_t nlo = lo + (nle - 1u) * step;
-    hi = min(hi, lo + nle * step);
-    lo = nlo;
-  }
-  return lo;
-}
-
 __device__ inline uint32_t pad_index(uint32_t e) { return e + (e >> 5); }  // one pad word per 32
 
 // Rows to bin (see launch_rows): a block takes kRowsPerBlock consecutive
 // rows, four per thread, strided so that the stores coalesce.  They belong
 // to at most kRowsPerBlock entries (each entry has at least one row), whose
-// row bases the block copies to LDS for short binary searches; the block's
-// two searches of the row bases in memory are shared by its 1024 rows.
-constexpr int kRowsPerThread = 4;
-constexpr int kRowsPerBlock = kBlock * kRowsPerThread;
+// row bases the block copies to LDS for short binary searches; the row scan
+// recorded the block's first entry, so no search runs in memory.
 __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry,
-                                                      const uint32_t* row_base, uint32_t V, uint32_t R,
+                                                      const uint32_t* row_base, const uint32_t* first_entry,
+                                                      uint32_t V, uint32_t R,
                                                       const float4* splats, int tight, uint32_t* row_cnt,
                                                       uint32_t* row_g, uint32_t* row_yc) {
   __shared__ uint32_t s_base[kRowsPerBlock];
   __shared__ uint32_t s_first, s_count;
   const uint32_t t0 = blockIdx.x * kRowsPerBlock;
   const uint32_t t1 = min(t0 + (uint32_t)kRowsPerBlock, R);
-  if (threadIdx.x < 64) {
-    const uint32_t first = wave_search_le(row_base, 0u, V, t0);
-    const uint32_t last = wave_search_le(row_base, first, min(V, first + (uint32_t)kRowsPerBlock), t1 - 1u);
-    if (threadIdx.x == 0) {
-      s_first = first;
-      s_count = last - first + 1u;
-    }
+  if (threadIdx.x == 0) {
+    // the entries of this block's rows: from the entry of its first row to,
+    // at most, the entry of the next block's first row (recorded by the row
+    // scan)
+    const uint32_t first = first_entry[blockIdx.x];
+    const uint32_t last = t1 < R ? first_entry[blockIdx.x + 1] : V - 1u;
+    s_first = first;
+    s_count = min(last - first + 1u, (uint32_t)kRowsPerBlock);
   }
   __syncthreads();
   const uint32_t first = s_first, m = s_count;
@@ -557,7 +549,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
 // staged in LDS (up to kDupItems rows; rows beyond come from memory).  The
 // slots are staged in LDS and written coalesced.
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_off, const uint32_t* row_g,
-                                                           const uint32_t* row_yc, uint32_t R, uint32_t K, TileMap map,
+                                                           const uint32_t* row_yc, const uint32_t* first_row,
+                                                           uint32_t R, uint32_t K, TileMap map,
                                                            int digit_bits, uint32_t nblocks, uint32_t* hist,
                                                            uint32_t* out_keys, uint32_t* out_vals) {
   __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
@@ -569,13 +562,14 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_o
   const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
   const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
-  if (threadIdx.x < 64) {
-    const uint32_t first = wave_search_le(row_off, 0u, R, o_begin);
-    const uint32_t last = wave_search_le(row_off, first, min(R, first + (uint32_t)kDupItems), o_end - 1u);
-    if (threadIdx.x == 0) {
-      s_first = first;
-      s_count = last - first + 1u;
-    }
+  if (threadIdx.x == 0) {
+    // the rows that hold this block's pairs run from the row of its first
+    // pair to, at most, the row of the next block's first pair (the scan of
+    // the row counts recorded both)
+    const uint32_t first = first_row[blockIdx.x];
+    const uint32_t last = o_end < K ? first_row[blockIdx.x + 1] : R - 1u;
+    s_first = first;
+    s_count = min(last - first + 1u, (uint32_t)kDupItems);
   }
   __syncthreads();
   const uint32_t first = s_first, m = s_count;
@@ -755,10 +749,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 }
 
 hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_t* d_count, int64_t max_count,
-                       int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s) {
+                       int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s, uint32_t* aux,
+                       uint32_t aux_block) {
   if (max_count <= 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
+  if (aux && aux_block == 0) return hipErrorInvalidValue;
   const uint32_t nb = (uint32_t)ceil_div(max_count, kItemsPerBlock);
-  const ScanIn in{in_a, in_b};
+  const ScanIn in{in_a, in_b, aux, aux_block};
   ProfScope prof(s, kKScan);
   switch (mode) {
     case kScanFlag:
@@ -834,19 +830,20 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
   return hipGetLastError();
 }
 
-hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base, int64_t V,
-                       int64_t R, const float4* splats, bool tight, uint32_t* row_cnt, uint32_t* row_g,
-                       uint32_t* row_yc, hipStream_t s) {
+hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base,
+                       const uint32_t* first_entry, int64_t V, int64_t R, const float4* splats, bool tight,
+                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, hipStream_t s) {
   if (V <= 0 || R <= 0) return hipSuccess;
   ProfScope prof(s, kKRows);
   hipLaunchKernelGGL(rows_kernel, dim3((unsigned)ceil_div(R, kRowsPerBlock)), dim3(kBlock), 0, s, ids, rx, ry, row_base,
+                     first_entry,
                      (uint32_t)V, (uint32_t)R, splats, tight ? 1 : 0, row_cnt, row_g, row_yc);
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc, int64_t R,
-                            int64_t K, const ViewBatch& b, int64_t n, int tile_bits, uint32_t* hist, uint32_t* out_keys,
-                            uint32_t* out_vals, hipStream_t s) {
+hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
+                            const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
+                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s) {
   if (R <= 0 || K <= 0) return hipSuccess;
   const int passes = radix_passes(tile_bits);
   const int first_bits = passes > 0 ? (tile_bits + passes - 1) / passes : 0;  // as launch_radix_sort
@@ -859,7 +856,8 @@ hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, cons
     map.tile_base[v] = v < b.count ? b.v[v].tile_base : 0u;
     map.tiles_x[v] = v < b.count ? (uint32_t)b.v[v].tiles_x : 1u;
   }
-  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, (uint32_t)R, (uint32_t)K,
+  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row, (uint32_t)R,
+                     (uint32_t)K,
                      map, first_bits, nb, hist, out_keys, out_vals);
   return hipGetLastError();
 }

@@ -52,10 +52,10 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * K
     if name == "ranges":
         return 4.0 * K
-    if name == "sh_backward":  # tile count, mean, dL/drgb, direction gradient in; dL/dSH, dL/dmu out
-        return 28.0 * N + 48.0 * V + (12.0 + 4.0 * S) * N
-    if name == "preprocess_backward":
-        return 4.0 * N + 80.0 * V + 44.0 * N
+    if name == "preprocess_backward":  # colour and geometry parts in one launch: tile count and mean of
+        # every Gaussian, the colour's direction gradient, scale, quaternion, opacity and 2D gradient slot
+        # of the visible ones in; dL/dSH and dL/d(mu, s, q, o) of every Gaussian out
+        return 16.0 * N + 116.0 * V + (4.0 * S + 44.0) * N
     return None
 
 

@@ -79,7 +79,6 @@ enum KernelId {
   kKBlendForward,
   kKBlendBackward,
   kKPreprocessBackward,
-  kKShBackward,
   kKColor,
   kKRows,
   kKLoss,

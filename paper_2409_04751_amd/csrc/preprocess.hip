@@ -467,15 +467,12 @@ struct PreBwdArgs {
   int accumulate;  // add to the gradient buffers instead of writing them
 };
 
-// Colour part of the backward, one thread per Gaussian: dL/dSH and the term
-// of dL/dmu that flows through the view direction of the SH evaluation
-// (written to g_means; the geometry kernel adds its own term).  Streams the
-// 4S bytes of coefficients in and 4S bytes of gradient out at low register
-// count, apart from the fp64 geometry.
+// Colour part of the backward for Gaussian i: dL/dSH and the term of dL/dmu
+// that flows through the view direction of the SH evaluation (written to
+// g_means; the geometry part adds its own term).  It streams the 4S bytes of
+// gradient out without reading the coefficients.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
+__device__ inline void sh_backward_body(const PreBwdArgs& a, uint32_t i) {
   const uint32_t n = a.n;
   constexpr int nb = (DEG + 1) * (DEG + 1);
   // one path for every lane (culled lanes compute and select zeros), so each
@@ -525,13 +522,12 @@ __global__ __launch_bounds__(kBlock) void sh_backward_kernel(PreBwdArgs a) {
     for (int ch = 0; ch < 3; ++ch) a.g_means[ch * n + i] += (float)gm[ch];
 }
 
-// Geometry part of the backward (Sec. 4.3): from dL/d(mu_p, conic, opacity)
-// to dL/d(mu, s, q, o) through the fisheye Jacobian, in fp64.  Runs after
-// sh_backward_kernel and adds to the direction term it left in g_means.
+// Geometry part of the backward (Sec. 4.3) for Gaussian i: from
+// dL/d(mu_p, conic, opacity) to dL/d(mu, s, q, o) through the fisheye
+// Jacobian, in fp64.  Runs after the colour part and adds to the direction
+// term it left in g_means.
 template <int MC>
-__global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
+__device__ inline void geometry_backward_body(const PreBwdArgs& a, uint32_t i) {
   const uint32_t n = a.n;
   Geometry G;
   const bool visible =
@@ -628,6 +624,19 @@ __global__ __launch_bounds__(kBlock) void geometry_backward_kernel(PreBwdArgs a)
   }
 }
 
+// The two parts of the backward in one launch, one thread per Gaussian: the
+// colour part streams the SH gradients out while the fp64 geometry of the
+// same wave waits on its dependent loads, and both read the Gaussian's
+// gradient slot and tile count once.  The geometry part adds to the view-
+// direction term the colour part left in g_means (same thread, program order).
+template <int DEG, int MC>
+__global__ __launch_bounds__(kBlock) void backward_fused_kernel(PreBwdArgs a) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  sh_backward_body<DEG>(a, i);
+  geometry_backward_body<MC>(a, i);
+}
+
 }  // namespace
 
 hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, char* ws, const Layout& L,
@@ -722,20 +731,19 @@ hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& 
   a.g_means2d = out.means2d;
   a.accumulate = out.accumulate ? 1 : 0;
   const unsigned blocks = (unsigned)ceil_div(g.n, kBlock);
-  {
-    ProfScope prof(s, kKShBackward);
-    switch (g.sh_degree) {
-      case 0: hipLaunchKernelGGL(sh_backward_kernel<0>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-      case 1: hipLaunchKernelGGL(sh_backward_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-      case 2: hipLaunchKernelGGL(sh_backward_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-      default: hipLaunchKernelGGL(sh_backward_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, a); break;
-    }
-  }
   ProfScope prof(s, kKPreprocessBackward);
-  if (v.model == kModelEquidistant)
-    hipLaunchKernelGGL(geometry_backward_kernel<kMcEquidistant>, dim3(blocks), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(geometry_backward_kernel<kMcOther>, dim3(blocks), dim3(kBlock), 0, s, a);
+#define FGS_BWD(D)                                                                                            \
+  if (v.model == kModelEquidistant)                                                                           \
+    hipLaunchKernelGGL((backward_fused_kernel<D, kMcEquidistant>), dim3(blocks), dim3(kBlock), 0, s, a);     \
+  else                                                                                                        \
+    hipLaunchKernelGGL((backward_fused_kernel<D, kMcOther>), dim3(blocks), dim3(kBlock), 0, s, a);
+  switch (g.sh_degree) {
+    case 0: FGS_BWD(0) break;
+    case 1: FGS_BWD(1) break;
+    case 2: FGS_BWD(2) break;
+    default: FGS_BWD(3) break;
+  }
+#undef FGS_BWD
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace {
 const char* const kNames[kKNumKernels] = {
     "preprocess", "compact", "depth_sort_hist", "depth_sort_scatter", "scan", "duplicate", "tile_sort_hist",
     "tile_sort_scatter", "ranges", "fill", "blend_forward", "blend_backward", "preprocess_backward",
-    "sh_backward", "color", "rows", "loss", "spatial_order",
+    "color", "rows", "loss", "spatial_order",
     "grad_segreduce"};
 
 struct Record {

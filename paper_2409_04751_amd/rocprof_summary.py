@@ -136,8 +136,7 @@ KERNELS = {
     "ranges": "::ranges_kernel(",
     "blend_forward": "::blend_forward_kernel(",
     "blend_backward": "::blend_backward_kernel(",
-    "sh_backward": "::sh_backward_kernel<",
-    "preprocess_backward": "::geometry_backward_kernel<",
+    "preprocess_backward": "::backward_fused_kernel<",
     "loss": "::l1_",
 }
 

@@ -478,8 +478,10 @@ __device__ inline void sh_backward_body(const PreBwdArgs& a, uint32_t i) {
   // one path for every lane (culled lanes compute and select zeros), so each
   // plane is written by one full-wave store.  The SH coefficients are not
   // read: the forward left, per channel, the colour's gradient in the view
-  // direction and the clamp mask.
+  // direction and the clamp mask.  Adding to earlier views' gradients, a
+  // culled Gaussian has nothing to add and touches nothing.
   const bool vis = a.tiles[i] != 0;
+  if (a.accumulate && !vis) return;
   const float* g2 = a.grad2d + 9 * (size_t)grad_slot(i);
   const float grgb[3] = {g2[6], g2[7], g2[8]};
   float4 J0 = make_float4(0.f, 0.f, 0.f, 0.f), J1 = J0, J2 = J0;

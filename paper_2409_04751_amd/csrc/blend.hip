@@ -61,121 +61,6 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
   return __builtin_fmaf(a.z * t, t, (b.x * dy) * dy);
 }
 
-// Which parts of a tile can hold a pixel at which the splat is not skipped
-// (a wave owns one 16x8 half).  Such a pixel has
-// |A'| t^2 + |D'| dy^2 <= P = -q2min with t = dx + beta dy: an ellipse with
-// half extents ry = sqrt(P / |D'|) in y and rx = sqrt(P (1/|A'| + beta^2/|D'|))
-// in x.  The box is widened by 1% + 1/16 px, so the float evaluation of the
-// per-pixel test cannot pass outside it; a non-finite extent, or P so small
-// that the per-pixel terms could underflow, keeps every pixel, and P < 0
-// (opacity below 1/255) keeps none, as the per-pixel test would.  Lists of
-// the entries per part let each wave skip splats that cannot reach its
-// pixels; the tile lists themselves are unchanged.
-//
-// splat_box gives the half extents (rx, ry) of that box and returns 0 if no
-// pixel can pass, 1 for a box, 2 if every pixel must be kept.
-__device__ inline int splat_box(const float4& a, const float4& b, float& rx, float& ry) {
-  const float P = -b.y;
-  if (!(P > 1e-6f)) return P >= 0.0f ? 2 : 0;
-  // t = dx + beta dy loses ~1e-7 (1 + |beta|) px to rounding: past |beta| =
-  // 1e3 that could approach the margin, so such slivers keep every quadrant
-  if (!(fabsf(a.w) <= 1e3f)) return 2;
-  const float iA = 1.0f / fabsf(a.z), iD = 1.0f / fabsf(b.x);
-  constexpr float kBig = 1e30f;
-  ry = sqrtf(P * iD);
-  rx = sqrtf(P * __builtin_fmaf(a.w * a.w, iD, iA));
-  ry = ry <= kBig ? __builtin_fmaf(ry, 1.01f, 0.0625f) : kBig;
-  rx = rx <= kBig ? __builtin_fmaf(rx, 1.01f, 0.0625f) : kBig;
-  return 1;
-}
-
-// Bit h set if the box meets pixel rows [8h, 8h+7] of the tile.
-__device__ inline uint32_t half_mask(const float4& a, const float4& b) {
-  float rx, ry;
-  const int k = splat_box(a, b, rx, ry);
-  if (k != 1) return k == 2 ? 0x3u : 0u;
-  if (!(a.x + rx >= 0.0f && a.x - rx <= 15.0f)) return 0u;
-  uint32_t m = 0;
-  if (a.y + ry >= 0.0f && a.y - ry <= 7.0f) m |= 1u;
-  if (a.y + ry >= 8.0f && a.y - ry <= 15.0f) m |= 2u;
-  return m;
-}
-
-__device__ inline uint32_t lanes_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Both blends run two waves per tile, and each lane owns two pixels of its
-// wave's 16x8 half: (l & 15, 8w + (l >> 4)) and the pixel 4 rows below.  Every
-// LDS read of a staged splat (and, in the backward, every DPP reduction) then
-// serves two pixels: the per-splat loops are bound by LDS bandwidth and VALU
-// issue together.
-constexpr int kPairThreads = 128;
-constexpr int kPairChunk = kPairThreads;
-
-struct HalfLists {
-  uint8_t idx[2][kPairChunk];  // [half][position]: staged entry, in entry order
-  uint32_t wcount[2][2];       // [staging wave][half]
-};
-
-// Per-half lists of the staged entries, in entry order; called by all threads
-// after thread t staged entry t with half mask m (0 for no entry); returns
-// the length of the calling wave's list (wave-uniform).  Contains the
-// barriers that publish the staged records too.
-__device__ inline int build_half_lists(uint32_t m, HalfLists& Q) {
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint64_t bal0 = __ballot(m & 1u), bal1 = __ballot((m >> 1) & 1u);
-  if (lane == 0) {
-    Q.wcount[wave][0] = (uint32_t)__builtin_popcountll(bal0);
-    Q.wcount[wave][1] = (uint32_t)__builtin_popcountll(bal1);
-  }
-  __syncthreads();
-  if (m & 1u) Q.idx[0][(wave ? Q.wcount[0][0] : 0u) + lanes_below(bal0)] = (uint8_t)threadIdx.x;
-  if (m & 2u) Q.idx[1][(wave ? Q.wcount[0][1] : 0u) + lanes_below(bal1)] = (uint8_t)threadIdx.x;
-  const int n = (int)(Q.wcount[0][wave] + Q.wcount[1][wave]);
-  __syncthreads();
-  return __builtin_amdgcn_readfirstlane(n);
-}
-
-// Walks the calling wave's list (forward or reverse entry order) and calls
-// body(entry, a, b, c) per listed entry until it returns true.  The list is
-// read four indices per LDS word, and the next entry's staged records are
-// fetched before the body of the current one runs, so the body does not wait
-// on a chain of dependent LDS reads.  Index and records are wave-uniform.
-template <bool kReverse, bool kColor, class Body>
-__device__ inline void walk_half_list(const HalfLists& Q, uint32_t wave, int cnt, const float4* sa,
-                                      const float4* sb, const float2* sc, Body&& body) {
-  if (cnt <= 0) return;
-  const uint32_t* words = reinterpret_cast<const uint32_t*>(Q.idx[wave]);
-  int j = kReverse ? cnt - 1 : 0;
-  uint32_t word = __builtin_amdgcn_readfirstlane(words[j >> 2]);
-  // the word of the next group of four, fetched one group ahead
-  const int jg = kReverse ? (j >> 2) - 1 : (j >> 2) + 1;
-  uint32_t word_next = (jg >= 0 && 4 * jg < cnt) ? words[jg] : 0u;
-  int idx = (int)((word >> (8 * (j & 3))) & 0xFFu);
-  float4 na = sa[idx], nb = sb[idx];
-  float2 nc = kColor ? sc[idx] : make_float2(0.0f, 0.0f);
-  for (int step = 0; step < cnt; ++step) {
-    const int cur = idx;
-    const float4 ga = na, gb = nb;
-    const float2 gc = nc;
-    if (step + 1 < cnt) {
-      const int jn = kReverse ? j - 1 : j + 1;
-      if ((jn >> 2) != (j >> 2)) {
-        word = __builtin_amdgcn_readfirstlane(word_next);
-        const int g2 = kReverse ? (jn >> 2) - 1 : (jn >> 2) + 1;
-        word_next = (g2 >= 0 && 4 * g2 < cnt) ? words[g2] : 0u;
-      }
-      j = jn;
-      idx = (int)((word >> (8 * (j & 3))) & 0xFFu);
-      na = sa[idx];
-      nb = sb[idx];
-      if (kColor) nc = sc[idx];
-    }
-    if (body(cur, ga, gb, gc)) break;
-  }
-}
-
 // Front-to-back step of one pixel, branch-free: a pixel that is done, or that
 // the splat does not reach (alpha < 1/255), or that the splat would take
 // below the transmittance floor (which makes it done) adds w = 0 and keeps

@@ -16,7 +16,7 @@ constexpr int kItemsPerThread = 16;
 constexpr int kItemsPerBlock = kBlock * kItemsPerThread;  // radix sort / scan tile
 constexpr int kRadixBits = 9;  // widest digit: a 17-bit batch tile id still sorts in 2 passes
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kIptPayload1 = 16;  // radix items per thread with one payload word
+constexpr int kIptPayload1 = 12;  // radix items per thread with one payload word
 constexpr int kIptPayload3 = 8;   // ... with three payload words (LDS staging size)
 
 // The hardware hands the blocks of a launch to the 8 XCDs round-robin (block

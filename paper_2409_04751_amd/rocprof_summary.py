@@ -131,11 +131,11 @@ KERNELS = {
     "depth_sort_scatter": "::radix_scatter_kernel<3,",
     "rows": "::rows_kernel(",
     "duplicate": "::duplicate_kernel(",
-    "tile_sort_hist": "::radix_hist_kernel<16>",
+    "tile_sort_hist": "::radix_hist_kernel<12>",
     "tile_sort_scatter": "::radix_scatter_kernel<1,",
     "ranges": "::ranges_kernel(",
     "blend_forward": "::blend_forward_kernel(",
-    "blend_backward": "::blend_backward_kernel(",
+    "blend_backward": "::blend_backward_kernel<false>",
     "preprocess_backward": "::backward_fused_kernel<",
     "loss": "::l1_",
 }

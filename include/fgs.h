@@ -237,21 +237,22 @@ int fgs_render_backward(const fgs_gaussians* g, const fgs_pose* pose, const fgs_
 /*
  * Bytes of scratch fgs_render_backward_deterministic needs for n Gaussians
  * and up to k_capacity intersections (the K the view's forward reported):
- * 36 bytes per intersection for the per-entry sums, 16 for sorting them by
- * Gaussian, plus 8 per Gaussian and the sort's histograms.
+ * 36 bytes per intersection for the per-entry sums, 4 per Gaussian for the
+ * start of its run, and a scan's partial sums.
  */
 int fgs_deterministic_workspace_bytes(int64_t n, int64_t k_capacity, size_t* bytes);
 
 /*
- * fgs_render_backward with a run-to-run deterministic result.  The blend
- * backward stores each list entry's nine 2D-gradient sums (the reverse pass
- * of Eq. 3 as in Sec. 4.2) instead of adding them to per-Gaussian
- * accumulators with float atomics; the entries are then stably sorted by
- * Gaussian id inside det_workspace and each Gaussian's sums added in an
- * order fixed by their number (one wave per Gaussian: strided partial sums
- * in list order, then a fixed butterfly).  The same inputs give
- * bit-identical gradients on every call; they differ from
- * fgs_render_backward's only by the order of the float additions.
+ * fgs_render_backward with a run-to-run deterministic result.  Each Gaussian
+ * owns a run of as many slots as tiles it was binned to (an exclusive scan of
+ * the tile counts).  The blend backward stores each list entry's nine
+ * 2D-gradient sums (the reverse pass of Eq. 3 as in Sec. 4.2) in the slot of
+ * the entry's tile among its Gaussian's tiles, in tile order, instead of
+ * adding them to per-Gaussian accumulators with float atomics; one wave per
+ * Gaussian then adds its run in an order fixed by the run's length (strided
+ * partial sums, then a fixed butterfly).  The same inputs give bit-identical
+ * gradients on every call; they differ from fgs_render_backward's only by the
+ * order of the float additions.
  * det_workspace: device, caller-owned, at least
  *   fgs_deterministic_workspace_bytes(n, K) bytes for the forward's K (its
  *   contents on entry do not matter; it holds nothing afterwards).

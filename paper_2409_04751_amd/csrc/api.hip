@@ -466,7 +466,7 @@ int backward_impl(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera
   const ViewParams v = make_view(pose, cam, bg, 0u, 0u);
   float* grad2d = reinterpret_cast<float*>(ws + L.grad2d);
   const uint32_t* ids = reinterpret_cast<const uint32_t*>(ws + L.tile_ids_final);
-  float* part = nullptr;
+  DetStore store{};
   int64_t K = 0;
   if (det) {
     // the forward's K, read back once: it sizes the per-entry sums
@@ -482,8 +482,14 @@ int backward_impl(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera
                     det_bytes, det_workspace_bytes(g->n, K), (long long)K);
       return fail(FGS_ERR_WORKSPACE, msg);
     }
-    part = static_cast<float*>(det_ws);
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(part), 0u, 9 * K, s), "clear per-entry sums");
+    char* dws = static_cast<char*>(det_ws);
+    store.part = reinterpret_cast<float*>(dws);
+    store.rects = reinterpret_cast<const uint2*>(ws + L.rects);
+    store.rowrange = reinterpret_cast<const uint32_t*>(ws + L.rowrange);
+    store.gauss_off = det_gauss_off(dws, g->n, K);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(store.part), 0u, 9 * K, s), "clear per-entry sums");
+    HIP_TRY(launch_grad_offsets(reinterpret_cast<const uint32_t*>(ws + L.tiles), g->n, K, dws, s),
+            "per-Gaussian runs");
   } else {
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, grad_words(g->n), s), "clear grad2d");
   }
@@ -492,10 +498,12 @@ int backward_impl(const fgs_gaussians* g, const fgs_pose* pose, const fgs_camera
                                 reinterpret_cast<const float4*>(ws + L.colors), dL_drgb,
                                 reinterpret_cast<const float*>(ws + L.pixel_T),
                                 reinterpret_cast<const uint32_t*>(ws + L.pixel_last),
-                                reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, part, g->n, s),
+                                reinterpret_cast<const uint32_t*>(ws + L.counters), grad2d, det ? &store : nullptr,
+                                g->n, s),
           "blend backward");
   if (det)
-    HIP_TRY(launch_grad_segreduce(ids, K, g->n, bits_for(g->n), static_cast<char*>(det_ws), det_bytes, grad2d, s),
+    HIP_TRY(launch_grad_segreduce(reinterpret_cast<const uint32_t*>(ws + L.tiles), g->n, K, static_cast<char*>(det_ws),
+                                  grad2d, s),
             "deterministic reduction");
   HIP_TRY(launch_preprocess_backward(*g, v, ws, L, *grads, s), "preprocess backward");
   return FGS_OK;

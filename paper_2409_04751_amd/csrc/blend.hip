@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "fgs_internal.hpp"
+#include "reach.hpp"
 
 namespace fgs {
 namespace {
@@ -207,9 +208,38 @@ struct BlendBwdArgs {
   const uint32_t* pixel_last;
   const uint32_t* counters;
   float* grad2d;  // [grad_slot(g)][9]
-  float* part;    // null, or [entry][9]: the sums stored per list entry instead
+  // deterministic mode: the nine sums of each list entry are stored at
+  // part[gauss_off[g] + rank][9], rank = the entry's tile among g's tiles in
+  // tile order (its position in g's run of the duplication), recomputed from
+  // g's rect, rows to bin and splat record as the binning counted them
+  float* part;
+  const uint2* rects;
+  const uint32_t* rowrange;
+  const float4* raw_splats;  // the records as stored (splats, unshifted)
+  const uint32_t* gauss_off;
   uint32_t n;
 };
+
+// Position of tile (tx, ty) among the tiles Gaussian g was binned to, in
+// tile order: the kept columns of g's rows above ty, then the columns of row
+// ty before tx.  Rows and columns are those the binning took: the whole rect
+// with FGS_RECT_BINNING, else the rows from rowrange with reach_row's
+// columns on the float record (the same routine, so the same counts).
+__device__ inline uint32_t tile_rank(const BlendBwdArgs& a, uint32_t g, int tx, int ty, bool rect) {
+  const uint2 rc = a.rects[g];
+  const int x0 = (int)(rc.x & 0xFFFFu), x1 = (int)(rc.y & 0xFFFFu);
+  if (rect) return (uint32_t)((ty - (int)(rc.x >> 16)) * (x1 - x0) + (tx - x0));
+  const int y0 = (int)(a.rowrange[g] & 0xFFFFu);
+  const SplatReach R = splat_reach(a.raw_splats[2 * (size_t)g], a.raw_splats[2 * (size_t)g + 1]);
+  uint32_t rank = 0;
+  int c0, c1;
+  for (int y = y0; y < ty; ++y) {
+    reach_row(R, y, x0, x1, c0, c1);
+    rank += (uint32_t)(c1 - c0);
+  }
+  reach_row(R, ty, x0, x1, c0, c1);
+  return rank + (uint32_t)(tx - c0);
+}
 
 // DPP lane exchange inside each 16-lane row (all patterns are permutations,
 // so every lane has a valid source).
@@ -351,6 +381,7 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
   const uint2 r = a.ranges[tile];
   const size_t hw = (size_t)a.width * a.height;
   const bool saved = (a.counters[kCountFlags] & FGS_SAVE_PIXEL_STATE) != 0;
+  const bool rect = (a.counters[kCountFlags] & FGS_RECT_BINNING) != 0;
   const float fi = (float)(lane & 15u);
   const int px = tx * kTile + (int)(lane & 15u);
   BwdPixel P[4];
@@ -443,7 +474,10 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       S.sa[lane] = ta;
       S.sb[lane] = tb;
       S.sc[lane] = tc;
-      S.sid[lane] = g;
+      if constexpr (STORE)  // where this entry's sums go (sid is not needed for atomics)
+        S.sid[lane] = a.gauss_off[g] + tile_rank(a, g, tx, ty, rect);
+      else
+        S.sid[lane] = g;
     }
     wave_lds_sync();
     const int cnt = end - beg;
@@ -491,8 +525,8 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       const float part = wave_rows_sum(row_reduce_scatter9(v, rb3, rb2, rb1, rb0));
       if (writer) {
         const float val = part * wscale;
-        if constexpr (STORE)  // e counts from the tile's first entry
-          a.part[((size_t)r.x + e) * 9 + rval] = val;
+        if constexpr (STORE)
+          a.part[(size_t)S.sid[idx] * 9 + rval] = val;
         else if (val != 0.0f)
           atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
       }
@@ -536,7 +570,8 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids, const float4* splats,
                                  const float4* colors,
                                  const float* dL_dimg, const float* pixel_T, const uint32_t* pixel_last,
-                                 const uint32_t* counters, float* grad2d, float* part, int64_t n, hipStream_t s) {
+                                 const uint32_t* counters, float* grad2d, const DetStore* det, int64_t n,
+                                 hipStream_t s) {
   BlendBwdArgs a;
   a.ranges = ranges;
   a.ids = ids;
@@ -552,11 +587,15 @@ hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const
   a.pixel_last = pixel_last;
   a.counters = counters;
   a.grad2d = grad2d;
-  a.part = part;
+  a.part = det ? det->part : nullptr;
+  a.rects = det ? det->rects : nullptr;
+  a.rowrange = det ? det->rowrange : nullptr;
+  a.raw_splats = splats;
+  a.gauss_off = det ? det->gauss_off : nullptr;
   a.n = (uint32_t)n;
   const int64_t tiles = (int64_t)v.tiles_x * v.tiles_y;
   ProfScope prof(s, kKBlendBackward);
-  if (part)
+  if (det)
     hipLaunchKernelGGL(blend_backward_kernel<true>, dim3((unsigned)ceil_div(tiles, kBwdWaves)), dim3(kBwdThreads), 0,
                        s, a);
   else

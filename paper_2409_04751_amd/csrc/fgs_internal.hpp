@@ -255,26 +255,39 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
                                 const float4* splats, const float4* colors, const BatchOut& out, float* pixel_T,
                                 uint32_t* pixel_last, bool save, hipStream_t s);
 
+// Deterministic mode of the blend backward: each list entry's nine sums are
+// stored at part[gauss_off[g] + rank][9] (rank = the entry's tile among the
+// tiles g was binned to, in tile order), so each Gaussian's sums form one
+// run in tile order.  rects / rowrange as the forward's preprocess left them.
+struct DetStore {
+  float* part;
+  const uint2* rects;
+  const uint32_t* rowrange;
+  const uint32_t* gauss_off;
+};
+
 // grad2d: [grad_slot(g)][9] per-Gaussian sums (dL/d mu_p xy, conic A B C, opacity, rgb),
 // grad_words(n) zeroed words, to which each (Gaussian, tile) adds its sums
-// with float atomics.  With `part` not null the sums are stored instead, as
-// part[e][9] for list entry e (entries the backward does not reach keep what
-// the caller stored: zeros), and grad2d is not touched.
+// with float atomics; with det not null the sums are stored as DetStore says
+// (entries the backward does not reach keep what the caller stored: zeros)
+// and grad2d is not touched.
 hipError_t launch_blend_backward(const ViewParams& v, const uint2* ranges, const uint32_t* ids,
                                  const float4* splats, const float4* colors, const float* dL_dimg,
                                  const float* pixel_T,
-                                 const uint32_t* pixel_last, const uint32_t* counters, float* grad2d, float* part,
-                                 int64_t n, hipStream_t s);
+                                 const uint32_t* pixel_last, const uint32_t* counters, float* grad2d,
+                                 const DetStore* det, int64_t n, hipStream_t s);
 
-// Deterministic reduction of the stored sums: det_workspace_bytes(n, K) bytes
-// of scratch whose first 36 K bytes are the part[K][9] array the blend
-// backward fills; the entries' Gaussian ids (the tile-sorted list, ids < n,
-// key_bits wide) are stably sorted in that scratch and each Gaussian's run is
-// summed in an order fixed by its length into grad2d[grad_slot(g)][9]
-// (written, every g < n).
+// Deterministic reduction, in det_workspace_bytes(n, K) bytes of scratch whose
+// first 36 K bytes are the part[K][9] array:
+//   launch_grad_offsets: gauss_off = exclusive scan of the tile counts (the
+//     start of each Gaussian's run), before the blend backward;
+//   launch_grad_segreduce: grad2d[grad_slot(g)][9] = the sum of g's run
+//     (tiles[g] entries) in an order fixed by its length (written, every g < n).
 size_t det_workspace_bytes(int64_t n, int64_t k_capacity);
-hipError_t launch_grad_segreduce(const uint32_t* ids, int64_t K, int64_t n, int key_bits, char* dws, size_t dws_bytes,
-                                 float* grad2d, hipStream_t s);
+uint32_t* det_gauss_off(char* dws, int64_t n, int64_t K);
+hipError_t launch_grad_offsets(const uint32_t* tiles, int64_t n, int64_t K, char* dws, hipStream_t s);
+hipError_t launch_grad_segreduce(const uint32_t* tiles, int64_t n, int64_t K, char* dws, float* grad2d,
+                                 hipStream_t s);
 
 hipError_t launch_preprocess_backward(const fgs_gaussians& g, const ViewParams& v, const char* ws,
                                       const Layout& L, const fgs_grads& out, hipStream_t s);

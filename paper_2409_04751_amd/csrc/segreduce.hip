@@ -4,13 +4,12 @@
 // projected mean, the conic, the opacity and the colour; Sec. 4.2, the part
 // shared with vanilla splatting) to the Gaussian's accumulators with float
 // atomics, so the result depends on the order in which tiles finish.  Here
-// the blend backward stores the nine sums of every list entry instead
-// (part[e][9], e the entry's position in the tile-sorted list), and this file
-// adds them up per Gaussian in a fixed order: the entries are stably sorted by
-// Gaussian id (so each Gaussian's entries form one run, in list order), and
-// one wave per Gaussian sums its run in an order fixed by the run's length.  The same inputs give
-// the same bits on every run; the values differ from the atomic order only by
-// the reassociation of the float additions.
+// each Gaussian g owns a run of tiles[g] slots (gauss_off = exclusive scan of
+// the tile counts), the blend backward stores the sums of its entry in tile t
+// at the slot of t's rank among g's tiles (tile order), and each Gaussian's
+// run is added in an order fixed by the run's length.  The same
+// inputs give the same bits on every run; the values differ from the atomic
+// order only by the reassociation of the float additions.
 #include <algorithm>
 
 #include "fgs_internal.hpp"
@@ -18,64 +17,63 @@
 namespace fgs {
 namespace {
 
-__global__ __launch_bounds__(kBlock) void iota_kernel(uint32_t* p, uint32_t count) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < count) p[i] = i;
-}
+// grad2d[slot(g)][c] = the sum of g's run (tiles[g] slots from gauss_off[g]),
+// one thread per Gaussian, in an order fixed by the run's length: a run of up
+// to kLongRun slots is added front to back by its own thread; a longer one
+// (the largest splats reach thousands of tiles, which would hold a whole wave
+// back) by the whole wave, lane l taking slots l, l + 64, ... in order and the
+// lanes then added by a fixed butterfly (every lane ends with the same
+// total: each butterfly step adds the same two values in both partner lanes).
+constexpr uint32_t kLongRun = 64;
 
-// seg[k] = [first, one past last) position of key k's run in the sorted keys;
-// keys without a run keep the (0, 0) the caller stored.
-__global__ __launch_bounds__(kBlock) void seg_bounds_kernel(const uint32_t* keys, uint32_t count, uint32_t nkeys,
-                                                           uint2* seg) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t k = keys[i];
-  if (k >= nkeys) return;
-  if (i == 0 || keys[i - 1] != k) seg[k].x = i;
-  if (i + 1 == count || keys[i + 1] != k) seg[k].y = i + 1;
-}
-
-// grad2d[slot(g)][c] = the sum of part[pos][c] over g's run, one wave per
-// Gaussian (runs reach thousands of entries for the largest splats, so a
-// thread per Gaussian would serialise their loads): lane l adds entries
-// l, l + 64, ... in order, then the lanes are added by a fixed butterfly.
-// Both orders depend on the run's length only, so the sum is the same on
-// every call (every lane ends with the same total: each butterfly step adds
-// the same two values in both partner lanes).
-constexpr int kReduceWaves = kBlock / 64;
-
-__global__ __launch_bounds__(kBlock) void seg_reduce_kernel(const uint2* seg, const uint32_t* pos, const float* part,
-                                                           uint32_t n, float* grad2d) {
-  const uint32_t g = blockIdx.x * kReduceWaves + (threadIdx.x >> 6);
+__global__ __launch_bounds__(kBlock) void seg_reduce_kernel(const uint32_t* tiles, const uint32_t* gauss_off,
+                                                           const float* part, uint32_t n, float* grad2d) {
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
-  if (g >= n) return;  // wave-uniform
-  const uint2 r = seg[g];
+  const uint32_t cnt = g < n ? tiles[g] : 0u, beg = g < n ? gauss_off[g] : 0u;
   float acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-  for (uint32_t k = r.x + lane; k < r.y; k += 64) {
-    const float* p = part + (size_t)pos[k] * 9;
+  const bool long_run = cnt > kLongRun;
+  if (!long_run)
+    for (uint32_t k = beg; k < beg + cnt; ++k) {
+      const float* p = part + (size_t)k * 9;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] += p[c];
+      for (int c = 0; c < 9; ++c) acc[c] += p[c];
+    }
+  uint64_t m = __ballot(long_run);
+  while (m != 0ull) {  // wave-uniform
+    const uint32_t l = (uint32_t)__builtin_ctzll(m);
+    m &= m - 1ull;
+    const uint32_t b = (uint32_t)__shfl((int)beg, (int)l, 64), e = b + (uint32_t)__shfl((int)cnt, (int)l, 64);
+    float v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = 0.0f;
+    for (uint32_t k = b + lane; k < e; k += 64) {
+      const float* p = part + (size_t)k * 9;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) v[c] += p[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v[c] += __shfl_xor(v[c], d, 64);
+      if (lane == l) acc[c] = v[c];
+    }
   }
-  float mine = 0.0f;
+  if (g < n) {
+    float* out = grad2d + (size_t)grad_slot(g) * 9;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    float v = acc[c];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (lane == (uint32_t)c) mine = v;
+    for (int c = 0; c < 9; ++c) out[c] = acc[c];
   }
-  if (lane < 9u) grad2d[(size_t)grad_slot(g) * 9 + lane] = mine;
 }
 
 struct DetLayout {
-  size_t part, keys_a, keys_b, vals_a, vals_b, seg, hist, partials, bytes;
+  size_t part, off, partials, bytes;
 };
 
 DetLayout det_layout(int64_t n, int64_t kcap) {
   const int64_t nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
-  const int64_t nb = radix_blocks(kk, 1);
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   DetLayout d;
   size_t off = 0;  // part first: the blend backward writes it at the scratch's start
@@ -85,13 +83,8 @@ DetLayout det_layout(int64_t n, int64_t kcap) {
     return at;
   };
   d.part = take((size_t)kk * 9 * 4);
-  d.keys_a = take((size_t)kk * 4);
-  d.keys_b = take((size_t)kk * 4);
-  d.vals_a = take((size_t)kk * 4);
-  d.vals_b = take((size_t)kk * 4);
-  d.seg = take((size_t)nn * 8);
-  d.hist = take((size_t)nb * kRadix * 4);
-  d.partials = take((size_t)(ceil_div(std::max<int64_t>(kk, nb * kRadix), kItemsPerBlock) + 1) * 4);
+  d.off = take((size_t)nn * 4);
+  d.partials = take((size_t)(ceil_div(nn, kItemsPerBlock) + 1) * 4);
   d.bytes = off;
   return d;
 }
@@ -100,44 +93,25 @@ DetLayout det_layout(int64_t n, int64_t kcap) {
 
 size_t det_workspace_bytes(int64_t n, int64_t k_capacity) { return det_layout(n, k_capacity).bytes; }
 
-hipError_t launch_grad_segreduce(const uint32_t* ids, int64_t K, int64_t n, int key_bits, char* dws, size_t dws_bytes,
-                                 float* grad2d, hipStream_t s) {
+uint32_t* det_gauss_off(char* dws, int64_t n, int64_t K) {
+  return reinterpret_cast<uint32_t*>(dws + det_layout(n, K).off);
+}
+
+hipError_t launch_grad_offsets(const uint32_t* tiles, int64_t n, int64_t K, char* dws, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const DetLayout d = det_layout(n, K);
-  if (dws_bytes < d.bytes) return hipErrorInvalidValue;
-  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(dws + off); };
-  uint2* seg = reinterpret_cast<uint2*>(dws + d.seg);
-  hipError_t e = launch_fill_u32(U(d.seg), 0u, 2 * n, s);
-  if (e != hipSuccess) return e;
-  const uint32_t* keys = U(d.keys_a);
-  const uint32_t* pos = U(d.vals_a);
-  if (K > 0) {
-    e = hipMemcpyAsync(U(d.keys_a), ids, (size_t)K * 4, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    {
-      ProfScope prof(s, kKSegReduce);
-      hipLaunchKernelGGL(iota_kernel, dim3((unsigned)ceil_div(K, kBlock)), dim3(kBlock), 0, s, U(d.vals_a),
-                         (uint32_t)K);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // stable: each Gaussian's entries keep their list order
-    RadixBuffers B{1, U(d.keys_a), U(d.keys_b), {U(d.vals_a), nullptr, nullptr}, {U(d.vals_b), nullptr, nullptr}};
-    e = launch_radix_sort(B, nullptr, K, key_bits, U(d.hist), U(d.partials), s, kKSegReduce, kKSegReduce);
-    if (e != hipSuccess) return e;
-    if (radix_passes(key_bits) % 2 == 1) {
-      keys = U(d.keys_b);
-      pos = U(d.vals_b);
-    }
-    ProfScope prof(s, kKSegReduce);
-    hipLaunchKernelGGL(seg_bounds_kernel, dim3((unsigned)ceil_div(K, kBlock)), dim3(kBlock), 0, s, keys, (uint32_t)K,
-                       (uint32_t)n, seg);
-  }
-  {
-    ProfScope prof(s, kKSegReduce);
-    hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)ceil_div(n, kReduceWaves)), dim3(kBlock), 0, s, seg, pos,
-                       reinterpret_cast<const float*>(dws + d.part), (uint32_t)n, grad2d);
-  }
+  return launch_scan(tiles, nullptr, nullptr, n, kScanPlain, reinterpret_cast<uint32_t*>(dws + d.partials), nullptr,
+                     reinterpret_cast<uint32_t*>(dws + d.off), s);
+}
+
+hipError_t launch_grad_segreduce(const uint32_t* tiles, int64_t n, int64_t K, char* dws, float* grad2d,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const DetLayout d = det_layout(n, K);
+  ProfScope prof(s, kKSegReduce);
+  hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, s, tiles,
+                     reinterpret_cast<const uint32_t*>(dws + d.off), reinterpret_cast<const float*>(dws + d.part),
+                     (uint32_t)n, grad2d);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ class Workspace:
         self.generation = 0
         # backwards on this workspace reduce the 2D gradients in a fixed order
         # (bit-identical from run to run) instead of with float atomics; they
-        # then need K x 52 bytes more scratch, kept in det_buf
+        # then need about 36 K + 4 N bytes more scratch, kept in det_buf
         self.deterministic = deterministic
         self.det_buf: torch.Tensor | None = None
         self.k = 0  # intersections of the last forward rendered into it

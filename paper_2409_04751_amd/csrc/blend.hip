@@ -19,6 +19,7 @@
 // (equivalently q2 < log2(1/(255 o))), alpha = min(0.99, o e^q), stop before
 // the Gaussian that would take T below 1e-4.
 #include <algorithm>
+#include <type_traits>
 
 #include "fgs_internal.hpp"
 #include "reach.hpp"
@@ -364,7 +365,59 @@ struct BwdStage {
   float4 sb[kBwdChunk];
   float2 sc[kBwdChunk];
   uint32_t sid[kBwdChunk];
+  uint32_t sslot[kBwdChunk];  // the entry's slot in the block's table (kNoSlot: none)
 };
+
+// The block's four waves blend four neighbouring tiles, whose lists share
+// most of their Gaussians.  Device-scope float atomics are performed past the
+// per-XCD L2s, on the memory side, so each (Gaussian, tile) adding its nine
+// sums to the global accumulators costs a memory-side atomic request; the
+// block instead adds them into an LDS table keyed by Gaussian (open
+// addressing, linear probing, LDS atomics) and adds each Gaussian's totals to
+// the accumulators once, after its four tiles are done.  An entry that finds
+// no free slot within kTableProbes adds directly, as before, and so does a
+// wave whose pixels blend more than kTableListMax entries (unsaturated
+// tiles): its Gaussians would only crowd the table.
+constexpr int kTableBits = 8;
+constexpr uint32_t kTableSize = 1u << kTableBits;
+constexpr int kTableProbes = 8;
+constexpr uint32_t kTableListMax = 128;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
+struct GradTable {
+  uint32_t key[kTableSize];
+  float val[kTableSize][9];
+  uint32_t used;  // slots taken; past three quarters new Gaussians add directly
+};
+struct NoTable {};
+
+// Slot of Gaussian g in the table, inserting it if absent (one lane per call).
+// Long unsaturated lists (thousands of entries per block) would fill the
+// table and make every entry probe in vain, so once three quarters of the
+// slots are taken a Gaussian not yet in the table is not inserted (the count
+// is read without ordering: it only decides between two correct paths).
+__device__ inline uint32_t table_slot(GradTable& T, uint32_t g) {
+  const uint32_t h = (g * 2654435761u) >> (32 - kTableBits);
+  const bool full = __hip_atomic_load(&T.used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >=
+                    kTableSize / 4 * 3;
+  for (int p = 0; p < kTableProbes; ++p) {
+    const uint32_t s = (h + (uint32_t)p) & (kTableSize - 1u);
+    if (full) {
+      const uint32_t k = __hip_atomic_load(&T.key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == g) return s;
+      if (k == kEmptyKey) return kNoSlot;
+      continue;
+    }
+    const uint32_t old = atomicCAS(&T.key[s], kEmptyKey, g);
+    if (old == kEmptyKey) {
+      atomicAdd(&T.used, 1u);
+      return s;
+    }
+    if (old == g) return s;
+  }
+  return kNoSlot;
+}
 
 
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
@@ -374,8 +427,8 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 
 // STORE: the nine sums of each entry are stored at part[entry] (the
 // deterministic mode) instead of added to the Gaussian's accumulators
-template <bool STORE>
-__device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_t tile, uint32_t lane) {
+template <bool STORE, class Table>
+__device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, Table& T, uint32_t tile, uint32_t lane) {
   const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 r = a.ranges[tile];
@@ -440,6 +493,7 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
     }
   }
   const uint32_t maxlast = wave_max_u32(max(max(P[0].last, P[1].last), max(P[2].last, P[3].last)));
+  [[maybe_unused]] const bool use_table = maxlast <= kTableListMax;
 
   // ---- reverse sweep ----
 #pragma unroll
@@ -474,10 +528,12 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       S.sa[lane] = ta;
       S.sb[lane] = tb;
       S.sc[lane] = tc;
-      if constexpr (STORE)  // where this entry's sums go (sid is not needed for atomics)
+      if constexpr (STORE) {  // where this entry's sums go (sid is not needed for atomics)
         S.sid[lane] = a.gauss_off[g] + tile_rank(a, g, tx, ty, rect);
-      else
+      } else {
         S.sid[lane] = g;
+        S.sslot[lane] = use_table ? table_slot(T, g) : kNoSlot;
+      }
     }
     wave_lds_sync();
     const int cnt = end - beg;
@@ -525,23 +581,52 @@ __device__ inline void backward_tile(const BlendBwdArgs& a, BwdStage& S, uint32_
       const float part = wave_rows_sum(row_reduce_scatter9(v, rb3, rb2, rb1, rb0));
       if (writer) {
         const float val = part * wscale;
-        if constexpr (STORE)
+        if constexpr (STORE) {
           a.part[(size_t)S.sid[idx] * 9 + rval] = val;
-        else if (val != 0.0f)
-          atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
+        } else if (val != 0.0f) {
+          const uint32_t ts = S.sslot[idx];
+          if (ts != kNoSlot)
+            atomicAdd(&T.val[ts][rval], val);
+          else
+            atomicAdd(&gout[(size_t)grad_slot(S.sid[idx]) * 9], val);
+        }
       }
     }
     wave_lds_sync();
   }
 }
 
+// Five waves per SIMD with the table (its 92 registers then need no spills;
+// six would spill 14), six in the deterministic mode.
 template <bool STORE>
-__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(6))) void blend_backward_kernel(BlendBwdArgs a) {
+__global__ __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(STORE ? 6 : 5))) void blend_backward_kernel(BlendBwdArgs a) {
   __shared__ BwdStage stage[kBwdWaves];
+  using Table = std::conditional_t<STORE, NoTable, GradTable>;
+  __shared__ Table table;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   BwdStage& S = stage[wave];
+  if constexpr (!STORE) {
+    for (uint32_t i = threadIdx.x; i < kTableSize; i += kBwdThreads) table.key[i] = kEmptyKey;
+    if (threadIdx.x == 0) table.used = 0;
+    float* v = &table.val[0][0];
+    for (uint32_t i = threadIdx.x; i < kTableSize * 9; i += kBwdThreads) v[i] = 0.0f;
+    __syncthreads();
+  }
   const uint32_t tile = xcd_chunk(blockIdx.x, gridDim.x) * kBwdWaves + wave;
-  if (tile < (uint32_t)a.tiles_x * (uint32_t)a.tiles_y) backward_tile<STORE>(a, S, tile, lane);
+  if (tile < (uint32_t)a.tiles_x * (uint32_t)a.tiles_y) backward_tile<STORE>(a, S, table, tile, lane);
+  if constexpr (!STORE) {
+    // each used slot's nine totals: lanes 16 k .. 16 k + 8 of a wave take
+    // slot 4 w + k + 16 j, so one atomic instruction covers four Gaussians'
+    // 36-byte blocks
+    __syncthreads();
+    const uint32_t c = lane & 15u;
+    for (uint32_t sl = (threadIdx.x >> 4); sl < kTableSize; sl += kBwdThreads / 16) {
+      const uint32_t g = table.key[sl];
+      if (g == kEmptyKey || c >= 9u) continue;
+      const float v = table.val[sl][c];
+      if (v != 0.0f) atomicAdd(&a.grad2d[(size_t)grad_slot(g) * 9 + c], v);
+    }
+  }
 }
 
 }  // namespace

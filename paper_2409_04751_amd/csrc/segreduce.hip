@@ -35,12 +35,26 @@ __global__ __launch_bounds__(kBlock) void seg_reduce_kernel(const uint32_t* tile
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
   const bool long_run = cnt > kLongRun;
-  if (!long_run)
-    for (uint32_t k = beg; k < beg + cnt; ++k) {
+  if (!long_run) {
+    // four entries' loads in flight at a time, added in order
+    uint32_t k = beg;
+    for (; k + 4u <= beg + cnt; k += 4u) {
+      float w[4][9];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) w[j][c] = part[(size_t)(k + j) * 9 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] += w[j][c];
+    }
+    for (; k < beg + cnt; ++k) {
       const float* p = part + (size_t)k * 9;
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] += p[c];
     }
+  }
   uint64_t m = __ballot(long_run);
   while (m != 0ull) {  // wave-uniform
     const uint32_t l = (uint32_t)__builtin_ctzll(m);

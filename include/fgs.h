@@ -224,7 +224,8 @@ int fgs_render_forward_batch(const fgs_gaussians* g, int32_t nviews, const fgs_p
  * Blend backward walks each pixel's contributors last to first, recovering
  * T_i = T_{i+1} / (1 - alpha_i) from the final transmittance (recomputed by a
  * front-to-back sweep unless the forward saved it), reduces per-Gaussian
- * gradients within each tile and adds them to global accumulators; the
+ * gradients within each tile, adds them up over each block of four
+ * neighbouring tiles in LDS and then to global accumulators; the
  * preprocess backward then applies the chain of Sec. 4.2-4.3 (J_phi and
  * dJ/dmu_c) and the covariance / SH derivatives.  Overwrites the
  * workspace's grad2d scratch.  Gradients are deterministic up to the order of

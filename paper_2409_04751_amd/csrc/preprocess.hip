@@ -593,21 +593,37 @@ __device__ inline void geometry_backward_body(const PreBwdArgs& a, uint32_t i) {
   for (int c = 0; c < 3; ++c)
     gm[c] = a.v.R[0 * 3 + c] * gpc[0] + a.v.R[1 * 3 + c] * gpc[1] + a.v.R[2 * 3 + c] * gpc[2];
   for (int c = 0; c < 3; ++c) a.g_means[c * n + i] = (float)(gm[c] + (double)a.g_means[c * n + i]);
-  // Sigma = M M^T, M = R S: dL/dM = 2 dS M
+  // Sigma = M M^T, M = R S: dL/dM = 2 dS M.  The rotation, the normalised
+  // quaternion and the scales are formed again from the inputs, as
+  // compute_geometry formed them (the same operations, so the same values):
+  // the registers of G's copies are then free through the chain above, which
+  // keeps the kernel at four waves per SIMD.
+  double Rq[9], qn[4], sc[3];
+  double qnorm;
+  {
+    const float qf[4] = {a.quats[i], a.quats[n + i], a.quats[2 * n + i], a.quats[3 * n + i]};
+    double q2 = 0.0;
+    for (int k = 0; k < 4; ++k) q2 += (double)qf[k] * (double)qf[k];
+    qnorm = sqrt(q2);
+    const double iq = 1.0 / qnorm;
+    for (int k = 0; k < 4; ++k) qn[k] = (double)qf[k] * iq;
+    quat_to_rot(qn, Rq);
+    for (int k = 0; k < 3; ++k) sc[k] = (double)a.scales[k * n + i];
+  }
   double M[9];
   for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) M[r * 3 + c] = G.Rq[r * 3 + c] * G.s[c];
+    for (int c = 0; c < 3; ++c) M[r * 3 + c] = Rq[r * 3 + c] * sc[c];
   double dM[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
       dM[r * 3 + c] = 2.0 * (dS[r * 3 + 0] * M[0 * 3 + c] + dS[r * 3 + 1] * M[1 * 3 + c] + dS[r * 3 + 2] * M[2 * 3 + c]);
   for (int c = 0; c < 3; ++c)
-    put(&a.g_scales[c * n + i], (float)(dM[0 * 3 + c] * G.Rq[0 * 3 + c] + dM[1 * 3 + c] * G.Rq[1 * 3 + c] +
-                                        dM[2 * 3 + c] * G.Rq[2 * 3 + c]));
+    put(&a.g_scales[c * n + i], (float)(dM[0 * 3 + c] * Rq[0 * 3 + c] + dM[1 * 3 + c] * Rq[1 * 3 + c] +
+                                        dM[2 * 3 + c] * Rq[2 * 3 + c]));
   double dR[9];
   for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * G.s[c];
-  const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * sc[c];
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
   double gq[4];
   gq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
   gq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
@@ -617,8 +633,8 @@ __device__ inline void geometry_backward_body(const PreBwdArgs& a, uint32_t i) {
   gq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
                  y * dR[7]);
   // through the normalisation q / |q|
-  const double qd = G.qn[0] * gq[0] + G.qn[1] * gq[1] + G.qn[2] * gq[2] + G.qn[3] * gq[3];
-  for (int c = 0; c < 4; ++c) put(&a.g_quats[c * n + i], (float)((gq[c] - G.qn[c] * qd) / G.qnorm));
+  const double qd = qn[0] * gq[0] + qn[1] * gq[1] + qn[2] * gq[2] + qn[3] * gq[3];
+  for (int c = 0; c < 4; ++c) put(&a.g_quats[c * n + i], (float)((gq[c] - qn[c] * qd) / qnorm));
   put(&a.g_opac[i], go);
   if (a.g_means2d) {
     put(&a.g_means2d[i], (float)gmu[0]);

@@ -44,7 +44,8 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * N
     if name == "depth_sort_hist":
         return 4.0 * N
-    if name == "duplicate":  # K pairs out (the rows' offsets, ids and columns are read once per row)
+    if name == "duplicate":  # K pairs out, in the tile sort's first-pass order (the rows' offsets, ids
+        # and columns are read once per row)
         return 8.0 * K
     if name == "tile_sort_hist":
         return 4.0 * K

@@ -101,7 +101,9 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
-  const bool in_b = L.tile_passes % 2 == 1;
+  // the duplication does the first pass into *_a (also with no key bits),
+  // each later pass swaps the planes
+  const bool in_b = (std::max(L.tile_passes, 1) - 1) % 2 == 1;
   L.tile_keys_final = in_b ? L.tkeys_b : L.tkeys_a;
   L.tile_ids_final = in_b ? L.tvals_b : L.tvals_a;
   return L;
@@ -328,7 +330,7 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   const int depth_bits = V > 1 ? bits_for((int64_t)(kmax - kmin) + 1) : 0;
   RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
                   {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
-  HIP_TRY(launch_radix_sort(DB, nullptr, V, depth_bits, hist, partials, s, kKDepthHist, kKDepthScatter, false, kmin),
+  HIP_TRY(launch_radix_sort(DB, nullptr, V, depth_bits, hist, partials, s, kKDepthHist, kKDepthScatter, 0, kmin),
           "depth sort");
   // an odd number of passes leaves the order in the *_b planes; the id plane
   // is copied back so the layout's depth_order always holds it
@@ -354,11 +356,13 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s,
                       U(L.block_first), kDupItems),
           "row count scan");
-  HIP_TRY(launch_duplicate(U(L.row_off), row_g, row_yc, U(L.block_first), R, K, b, n, L.tile_bits, hist,
-                           U(L.tkeys_a), U(L.tvals_a), s),
+  // the pairs come out of the duplication in the order of the tile sort's
+  // first pass (into *_a: the rows still sit in *_b); the sort does the rest
+  HIP_TRY(launch_duplicate_sorted(U(L.row_off), row_g, row_yc, U(L.block_first), R, K, b, n, L.tile_bits, hist,
+                                  partials, U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
   RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
-  HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, true),
+  HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, 1),
           "tile sort");
   uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);
   HIP_TRY(launch_ranges(U(L.tile_keys_final), K, ranges, (int32_t)L.total_tiles, s), "ranges");

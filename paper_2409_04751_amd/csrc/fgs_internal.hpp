@@ -84,6 +84,7 @@ enum KernelId {
   kKLoss,
   kKOrder,
   kKSegReduce,
+  kKDupHist,
   kKNumKernels
 };
 const char* kernel_name(int id);
@@ -197,15 +198,15 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
                        uint32_t* aux = nullptr, uint32_t aux_block = 0);
 
 // Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
-// bits [0, bits), same item-count convention as launch_scan.  The result is
-// in the *_a buffers after an even number of passes, else in *_b.
-// If first_hist_ready, the digit histogram of pass 0 is already in hist
-// (digit-major, one column per radix block).
+// bits [0, bits), same item-count convention as launch_scan.  Passes before
+// first_pass are taken as done (the keys in *_a are in their order); the
+// result is in the *_a buffers after an even number of the remaining passes,
+// else in *_b.
 // Digits are taken from key - key_bias (every key must be >= key_bias); the
 // keys themselves are moved unchanged.
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                             bool first_hist_ready = false, uint32_t key_bias = 0);
+                             int first_pass = 0, uint32_t key_bias = 0);
 int radix_passes(int bits);
 int64_t radix_blocks(int64_t max_count, int payload);
 
@@ -234,15 +235,17 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
                        uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, hipStream_t s);
 
 // One (tile, id) pair per kept tile of each row, at the row's offset
-// row_off[t] (exclusive scan of the counts); K pairs in total, in depth
-// order.  Also writes the first-pass digit histogram of the tile sort
-// (tile_bits key bits) into hist.  Ids are view-major (view * n +
-// Gaussian); the pair's key is the view's tile_base plus the tile index
-// inside the view.
+// row_off[t] (exclusive scan of the counts) in depth order, K pairs in
+// total, put through the first pass of the tile sort (the tile_bits-bit
+// sort launch_radix_sort would do, first digit) on the way: the pairs land
+// in out_keys / out_vals in that pass's order.  Ids are view-major (view * n
+// + Gaussian); the pair's key is the view's tile_base plus the tile index
+// inside the view.  hist and partials are the radix sort's scratch.
 // first_row[b]: the row that holds pair b * kDupItems (the row-count scan's aux)
-hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
-                            const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s);
+hipError_t launch_duplicate_sorted(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
+                                   const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
+                                   int tile_bits, uint32_t* hist, uint32_t* partials, uint32_t* out_keys,
+                                   uint32_t* out_vals, hipStream_t s);
 
 hipError_t launch_ranges(const uint32_t* sorted_keys, int64_t K, uint2* ranges, int32_t ntiles, hipStream_t s);
 

@@ -11,7 +11,7 @@ const char* const kNames[kKNumKernels] = {
     "preprocess", "compact", "depth_sort_hist", "depth_sort_scatter", "scan", "duplicate", "tile_sort_hist",
     "tile_sort_scatter", "ranges", "fill", "blend_forward", "blend_backward", "preprocess_backward",
     "color", "rows", "loss", "spatial_order",
-    "grad_segreduce"};
+    "grad_segreduce", "duplicate_hist"};
 
 struct Record {
   int id;

@@ -249,78 +249,72 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[d * nblocks + blockIdx.x] = h[d];
 }
 
-// Stable scatter of one pass; P u32 payload words per key.
-// RB: the widest digit this instantiation handles (its LDS tables are 1 << RB
-// long, so narrow digits keep the footprint, and the occupancy, of their width)
+// LDS of a block's stable scatter: 16-bit per-wave digit counters and one
+// start table (local start while staging, then global minus local start
+// while writing) keep a 9-bit digit at the occupancy of an 8-bit one; the
+// staging planes hold the block's items in (digit, item) order.
+// While the block ranks its items, each wave keeps one 64-bit lane mask per
+// digit (match, [kWaves][1 << RB]); that table may share memory with the
+// staging planes, which are not used until the ranking is done.
+template <int RB>
+struct ScatterLds {
+  uint16_t (*wave_count)[1 << RB];  // [kWaves][1 << RB], zero on entry
+  uint32_t* start;                  // [1 << RB]
+  uint32_t* smem;                   // [kWaves + 1]
+  uint64_t* match;                  // [kWaves][1 << RB], any content on entry
+};
+
+// Orders the LDS accesses of one wave's lanes before and after this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ranks the items of one block by digit and writes them, stably, to
+// scanned_hist[digit * nblocks + chunk] + their rank among the block's items
+// of that digit.  Wave w holds items w * IPT * 64 + it * 64 + lane in
+// my_key[it] / my_val[it]; items at or past nvalid are not written, nor
+// are items whose place would be at or past out_limit (only a histogram
+// that disagrees with the items could put them there).
+// stage_keys / stage_vals[q] hold kBlock * IPT words each.
 template <int P, int IPT, int RB>
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* keys_in, ValPtrs<P> vin,
-                                                               uint32_t* keys_out, ValPtrs<P> vout,
-                                                               const uint32_t* d_count, uint32_t max_count,
-                                                               uint32_t key_bias, int shift, int bits, uint32_t nblocks,
-                                                               const uint32_t* scanned_hist) {
+__device__ inline void rank_stage_write(const uint32_t (&my_key)[IPT], const uint32_t (&my_val)[IPT][P],
+                                        uint32_t nvalid, uint32_t key_bias, int shift, int bits, uint32_t nblocks,
+                                        uint32_t chunk, const uint32_t* scanned_hist, const ScatterLds<RB>& L,
+                                        uint32_t* stage_keys, uint32_t* const (&stage_vals)[P], uint32_t* keys_out,
+                                        const ValPtrs<P>& vout, uint32_t out_limit) {
   constexpr int kItems = kBlock * IPT;
   constexpr int kPerWave = kItems / kWaves;
-  constexpr int kIters = kPerWave / 64;
-  constexpr uint32_t kR = 1u << RB;
-  static_assert(kR <= 2 * kBlock, "two digits per thread");
+  static_assert(kPerWave / 64 == IPT, "one item per lane and iteration");
+  static_assert((1u << RB) <= 2 * kBlock, "two digits per thread");
   static_assert(kItems <= 65535, "per-wave counts and prefixes fit 16 bits");
-  // 16-bit per-wave counters and one start table (local start while staging,
-  // then global minus local start while writing) keep a 9-bit digit at the
-  // occupancy of an 8-bit one
-  __shared__ uint16_t wave_count[kWaves][kR];
-  __shared__ uint32_t start[kR];
-  __shared__ uint32_t stage_keys[kItems];
-  __shared__ uint32_t stage_vals[P][kItems];
-  __shared__ uint32_t smem[kWaves + 1];
-
-  const uint32_t count = item_count(d_count, max_count);
-  const uint32_t chunk = xcd_chunk(blockIdx.x, nblocks);
-  const uint32_t block_base = chunk * kItems;
-  if (block_base >= count) return;  // uniform per block
   const uint32_t radix = 1u << bits, mask = radix - 1u;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
-    for (int w = 0; w < kWaves; ++w) wave_count[w][d] = 0;
-  }
-  __syncthreads();
-
-  const uint32_t wave_base = block_base + wave * kPerWave;
-  uint32_t my_key[kIters], my_rank[kIters], my_val[kIters][P];
-  // every load of the tile is issued before the first one is used
-  for (int it = 0; it < kIters; ++it) {
-    const uint32_t idx = wave_base + it * 64 + lane;
-    const bool valid = idx < count;
-    my_key[it] = valid ? keys_in[idx] : 0u;
-    for (int q = 0; q < P; ++q) my_val[it][q] = valid ? vin.p[q][idx] : 0u;
-  }
-  for (int it = 0; it < kIters; ++it) {
-    const uint32_t idx = wave_base + it * 64 + lane;
-    const bool valid = idx < count;
-    const uint32_t key = my_key[it];
-    const uint32_t digit = ((key - key_bias) >> shift) & mask;
-    // lanes with the same digit: per bit, the ballot of that bit, taken as
-    // is where the lane's bit is 1 and complemented where it is 0 (m is 0 or
-    // all ones), kept as two 32-bit halves
-    const uint64_t vb = __ballot(valid);
-    uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      if (b < bits) {  // uniform
-        const uint32_t bit = (digit >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        const uint32_t m = bit - 1u;
-        plo &= (uint32_t)bal ^ m;
-        phi &= (uint32_t)(bal >> 32) ^ m;
-      }
-    }
-    const uint64_t peers = ((uint64_t)phi << 32) | plo;
+  uint64_t* match = L.match + (size_t)wave * (1u << RB);
+  for (uint32_t d = lane; d < radix; d += 64) match[d] = 0ull;
+  const uint64_t lane_bit = 1ull << lane;
+  uint32_t my_rank[IPT];
+  for (int it = 0; it < IPT; ++it) {
+    const uint32_t e = wave * kPerWave + it * 64 + lane;
+    const bool valid = e < nvalid;
+    const uint32_t digit = ((my_key[it] - key_bias) >> shift) & mask;
+    // lanes with the same digit: each lane sets its bit in its digit's mask,
+    // reads the mask back once every lane has set its bit, and clears it
+    // once every lane has read it
+    wave_sync();
+    if (valid) __hip_atomic_fetch_or(&match[digit], lane_bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    wave_sync();
+    const uint64_t peers = valid ? match[digit] : 0ull;
+    wave_sync();
+    if (valid) match[digit] = 0ull;
     uint32_t rank = 0xFFFFFFFFu;
     if (valid) {
-      const uint32_t before = wave_count[wave][digit];
+      const uint32_t before = L.wave_count[wave][digit];
       rank = before + popc_below(peers);
       // the highest peer lane publishes the new count
       const uint32_t last_lane = 63u - (uint32_t)__builtin_clzll(peers);
-      if (lane == last_lane) wave_count[wave][digit] = (uint16_t)(before + (uint32_t)__builtin_popcountll(peers));
+      if (lane == last_lane) L.wave_count[wave][digit] = (uint16_t)(before + (uint32_t)__builtin_popcountll(peers));
     }
     my_rank[it] = rank;
   }
@@ -332,39 +326,85 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
     const uint32_t d = 2u * threadIdx.x + q;
     if (d < radix) {
       for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = wave_count[w][d];
-        wave_count[w][d] = (uint16_t)dcount[q];
+        const uint32_t c = L.wave_count[w][d];
+        L.wave_count[w][d] = (uint16_t)dcount[q];
         dcount[q] += c;
       }
       gstart[q] = scanned_hist[d * nblocks + chunk];
     }
   }
   uint32_t total;
-  const uint32_t ls = block_exclusive_scan(dcount[0] + dcount[1], smem, total);
+  const uint32_t ls = block_exclusive_scan(dcount[0] + dcount[1], L.smem, total);
   const uint32_t lstart[2] = {ls, ls + dcount[0]};
   for (int q = 0; q < 2; ++q)
-    if (2u * threadIdx.x + q < radix) start[2u * threadIdx.x + q] = lstart[q];
+    if (2u * threadIdx.x + q < radix) L.start[2u * threadIdx.x + q] = lstart[q];
   __syncthreads();
-  for (int it = 0; it < kIters; ++it) {
+  for (int it = 0; it < IPT; ++it) {
     if (my_rank[it] == 0xFFFFFFFFu) continue;
     const uint32_t digit = ((my_key[it] - key_bias) >> shift) & mask;
-    const uint32_t pos = start[digit] + wave_count[wave][digit] + my_rank[it];
+    const uint32_t pos = L.start[digit] + L.wave_count[wave][digit] + my_rank[it];
     stage_keys[pos] = my_key[it];
     for (int q = 0; q < P; ++q) stage_vals[q][pos] = my_val[it][q];
   }
   __syncthreads();
   // item e of the staged block goes to global_start + (e - local_start)
   for (int q = 0; q < 2; ++q)
-    if (2u * threadIdx.x + q < radix) start[2u * threadIdx.x + q] = gstart[q] - lstart[q];
+    if (2u * threadIdx.x + q < radix) L.start[2u * threadIdx.x + q] = gstart[q] - lstart[q];
   __syncthreads();
-  const uint32_t nvalid = min((uint32_t)kItems, count - block_base);
   for (uint32_t e = threadIdx.x; e < nvalid; e += kBlock) {
     const uint32_t key = stage_keys[e];
     const uint32_t digit = ((key - key_bias) >> shift) & mask;
-    const uint32_t dst = start[digit] + e;
+    const uint32_t dst = L.start[digit] + e;
+    if (dst >= out_limit) continue;
     keys_out[dst] = key;
     for (int q = 0; q < P; ++q) vout.p[q][dst] = stage_vals[q][e];
   }
+}
+
+// Stable scatter of one pass; P u32 payload words per key.
+// RB: the widest digit this instantiation handles (its LDS tables are 1 << RB
+// long, so narrow digits keep the footprint, and the occupancy, of their width)
+template <int P, int IPT, int RB>
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* keys_in, ValPtrs<P> vin,
+                                                               uint32_t* keys_out, ValPtrs<P> vout,
+                                                               const uint32_t* d_count, uint32_t max_count,
+                                                               uint32_t key_bias, int shift, int bits, uint32_t nblocks,
+                                                               const uint32_t* scanned_hist) {
+  constexpr int kItems = kBlock * IPT;
+  constexpr int kPerWave = kItems / kWaves;
+  constexpr uint32_t kR = 1u << RB;
+  static_assert(kWaves * kR <= (1 + P) * kItems / 2, "the match tables fit in the staging planes");
+  __shared__ uint16_t wave_count[kWaves][kR];
+  __shared__ uint32_t start[kR];
+  __shared__ uint64_t stage[(1 + P) * kItems / 2];  // keys, then the P value planes
+  __shared__ uint32_t smem[kWaves + 1];
+
+  const uint32_t count = item_count(d_count, max_count);
+  const uint32_t chunk = xcd_chunk(blockIdx.x, nblocks);
+  const uint32_t block_base = chunk * kItems;
+  if (block_base >= count) return;  // uniform per block
+  const uint32_t radix = 1u << bits;
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
+    for (int w = 0; w < kWaves; ++w) wave_count[w][d] = 0;
+  }
+  __syncthreads();
+
+  const uint32_t wave_base = block_base + wave * kPerWave;
+  uint32_t my_key[IPT], my_val[IPT][P];
+  // every load of the tile is issued before the first one is used
+  for (int it = 0; it < IPT; ++it) {
+    const uint32_t idx = wave_base + it * 64 + lane;
+    const bool valid = idx < count;
+    my_key[it] = valid ? keys_in[idx] : 0u;
+    for (int q = 0; q < P; ++q) my_val[it][q] = valid ? vin.p[q][idx] : 0u;
+  }
+  uint32_t* const stage_keys = reinterpret_cast<uint32_t*>(stage);
+  uint32_t* sv[P];
+  for (int q = 0; q < P; ++q) sv[q] = stage_keys + (size_t)(1 + q) * kItems;
+  const ScatterLds<RB> L{wave_count, start, smem, stage};
+  rank_stage_write<P, IPT, RB>(my_key, my_val, min((uint32_t)kItems, count - block_base), key_bias, shift, bits,
+                               nblocks, chunk, scanned_hist, L, stage_keys, sv, keys_out, vout, count);
 }
 
 // ---- compaction of the visible Gaussians (stable, id order) ----------------
@@ -469,15 +509,15 @@ __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4
 }
 
 // ---- duplication: one pair per (Gaussian, covered tile) --------------------
-// Balanced by output: block b owns output slots [b*4096, b*4096 + 4096) -- the
-// same slots as radix block b of the tile sort -- whatever Gaussians they
-// belong to, so the near, large splats at the front of the depth order do not
-// pile up in a few blocks.  Thread t walks the 16 consecutive slots
-// 16t .. 16t+15 starting from a binary search for its first Gaussian; the
-// block stages its (tile, id) pairs in LDS and writes them out coalesced.
-// It also counts the first digit of the tile sort for its slots, which is
-// exactly that sort's first histogram.
-
+// Balanced by output: block b owns the kDupItems output slots from
+// b * kDupItems on -- the items of radix block b of the tile sort's first
+// pass -- whatever Gaussians they belong to, so the near, large splats at the
+// front of the depth order do not pile up in a few blocks.  The duplication
+// is fused with that first pass: a histogram kernel counts each block's
+// first digits from the rows alone, a scan of those counts gives every
+// block's starts, and the duplication block then generates its pairs in
+// LDS, ranks them by the digit and writes them straight to their places
+// after the pass.  The pairs in slot order never go through memory.
 
 struct TileMap {
   int32_t count;                     // views
@@ -542,32 +582,134 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
   }
 }
 
-// Each thread emits 16 consecutive slots: it finds the row of its first slot
-// (the last row whose offset is <= the slot: rows without a kept tile share
-// the next row's offset) and emits that row's tiles, moving to the next
-// non-empty row at its offset.  The row offsets of the block's slots are
-// staged in LDS (up to kDupItems rows; rows beyond come from memory).  The
-// slots are staged in LDS and written coalesced.
-__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_off, const uint32_t* row_g,
-                                                           const uint32_t* row_yc, const uint32_t* first_row,
-                                                           uint32_t R, uint32_t K, TileMap map,
-                                                           int digit_bits, uint32_t nblocks, uint32_t* hist,
-                                                           uint32_t* out_keys, uint32_t* out_vals) {
-  __shared__ uint32_t s_keys[kDupItems + kDupItems / 32];
-  __shared__ uint32_t s_vals[kDupItems + kDupItems / 32];
-  __shared__ uint32_t s_off[kDupItems];  // offsets of the rows that own this block's slots
-  __shared__ uint32_t s_hist[kRadix];
-  __shared__ uint32_t s_first, s_count;
-  const uint32_t o_begin = blockIdx.x * kDupItems;
+// First digit of the tile sort (digit_bits low key bits) for the pairs of
+// each duplication block, from the rows alone: the slots of one row hold
+// consecutive tile keys, so a row's part of a block adds n >> digit_bits to
+// every digit and one to each of the n mod radix digits from its first key's
+// on (cyclically).  One wave per duplication block keeps a difference array
+// over the digits in LDS; hist[d * nblocks + b] = block b's count of digit d.
+constexpr int kDupHistRows = 4;  // rows each lane loads before it counts them
+__global__ __launch_bounds__(kBlock) void dup_hist_kernel(const uint32_t* row_off, const uint32_t* row_g,
+                                                          const uint32_t* row_yc, const uint32_t* first_row,
+                                                          uint32_t R, uint32_t K, TileMap map, int digit_bits,
+                                                          uint32_t nblocks, uint32_t* hist) {
+  __shared__ uint32_t s_diff[kWaves][kRadix + 1];
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t db = blockIdx.x * kWaves + wave;  // this wave's duplication block
+  if (db >= nblocks) return;  // uniform per wave; no block barrier below
+  uint32_t* diff = s_diff[wave];
+  const uint32_t radix = 1u << digit_bits, mask = radix - 1u;
+  const uint32_t o_begin = db * kDupItems;
   const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
-  const uint32_t radix = 1u << digit_bits, dmask = radix - 1u;
-  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) s_hist[d] = 0;
+  for (uint32_t d = lane; d <= radix; d += 64) diff[d] = 0u;
+  // the rows from the one holding the block's first slot to the one holding
+  // the next block's first slot (the row-count scan recorded both)
+  const uint32_t first = first_row[db];
+  const uint32_t last = o_end < K ? first_row[db + 1] : R - 1u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t full = 0u;
+  for (uint32_t r0 = first; r0 <= last; r0 += 64u * kDupHistRows) {
+    uint32_t off[kDupHistRows], next[kDupHistRows], g[kDupHistRows], yc[kDupHistRows];
+#pragma unroll
+    for (int j = 0; j < kDupHistRows; ++j) {  // every load before the first use
+      const uint32_t r = r0 + (uint32_t)j * 64u + lane;
+      const bool in = r <= last;
+      off[j] = in ? row_off[r] : 0u;
+      next[j] = in ? (r + 1u < R ? row_off[r + 1u] : K) : 0u;
+      g[j] = in ? row_g[r] : 0u;
+      yc[j] = in ? row_yc[r] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kDupHistRows; ++j) {
+      const uint32_t a = max(off[j], o_begin), e = min(next[j], o_end);
+      if (e <= a) continue;  // past the block's rows, no kept tile, or none in this block
+      uint32_t tbase, tiles_x;
+      view_of(map, g[j], tbase, tiles_x);
+      const uint32_t key0 = tbase + (yc[j] >> 16) * tiles_x + (yc[j] & 0xFFFFu) + (a - off[j]);
+      const uint32_t n = e - a, rem = n & mask, d0 = key0 & mask;
+      full += n >> digit_bits;
+      if (rem != 0u) {  // digits d0 .. d0 + rem - 1, modulo radix (differences wrap as u32)
+        atomicAdd(&diff[d0], 1u);
+        if (d0 + rem <= radix) {
+          atomicSub(&diff[d0 + rem], 1u);
+        } else {
+          atomicSub(&diff[radix], 1u);
+          atomicAdd(&diff[0], 1u);
+          atomicSub(&diff[d0 + rem - radix], 1u);
+        }
+      }
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) full += __shfl_xor(full, d, 64);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // lane l: digits l * per .. l * per + per - 1, per = ceil(radix / 64) <= 8
+  const uint32_t per = (radix + 63u) / 64u;
+  uint32_t v[8], sum = 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t d = lane * per + (uint32_t)k;
+    v[k] = ((uint32_t)k < per && d < radix) ? diff[d] : 0u;
+    sum += v[k];
+  }
+  uint32_t incl = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= (uint32_t)d) incl += y;
+  }
+  uint32_t run = incl - sum + full;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t d = lane * per + (uint32_t)k;
+    run += v[k];
+    if ((uint32_t)k < per && d < radix) hist[d * nblocks + db] = run;
+  }
+}
+
+// Pairs of one duplication block (logical block chunk = xcd_chunk of the
+// hardware block, so that neighbouring blocks, whose output runs interleave
+// after the pass, share an XCD's L2).  Each thread emits kIptPayload1
+// consecutive slots: it finds the row of its first slot (the last row whose
+// offset is <= the slot: rows without a kept tile share the next row's
+// offset) and emits that row's tiles, moving to the next non-empty row at its
+// offset.  The row offsets of the block's slots are staged in LDS (up to
+// kDupItems rows; rows beyond come from memory), the pairs in LDS in slot
+// order; the waves then take them in slot order and scatter them by the
+// first digit as a radix block does.
+template <int RB>
+__global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row_off, const uint32_t* row_g,
+                                                             const uint32_t* row_yc, const uint32_t* first_row,
+                                                             uint32_t R, uint32_t K, TileMap map, int digit_bits,
+                                                             uint32_t nblocks, const uint32_t* scanned_hist,
+                                                             uint32_t* out_keys, uint32_t* out_vals) {
+  constexpr int kPerWave = kDupItems / kWaves;
+  // pairs in slot order (keys, then ids; one pad word per 32), then the
+  // scatter's match tables and staging planes
+  constexpr int kPadded = kDupItems + kDupItems / 32;
+  static_assert(kPadded % 2 == 0 && kWaves * (1 << RB) <= kPadded, "the match tables fit");
+  __shared__ uint64_t s_kv[kPadded];
+  uint32_t* const s_keys = reinterpret_cast<uint32_t*>(s_kv);
+  uint32_t* const s_vals = s_keys + kPadded;
+  __shared__ uint32_t s_off[kDupItems];  // offsets of the rows that own this block's slots
+  __shared__ uint16_t wave_count[kWaves][1 << RB];
+  __shared__ uint32_t start[1 << RB];
+  __shared__ uint32_t smem[kWaves + 1];
+  __shared__ uint32_t s_first, s_count;
+  const uint32_t chunk = xcd_chunk(blockIdx.x, nblocks);
+  const uint32_t o_begin = chunk * kDupItems;
+  const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
+  const uint32_t radix = 1u << digit_bits;
+  for (uint32_t d = threadIdx.x; d < radix; d += kBlock)
+    for (int w = 0; w < kWaves; ++w) wave_count[w][d] = 0;
   if (threadIdx.x == 0) {
     // the rows that hold this block's pairs run from the row of its first
     // pair to, at most, the row of the next block's first pair (the scan of
     // the row counts recorded both)
-    const uint32_t first = first_row[blockIdx.x];
-    const uint32_t last = o_end < K ? first_row[blockIdx.x + 1] : R - 1u;
+    const uint32_t first = first_row[chunk];
+    const uint32_t last = o_end < K ? first_row[chunk + 1] : R - 1u;
     s_first = first;
     s_count = min(last - first + 1u, (uint32_t)kDupItems);
   }
@@ -602,11 +744,9 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_o
     uint32_t col = (yc & 0xFFFFu) + (o - off_at(r));
     uint32_t next = off_at(r + 1u);
     for (int k = 0; k < kIptPayload1 && o < o_end; ++k) {
-      const uint32_t key = tbase + (yc >> 16) * tiles_x + col;
       const uint32_t e = o - o_begin;
-      s_keys[pad_index(e)] = key;
+      s_keys[pad_index(e)] = tbase + (yc >> 16) * tiles_x + col;
       s_vals[pad_index(e)] = g;
-      atomicAdd(&s_hist[key & dmask], 1u);
       ++o;
       ++col;
       if (o == next && o < o_end) {  // the next row with a kept tile
@@ -623,11 +763,20 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t* row_o
   }
   __syncthreads();
   const uint32_t cnt = o_end - o_begin;
-  for (uint32_t e = threadIdx.x; e < cnt; e += kBlock) {
-    out_keys[o_begin + e] = s_keys[pad_index(e)];
-    out_vals[o_begin + e] = s_vals[pad_index(e)];
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t my_key[kIptPayload1], my_val[kIptPayload1][1];
+  for (int it = 0; it < kIptPayload1; ++it) {
+    const uint32_t e = wave * kPerWave + it * 64 + lane;
+    my_key[it] = e < cnt ? s_keys[pad_index(e)] : 0u;
+    my_val[it][0] = e < cnt ? s_vals[pad_index(e)] : 0u;
   }
-  for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[d * nblocks + blockIdx.x] = s_hist[d];
+  __syncthreads();  // the staging planes reuse s_keys / s_vals
+  uint32_t* const sv[1] = {s_vals};
+  const ScatterLds<RB> L{wave_count, start, smem, s_kv};
+  ValPtrs<1> vout;
+  vout.p[0] = out_vals;
+  rank_stage_write<1, kIptPayload1, RB>(my_key, my_val, cnt, 0u, 0, digit_bits, nblocks, chunk, scanned_hist, L,
+                                        s_keys, sv, out_keys, vout, K);
 }
 
 // ranges[t].x = first index whose key >= t (so ranges[t].y = ranges[t+1].x):
@@ -680,7 +829,7 @@ __global__ __launch_bounds__(kBlock) void fill_u32_but_one_kernel(uint32_t* p, u
 template <int P, int IPT>
 hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                            uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                           bool first_hist_ready, uint32_t key_bias) {
+                           int first_pass, uint32_t key_bias) {
   const int passes = radix_passes(bits);
   const uint32_t nb = (uint32_t)ceil_div(max_count, (int64_t)kBlock * IPT);
   uint32_t* ki = B.keys_a;
@@ -694,7 +843,11 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
   for (int p = 0; p < passes; ++p) {
     const int remaining = bits - shift;
     const int pb = (remaining + (passes - p) - 1) / (passes - p);  // balanced digit widths
-    if (p > 0 || !first_hist_ready) {
+    if (p < first_pass) {  // done by the caller: the keys in *_a are in this pass's order
+      shift += pb;
+      continue;
+    }
+    {
       ProfScope prof(s, hist_id);
       hipLaunchKernelGGL((radix_hist_kernel<IPT>), dim3(nb), dim3(kBlock), 0, s, ki, d_count, (uint32_t)max_count,
                          key_bias, shift, pb, nb, hist);
@@ -808,13 +961,13 @@ int64_t radix_blocks(int64_t max_count, int payload) {
 
 hipError_t launch_radix_sort(const RadixBuffers& B, const uint32_t* d_count, int64_t max_count, int bits,
                              uint32_t* hist, uint32_t* partials, hipStream_t s, int hist_id, int scatter_id,
-                             bool first_hist_ready, uint32_t key_bias) {
-  if (max_count <= 0 || radix_passes(bits) == 0) return hipSuccess;
+                             int first_pass, uint32_t key_bias) {
+  if (max_count <= 0 || radix_passes(bits) <= first_pass) return hipSuccess;
   if (B.payload == 1)
     return radix_sort_impl<1, kIptPayload1>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
-                                            first_hist_ready, key_bias);
+                                            first_pass, key_bias);
   return radix_sort_impl<3, kIptPayload3>(B, d_count, max_count, bits, hist, partials, s, hist_id, scatter_id,
-                                          first_hist_ready, key_bias);
+                                          first_pass, key_bias);
 }
 
 hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, const uint2* rects,
@@ -841,14 +994,14 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
-                            const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
-                            int tile_bits, uint32_t* hist, uint32_t* out_keys, uint32_t* out_vals, hipStream_t s) {
+hipError_t launch_duplicate_sorted(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
+                                   const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
+                                   int tile_bits, uint32_t* hist, uint32_t* partials, uint32_t* out_keys,
+                                   uint32_t* out_vals, hipStream_t s) {
   if (R <= 0 || K <= 0) return hipSuccess;
   const int passes = radix_passes(tile_bits);
   const int first_bits = passes > 0 ? (tile_bits + passes - 1) / passes : 0;  // as launch_radix_sort
   const uint32_t nb = (uint32_t)ceil_div(K, kDupItems);
-  ProfScope prof(s, kKDuplicate);
   TileMap map;
   map.count = b.count;
   map.n = (uint32_t)n;
@@ -856,9 +1009,23 @@ hipError_t launch_duplicate(const uint32_t* row_off, const uint32_t* row_g, cons
     map.tile_base[v] = v < b.count ? b.v[v].tile_base : 0u;
     map.tiles_x[v] = v < b.count ? (uint32_t)b.v[v].tiles_x : 1u;
   }
-  hipLaunchKernelGGL(duplicate_kernel, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row, (uint32_t)R,
-                     (uint32_t)K,
-                     map, first_bits, nb, hist, out_keys, out_vals);
+  {
+    ProfScope prof(s, kKDupHist);
+    hipLaunchKernelGGL(dup_hist_kernel, dim3((unsigned)ceil_div(nb, kWaves)), dim3(kBlock), 0, s, row_off, row_g,
+                       row_yc, first_row, (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist);
+  }
+  hipError_t e = launch_scan(hist, nullptr, nullptr, (int64_t)nb << first_bits, kScanPlain, partials, nullptr, hist, s);
+  if (e != hipSuccess) return e;
+  ProfScope prof(s, kKDuplicate);
+  if (first_bits <= 7)
+    hipLaunchKernelGGL(dup_scatter_kernel<7>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
+                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
+  else if (first_bits == 8)
+    hipLaunchKernelGGL(dup_scatter_kernel<8>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
+                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
+  else
+    hipLaunchKernelGGL(dup_scatter_kernel<kRadixBits>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
+                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
   return hipGetLastError();
 }
 

@@ -130,7 +130,8 @@ KERNELS = {
     "compact": "::compact_kernel(",
     "depth_sort_scatter": "::radix_scatter_kernel<3,",
     "rows": "::rows_kernel(",
-    "duplicate": "::duplicate_kernel(",
+    "duplicate_hist": "::dup_hist_kernel(",
+    "duplicate": "::dup_scatter_kernel<",
     "tile_sort_hist": "::radix_hist_kernel<12>",
     "tile_sort_scatter": "::radix_scatter_kernel<1,",
     "ranges": "::ranges_kernel(",

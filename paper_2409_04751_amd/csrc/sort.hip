@@ -671,14 +671,13 @@ __global__ __launch_bounds__(kBlock) void dup_hist_kernel(const uint32_t* row_of
 
 // Pairs of one duplication block (logical block chunk = xcd_chunk of the
 // hardware block, so that neighbouring blocks, whose output runs interleave
-// after the pass, share an XCD's L2).  Each thread emits kIptPayload1
-// consecutive slots: it finds the row of its first slot (the last row whose
-// offset is <= the slot: rows without a kept tile share the next row's
-// offset) and emits that row's tiles, moving to the next non-empty row at its
-// offset.  The row offsets of the block's slots are staged in LDS (up to
-// kDupItems rows; rows beyond come from memory), the pairs in LDS in slot
-// order; the waves then take them in slot order and scatter them by the
-// first digit as a radix block does.
+// after the pass, share an XCD's L2).  The block's rows (from the one
+// holding its first slot to the one holding the next block's first slot)
+// are dealt to the threads, kDupGenRows at a time per thread with every load
+// issued first; a thread writes the slots of its rows that fall in the block
+// into LDS, in slot order.  The waves then take the pairs in slot order and
+// scatter them by the first digit as a radix block does.
+constexpr int kDupGenRows = 4;
 template <int RB>
 __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row_off, const uint32_t* row_g,
                                                              const uint32_t* row_yc, const uint32_t* first_row,
@@ -693,71 +692,42 @@ __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row
   __shared__ uint64_t s_kv[kPadded];
   uint32_t* const s_keys = reinterpret_cast<uint32_t*>(s_kv);
   uint32_t* const s_vals = s_keys + kPadded;
-  __shared__ uint32_t s_off[kDupItems];  // offsets of the rows that own this block's slots
   __shared__ uint16_t wave_count[kWaves][1 << RB];
   __shared__ uint32_t start[1 << RB];
   __shared__ uint32_t smem[kWaves + 1];
-  __shared__ uint32_t s_first, s_count;
   const uint32_t chunk = xcd_chunk(blockIdx.x, nblocks);
   const uint32_t o_begin = chunk * kDupItems;
   const uint32_t o_end = min(o_begin + (uint32_t)kDupItems, K);
   const uint32_t radix = 1u << digit_bits;
   for (uint32_t d = threadIdx.x; d < radix; d += kBlock)
     for (int w = 0; w < kWaves; ++w) wave_count[w][d] = 0;
-  if (threadIdx.x == 0) {
-    // the rows that hold this block's pairs run from the row of its first
-    // pair to, at most, the row of the next block's first pair (the scan of
-    // the row counts recorded both)
-    const uint32_t first = first_row[chunk];
-    const uint32_t last = o_end < K ? first_row[chunk + 1] : R - 1u;
-    s_first = first;
-    s_count = min(last - first + 1u, (uint32_t)kDupItems);
-  }
-  __syncthreads();
-  const uint32_t first = s_first, m = s_count;
-  for (uint32_t t = threadIdx.x; t < m; t += kBlock) s_off[t] = row_off[first + t];
-  __syncthreads();
-  // offset of row r (K past the last row)
-  auto off_at = [&](uint32_t r) -> uint32_t {
-    return r - first < m ? s_off[r - first] : (r < R ? row_off[r] : K);
-  };
-  uint32_t o = o_begin + threadIdx.x * kIptPayload1;
-  if (o < o_end) {
-    uint32_t r;
-    if (m < (uint32_t)kDupItems || o < off_at(first + m)) {
-      uint32_t lo = 0, hi = m;  // the table covers o
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= o) lo = mid; else hi = mid;
-      }
-      r = first + lo;
-    } else {  // more rows than the table holds (many empty ones): search memory
-      uint32_t lo = first + m - 1u, hi = R;
-      while (hi - lo > 1) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (row_off[mid] <= o) lo = mid; else hi = mid;
-      }
-      r = lo;
+  // the rows that hold this block's pairs run from the row of its first pair
+  // to, at most, the row of the next block's first pair (the scan of the row
+  // counts recorded both)
+  const uint32_t first = first_row[chunk];
+  const uint32_t last = o_end < K ? first_row[chunk + 1] : R - 1u;
+  for (uint32_t r0 = first; r0 <= last; r0 += kBlock * kDupGenRows) {
+    uint32_t off[kDupGenRows], next[kDupGenRows], g[kDupGenRows], yc[kDupGenRows];
+#pragma unroll
+    for (int j = 0; j < kDupGenRows; ++j) {
+      const uint32_t r = r0 + (uint32_t)j * kBlock + threadIdx.x;
+      const bool in = r <= last;
+      off[j] = in ? row_off[r] : 0u;
+      next[j] = in ? (r + 1u < R ? row_off[r + 1u] : K) : 0u;
+      g[j] = in ? row_g[r] : 0u;
+      yc[j] = in ? row_yc[r] : 0u;
     }
-    uint32_t g = row_g[r], yc = row_yc[r], tbase, tiles_x;
-    view_of(map, g, tbase, tiles_x);
-    uint32_t col = (yc & 0xFFFFu) + (o - off_at(r));
-    uint32_t next = off_at(r + 1u);
-    for (int k = 0; k < kIptPayload1 && o < o_end; ++k) {
-      const uint32_t e = o - o_begin;
-      s_keys[pad_index(e)] = tbase + (yc >> 16) * tiles_x + col;
-      s_vals[pad_index(e)] = g;
-      ++o;
-      ++col;
-      if (o == next && o < o_end) {  // the next row with a kept tile
-        do {
-          ++r;
-          next = off_at(r + 1u);
-        } while (next == o);
-        g = row_g[r];
-        yc = row_yc[r];
-        view_of(map, g, tbase, tiles_x);
-        col = yc & 0xFFFFu;
+#pragma unroll
+    for (int j = 0; j < kDupGenRows; ++j) {
+      const uint32_t a = max(off[j], o_begin), e = min(next[j], o_end);
+      if (e <= a) continue;  // past the block's rows, no kept tile, or none in this block
+      uint32_t tbase, tiles_x;
+      view_of(map, g[j], tbase, tiles_x);
+      const uint32_t key0 = tbase + (yc[j] >> 16) * tiles_x + (yc[j] & 0xFFFFu) - off[j];
+      for (uint32_t o = a; o < e; ++o) {
+        const uint32_t el = pad_index(o - o_begin);
+        s_keys[el] = key0 + o;
+        s_vals[el] = g[j];
       }
     }
   }
@@ -770,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row
     my_key[it] = e < cnt ? s_keys[pad_index(e)] : 0u;
     my_val[it][0] = e < cnt ? s_vals[pad_index(e)] : 0u;
   }
-  __syncthreads();  // the staging planes reuse s_keys / s_vals
+  __syncthreads();  // the match tables and staging planes reuse s_kv
   uint32_t* const sv[1] = {s_vals};
   const ScatterLds<RB> L{wave_count, start, smem, s_kv};
   ValPtrs<1> vout;

@@ -37,8 +37,7 @@ struct BlendArgs {
   const float4* splats;
   const float4* colors;
   float* pixel_T;
-  uint32_t* pixel_last;
-  int save;
+  uint32_t* pixel_last;  // written only by the forward that saves the pixel state
   BatchOut out;
   ViewBatch batch;
 };
@@ -68,7 +67,8 @@ __device__ inline float exponent2(const float4& a, const float4& b, float fi, fl
 // below the transmittance floor (which makes it done) adds w = 0 and keeps
 // T and last, exactly as if it had been skipped.  The blend backward's
 // re-sweep runs the same arithmetic, so T and last agree bit for bit.
-template <bool kColorAcc>
+// kLast: also track last (a forward that does not save it skips that).
+template <bool kColorAcc, bool kLast = true>
 __device__ inline void front_step(float fi, float fj, const float4& ga, const float4& gb, const float2& gc,
                                   uint32_t index, bool& done, float& T, uint32_t& last, float& C0, float& C1,
                                   float& C2) {
@@ -87,7 +87,7 @@ __device__ inline void front_step(float fi, float fj, const float4& ga, const fl
     C2 = __builtin_fmaf(gc.y, w, C2);
   }
   T = blend ? tn : T;
-  last = blend ? index + 1u : last;
+  if (kLast) last = blend ? index + 1u : last;
 }
 
 // The forward runs ONE wave per tile of every view of the batch (tiles are
@@ -115,6 +115,9 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// SAVE: the per-pixel final transmittance and last contributor are stored
+// (only then is the last contributor tracked).
+template <bool SAVE>
 __device__ inline void forward_tile(const BlendArgs& a, FwdStage& S, uint32_t gtile, uint32_t lane) {
   int vi = 0;
   while (vi + 1 < a.batch.count && gtile >= a.batch.v[vi + 1].tile_base) ++vi;
@@ -164,7 +167,8 @@ __device__ inline void forward_tile(const BlendArgs& a, FwdStage& S, uint32_t gt
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        front_step<true>(fi, fj[q], ga, gb, gc, first + (uint32_t)e, done[q], T[q], last[q], C0[q], C1[q], C2[q]);
+        front_step<true, SAVE>(fi, fj[q], ga, gb, gc, first + (uint32_t)e, done[q], T[q], last[q], C0[q], C1[q],
+                               C2[q]);
       if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
     }
     wave_lds_sync();  // this chunk's reads complete before the next staging overwrites it
@@ -178,13 +182,14 @@ __device__ inline void forward_tile(const BlendArgs& a, FwdStage& S, uint32_t gt
     out[p] = __builtin_fmaf(T[q], vp.bg[0], C0[q]);
     out[hw + p] = __builtin_fmaf(T[q], vp.bg[1], C1[q]);
     out[2 * hw + p] = __builtin_fmaf(T[q], vp.bg[2], C2[q]);
-    if (a.save) {
+    if (SAVE) {
       a.pixel_T[vp.pixel_base + p] = T[q];
       a.pixel_last[vp.pixel_base + p] = last[q];
     }
   }
 }
 
+template <bool SAVE>
 __global__ __launch_bounds__(kFwdThreads) void blend_forward_kernel(BlendArgs a) {
   __shared__ FwdStage stage[kFwdWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(kFwdThreads) void blend_forward_kernel(BlendArgs a)
   // consecutive tiles in one block, neighbouring blocks on one XCD (tiles
   // that gather the same splats share an L2)
   const uint32_t gtile = xcd_chunk(blockIdx.x, gridDim.x) * kFwdWaves + wave;
-  if (gtile < a.total_tiles) forward_tile(a, S, gtile, lane);
+  if (gtile < a.total_tiles) forward_tile<SAVE>(a, S, gtile, lane);
 }
 
 
@@ -642,13 +647,15 @@ hipError_t launch_blend_forward(const ViewBatch& b, int64_t total_tiles, const u
   a.colors = colors;
   a.pixel_T = pixel_T;
   a.pixel_last = pixel_last;
-  a.save = save ? 1 : 0;
   a.out = out;
   a.batch = b;
   a.total_tiles = (uint32_t)total_tiles;
   ProfScope prof(s, kKBlendForward);
-  hipLaunchKernelGGL(blend_forward_kernel, dim3((unsigned)ceil_div(total_tiles, kFwdWaves)), dim3(kFwdThreads), 0, s,
-                     a);
+  const dim3 grid((unsigned)ceil_div(total_tiles, kFwdWaves));
+  if (save)
+    hipLaunchKernelGGL(blend_forward_kernel<true>, grid, dim3(kFwdThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(blend_forward_kernel<false>, grid, dim3(kFwdThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -283,9 +283,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   uint32_t* partials = U(L.partials);
   uint32_t* hist = U(L.hist);
 
-  HIP_TRY(launch_clear_but_one(counters, kNumCounters, kCountFlags, flags, s), "clear counters, store flags");
   const bool tight = (flags & FGS_RECT_BINNING) == 0;
-  HIP_TRY(launch_preprocess(*g, b, tight, ws, L, s), "preprocess");
+  HIP_TRY(launch_preprocess(*g, b, tight, flags, ws, L, s), "preprocess");  // also clears the counters
   // stable compaction of the visible (view, Gaussian) entries; offsets holds
   // their positions until the tile-count scan reuses it.  The compaction
   // also sums K and finds the depth-key range, so one read-back gives every

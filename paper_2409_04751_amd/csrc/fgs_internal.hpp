@@ -181,9 +181,10 @@ struct BatchOut {
 // ---- launchers (each returns hipSuccess or the first HIP error) ----------
 
 // Preprocess: writes splats, depth_keys, tiles, rects, radii, and seeds the
-// depth sort with (key, id) in dkeys_a / dvals_a.
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, char* ws, const Layout& L,
-                             hipStream_t s);
+// depth sort with (key, id) in dkeys_a / dvals_a.  Also clears the device
+// counters, storing `flags` in their flags slot.
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, uint32_t flags, char* ws,
+                             const Layout& L, hipStream_t s);
 
 // Exclusive scan of u32 values read as `mode` says; the item count is
 // *d_count if d_count is non-null (device), capped by max_count (host).

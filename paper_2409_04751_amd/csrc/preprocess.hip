@@ -39,8 +39,17 @@ struct PreArgs {
   uint32_t* block_tiles;  // [view][block] tiles touched (multi-view only)
   int tight;              // count only the tiles the alpha >= 1/255 ellipse reaches
   uint32_t* rowrange;     // tight: [entry] first | (last + 1) << 16 of the rows with a kept tile
+  uint32_t* counters;     // cleared by the first block, with the flags stored (no launch of its own)
+  uint32_t flags;
   ViewBatch batch;
 };
+
+// The forward's device counters start at zero, the flags slot holding the
+// call's flags; the first kernel of the forward writes them.
+__device__ inline void clear_counters(const PreArgs& a) {
+  if (blockIdx.x == 0 && threadIdx.x < (uint32_t)kNumCounters)
+    a.counters[threadIdx.x] = threadIdx.x == (uint32_t)kCountFlags ? a.flags : 0u;
+}
 
 struct Geometry {
   double pc[3];
@@ -385,6 +394,7 @@ __device__ inline uint32_t entry_color(const PreArgs& a, uint32_t vi, uint32_t i
 template <int DEG, int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_fused_kernel(PreArgs a) {
   __shared__ RowCountLds rows_lds[kBlock / 64];
+  clear_counters(a);
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i, i < a.n, rows_lds[threadIdx.x >> 6]);
   if (ntiles == 0) return;
@@ -408,6 +418,7 @@ __device__ inline void entry_of_block(uint32_t nviews, uint32_t& vi, uint32_t& i
 template <int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_kernel(PreArgs a) {
   __shared__ RowCountLds rows_lds[kBlock / 64];
+  clear_counters(a);
   uint32_t vi, i;
   entry_of_block((uint32_t)a.batch.count, vi, i);
   entry_geometry<MC>(a, vi, i, (size_t)vi * a.n + i, i < a.n, rows_lds[threadIdx.x >> 6]);
@@ -657,10 +668,13 @@ __global__ __launch_bounds__(kBlock) void backward_fused_kernel(PreBwdArgs a) {
 
 }  // namespace
 
-hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, char* ws, const Layout& L,
-                             hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
+hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, uint32_t flags, char* ws,
+                             const Layout& L, hipStream_t s) {
+  uint32_t* const counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+  if (g.n == 0) return launch_clear_but_one(counters, kNumCounters, kCountFlags, flags, s);
   PreArgs a;
+  a.counters = counters;
+  a.flags = flags;
   a.means = g.means;
   a.scales = g.scales;
   a.quats = g.quats;

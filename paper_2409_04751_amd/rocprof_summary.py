@@ -135,7 +135,7 @@ KERNELS = {
     "tile_sort_hist": "::radix_hist_kernel<12>",
     "tile_sort_scatter": "::radix_scatter_kernel<1,",
     "ranges": "::ranges_kernel(",
-    "blend_forward": "::blend_forward_kernel(",
+    "blend_forward": "::blend_forward_kernel<false>",
     "blend_backward": "::blend_backward_kernel<false>",
     "preprocess_backward": "::backward_fused_kernel<",
     "loss": "::l1_",

@@ -98,6 +98,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   // order keeps them at a measured good offset there
   L.drx_b = take(nv * 4);
   L.dry_b = take(nv * 4);
+  L.block_kept = take((size_t)ceil_div((int64_t)nn, kBlock) * 4);  // last: moves no other array
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
@@ -289,9 +290,13 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   // their positions until the tile-count scan reuses it.  The compaction
   // also sums K and finds the depth-key range, so one read-back gives every
   // later stage its exact size.
-  HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible, U(L.offsets),
-                      s),
-          "visibility scan");
+  if (nviews == 1 && ceil_div(n, kBlock) <= kMaxPartsScan)  // the preprocess counted each block's kept entries
+    HIP_TRY(launch_flag_scan_from_parts(U(L.tiles), nv, U(L.block_kept), counters + kCountVisible, U(L.offsets), s),
+            "visibility scan");
+  else
+    HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible,
+                        U(L.offsets), s),
+            "visibility scan");
   HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects),
                          U(L.rowrange), tight, U(L.offsets), nv, U(L.dkeys_a),
                          U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters, reinterpret_cast<uint4*>(hist), s),

@@ -143,6 +143,7 @@ struct Layout {
   // the rows' Gaussian and (y << 16 | first column) live in tvals_b / tkeys_b
   // until the tile sort needs them
   size_t hist, partials, block_tiles;
+  size_t block_kept;  // one view: [ceil(n / 256)] entries each preprocess block kept
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
   int tile_bits = 0, tile_passes = 0;
   size_t tile_keys_final, tile_ids_final;
@@ -197,6 +198,13 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
 hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_t* d_count, int64_t max_count,
                        int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s,
                        uint32_t* aux = nullptr, uint32_t aux_block = 0);
+// The same exclusive scan of flags (in_a[i] != 0, max_count items) when the
+// producer already left the flag count of every kBlock items in parts (the
+// preprocess's kept counts): one launch instead of two.  Returns
+// hipErrorInvalidValue (nothing launched) beyond kMaxPartsScan parts.
+constexpr int64_t kMaxPartsScan = 16384;
+hipError_t launch_flag_scan_from_parts(const uint32_t* in_a, int64_t max_count, const uint32_t* parts,
+                                       uint32_t* total, uint32_t* out, hipStream_t s);
 
 // Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
 // bits [0, bits), same item-count convention as launch_scan.  Passes before

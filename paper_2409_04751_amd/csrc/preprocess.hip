@@ -39,6 +39,7 @@ struct PreArgs {
   uint32_t* block_tiles;  // [view][block] tiles touched (multi-view only)
   int tight;              // count only the tiles the alpha >= 1/255 ellipse reaches
   uint32_t* rowrange;     // tight: [entry] first | (last + 1) << 16 of the rows with a kept tile
+  uint32_t* block_kept;   // one view: [block] entries the block kept (tile count > 0 after the colour)
   uint32_t* counters;     // cleared by the first block, with the flags stored (no launch of its own)
   uint32_t flags;
   ViewBatch batch;
@@ -395,12 +396,22 @@ template <int DEG, int MC>
 __global__ __launch_bounds__(kBlock) void preprocess_fused_kernel(PreArgs a) {
   __shared__ RowCountLds rows_lds[kBlock / 64];
   clear_counters(a);
+  __shared__ uint32_t s_kept;
+  if (threadIdx.x == 0) s_kept = 0u;
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i, i < a.n, rows_lds[threadIdx.x >> 6]);
-  if (ntiles == 0) return;
-  float c[48];
-  load_sh<DEG>(a.sh, i, a.n, c);
-  entry_color<DEG>(a, 0u, i, i, c, ntiles);
+  uint32_t ntiles = entry_geometry<MC>(a, 0u, i, i, i < a.n, rows_lds[threadIdx.x >> 6]);
+  if (ntiles != 0) {
+    float c[48];
+    load_sh<DEG>(a.sh, i, a.n, c);
+    ntiles = entry_color<DEG>(a, 0u, i, i, c, ntiles);
+  }
+  // the block's count of kept entries: the compaction's scan adds these up
+  // instead of counting the tile counts again
+  const uint64_t kept = __ballot(ntiles != 0);
+  __syncthreads();
+  if ((threadIdx.x & 63u) == 0u && kept != 0ull) atomicAdd(&s_kept, (uint32_t)__builtin_popcountll(kept));
+  __syncthreads();
+  if (threadIdx.x == 0) a.block_kept[blockIdx.x] = s_kept;
 }
 
 // Batches: the geometry and the colour run as two kernels over a grid of
@@ -675,6 +686,7 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
   PreArgs a;
   a.counters = counters;
   a.flags = flags;
+  a.block_kept = reinterpret_cast<uint32_t*>(ws + L.block_kept);
   a.means = g.means;
   a.scales = g.scales;
   a.quats = g.quats;

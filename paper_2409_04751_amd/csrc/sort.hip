@@ -171,17 +171,27 @@ __device__ inline void load16(const ScanIn& in, uint32_t idx, uint32_t count, ui
 // FUSED: partials holds the block sums and each block adds up those before
 // it; otherwise partials already holds their exclusive scan.  The last block
 // writes the grand total (FUSED only).
+// parts_per_block: partials holds that many sums per block of items (the
+// producer's finer block sums), FUSED only.
 template <int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(ScanIn in, uint32_t* out, const uint32_t* d_count,
                                                             uint32_t max_count, const uint32_t* partials,
-                                                            uint32_t* total_out) {
+                                                            uint32_t* total_out, uint32_t parts_per_block = 1u) {
   static_assert(kItemsPerThread == 16, "load16");
   __shared__ uint32_t smem[kWaves + 1];
   const uint32_t count = item_count(d_count, max_count);
   uint32_t block_off;
   if (FUSED) {
-    uint32_t acc = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) acc += partials[b];
+    // four independent sums, so that a thread's loads are in flight together
+    uint32_t a4[4] = {0u, 0u, 0u, 0u};
+    const uint32_t before = blockIdx.x * parts_per_block;
+    uint32_t b = threadIdx.x;
+    for (; b + 3u * kBlock < before; b += 4u * kBlock) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a4[q] += partials[b + (uint32_t)q * kBlock];
+    }
+    for (; b < before; b += kBlock) a4[0] += partials[b];
+    const uint32_t acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     uint32_t tot;
     block_exclusive_scan(acc, smem, tot);
     block_off = tot;
@@ -920,6 +930,19 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
     default: FGS_APPLY(kScanPlain) break;
   }
 #undef FGS_APPLY
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_scan_from_parts(const uint32_t* in_a, int64_t max_count, const uint32_t* parts,
+                                       uint32_t* total, uint32_t* out, hipStream_t s) {
+  static_assert(kItemsPerBlock % kBlock == 0, "whole parts per scan block");
+  if (max_count <= 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
+  if (ceil_div(max_count, kBlock) > kMaxPartsScan) return hipErrorInvalidValue;
+  const uint32_t nb = (uint32_t)ceil_div(max_count, kItemsPerBlock);
+  const ScanIn in{in_a, nullptr, nullptr, 0u};
+  ProfScope prof(s, kKScan);
+  hipLaunchKernelGGL((scan_apply_kernel<kScanFlag, true>), dim3(nb), dim3(kBlock), 0, s, in, out, nullptr,
+                     (uint32_t)max_count, parts, total, (uint32_t)(kItemsPerBlock / kBlock));
   return hipGetLastError();
 }
 

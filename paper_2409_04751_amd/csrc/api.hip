@@ -98,7 +98,9 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   // order keeps them at a measured good offset there
   L.drx_b = take(nv * 4);
   L.dry_b = take(nv * 4);
-  L.block_kept = take((size_t)ceil_div((int64_t)nn, kBlock) * 4);  // last: moves no other array
+  // last: these move no other array
+  L.block_kept = take((size_t)ceil_div((int64_t)nn, kBlock) * 4);
+  L.block_pairs = take((size_t)(kk / kRowsPerBlock + 1) * 4);
   L.bytes = off;
   L.tile_bits = bits_for(L.total_tiles);
   L.tile_passes = radix_passes(L.tile_bits);
@@ -291,7 +293,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   // also sums K and finds the depth-key range, so one read-back gives every
   // later stage its exact size.
   if (nviews == 1 && ceil_div(n, kBlock) <= kMaxPartsScan)  // the preprocess counted each block's kept entries
-    HIP_TRY(launch_flag_scan_from_parts(U(L.tiles), nv, U(L.block_kept), counters + kCountVisible, U(L.offsets), s),
+    HIP_TRY(launch_scan_from_parts(U(L.tiles), kScanFlag, nv, U(L.block_kept), kBlock, counters + kCountVisible,
+                                   U(L.offsets), s),
             "visibility scan");
   else
     HIP_TRY(launch_scan(U(L.tiles), nullptr, nullptr, nv, kScanFlag, partials, counters + kCountVisible,
@@ -355,11 +358,17 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
                       kRowsPerBlock),
           "row scan");
   HIP_TRY(launch_rows(d_ids, d_rx, d_ry, U(L.offsets), U(L.block_first), V, R,
-                      reinterpret_cast<const float4*>(ws + L.splats), tight, U(L.row_off), row_g, row_yc, s),
+                      reinterpret_cast<const float4*>(ws + L.splats), tight, U(L.row_off), row_g, row_yc,
+                      U(L.block_pairs), s),
           "rows");
-  HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s,
-                      U(L.block_first), kDupItems),
-          "row count scan");
+  if (ceil_div(R, kRowsPerBlock) <= kMaxPartsScan)  // the rows kernel summed each block's counts
+    HIP_TRY(launch_scan_from_parts(U(L.row_off), kScanPlain, R, U(L.block_pairs), kRowsPerBlock, counters + kCountK,
+                                   U(L.row_off), s, U(L.block_first), kDupItems),
+            "row count scan");
+  else
+    HIP_TRY(launch_scan(U(L.row_off), nullptr, nullptr, R, kScanPlain, partials, counters + kCountK, U(L.row_off), s,
+                        U(L.block_first), kDupItems),
+            "row count scan");
   // the pairs come out of the duplication in the order of the tile sort's
   // first pass (into *_a: the rows still sit in *_b); the sort does the rest
   HIP_TRY(launch_duplicate_sorted(U(L.row_off), row_g, row_yc, U(L.block_first), R, K, b, n, L.tile_bits, hist,

@@ -144,6 +144,7 @@ struct Layout {
   // until the tile sort needs them
   size_t hist, partials, block_tiles;
   size_t block_kept;  // one view: [ceil(n / 256)] entries each preprocess block kept
+  size_t block_pairs;  // [kcap / kRowsPerBlock + 1]: pairs of each rows-kernel block
   size_t tkeys_a, tvals_a, tkeys_b, tvals_b;
   int tile_bits = 0, tile_passes = 0;
   size_t tile_keys_final, tile_ids_final;
@@ -198,13 +199,15 @@ hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool ti
 hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_t* d_count, int64_t max_count,
                        int mode, uint32_t* partials, uint32_t* total, uint32_t* out, hipStream_t s,
                        uint32_t* aux = nullptr, uint32_t aux_block = 0);
-// The same exclusive scan of flags (in_a[i] != 0, max_count items) when the
-// producer already left the flag count of every kBlock items in parts (the
-// preprocess's kept counts): one launch instead of two.  Returns
-// hipErrorInvalidValue (nothing launched) beyond kMaxPartsScan parts.
+// The same exclusive scan (mode kScanFlag or kScanPlain, max_count items,
+// aux as launch_scan) when the producer already left the sum of every
+// part_items consecutive items in parts (part_items divides kItemsPerBlock):
+// one launch instead of two.  Returns hipErrorInvalidValue (nothing
+// launched) beyond kMaxPartsScan parts.
 constexpr int64_t kMaxPartsScan = 16384;
-hipError_t launch_flag_scan_from_parts(const uint32_t* in_a, int64_t max_count, const uint32_t* parts,
-                                       uint32_t* total, uint32_t* out, hipStream_t s);
+hipError_t launch_scan_from_parts(const uint32_t* in_a, int mode, int64_t max_count, const uint32_t* parts,
+                                  int64_t part_items, uint32_t* total, uint32_t* out, hipStream_t s,
+                                  uint32_t* aux = nullptr, uint32_t aux_block = 0);
 
 // Stable LSD radix sort of u32 keys with B.payload u32 value planes on key
 // bits [0, bits), same item-count convention as launch_scan.  Passes before
@@ -239,9 +242,10 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
 // whole rect row -- as row_cnt[t] = c1 - c0, row_g[t] = Gaussian (entry) id,
 // row_yc[t] = y << 16 | c0.
 // first_entry[b]: the entry that holds row b * kRowsPerBlock (the row scan's aux)
+// block_pairs[b]: the kept tiles of the rows of block b (kRowsPerBlock rows).
 hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base,
                        const uint32_t* first_entry, int64_t V, int64_t R, const float4* splats, bool tight,
-                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, hipStream_t s);
+                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, uint32_t* block_pairs, hipStream_t s);
 
 // One (tile, id) pair per kept tile of each row, at the row's offset
 // row_off[t] (exclusive scan of the counts) in depth order, K pairs in

@@ -553,9 +553,9 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
                                                       const uint32_t* row_base, const uint32_t* first_entry,
                                                       uint32_t V, uint32_t R,
                                                       const float4* splats, int tight, uint32_t* row_cnt,
-                                                      uint32_t* row_g, uint32_t* row_yc) {
+                                                      uint32_t* row_g, uint32_t* row_yc, uint32_t* block_pairs) {
   __shared__ uint32_t s_base[kRowsPerBlock];
-  __shared__ uint32_t s_first, s_count;
+  __shared__ uint32_t s_first, s_count, s_sum;
   const uint32_t t0 = blockIdx.x * kRowsPerBlock;
   const uint32_t t1 = min(t0 + (uint32_t)kRowsPerBlock, R);
   if (threadIdx.x == 0) {
@@ -566,11 +566,13 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
     const uint32_t last = t1 < R ? first_entry[blockIdx.x + 1] : V - 1u;
     s_first = first;
     s_count = min(last - first + 1u, (uint32_t)kRowsPerBlock);
+    s_sum = 0u;
   }
   __syncthreads();
   const uint32_t first = s_first, m = s_count;
   for (uint32_t k = threadIdx.x; k < m; k += kBlock) s_base[k] = row_base[first + k];
   __syncthreads();
+  uint32_t kept = 0u;
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const uint32_t t = t0 + (uint32_t)q * kBlock + threadIdx.x;
@@ -589,7 +591,14 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const uint32_t* ids, const
     row_cnt[t] = (uint32_t)(c1 - c0);
     row_g[t] = g;
     row_yc[t] = ((uint32_t)y << 16) | (uint32_t)c0;
+    kept += (uint32_t)(c1 - c0);
   }
+  // the block's pair count, which the row-count scan adds up instead of
+  // reading the counts twice
+  for (int d = 32; d >= 1; d >>= 1) kept += __shfl_xor(kept, d, 64);
+  if ((threadIdx.x & 63u) == 0u) atomicAdd(&s_sum, kept);
+  __syncthreads();
+  if (threadIdx.x == 0) block_pairs[blockIdx.x] = s_sum;
 }
 
 // First digit of the tile sort (digit_bits low key bits) for the pairs of
@@ -933,16 +942,23 @@ hipError_t launch_scan(const uint32_t* in_a, const uint32_t* in_b, const uint32_
   return hipGetLastError();
 }
 
-hipError_t launch_flag_scan_from_parts(const uint32_t* in_a, int64_t max_count, const uint32_t* parts,
-                                       uint32_t* total, uint32_t* out, hipStream_t s) {
-  static_assert(kItemsPerBlock % kBlock == 0, "whole parts per scan block");
+hipError_t launch_scan_from_parts(const uint32_t* in_a, int mode, int64_t max_count, const uint32_t* parts,
+                                  int64_t part_items, uint32_t* total, uint32_t* out, hipStream_t s, uint32_t* aux,
+                                  uint32_t aux_block) {
   if (max_count <= 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
-  if (ceil_div(max_count, kBlock) > kMaxPartsScan) return hipErrorInvalidValue;
+  if (part_items <= 0 || kItemsPerBlock % part_items != 0 || ceil_div(max_count, part_items) > kMaxPartsScan ||
+      (mode != kScanFlag && mode != kScanPlain) || (aux && aux_block == 0))
+    return hipErrorInvalidValue;
   const uint32_t nb = (uint32_t)ceil_div(max_count, kItemsPerBlock);
-  const ScanIn in{in_a, nullptr, nullptr, 0u};
+  const uint32_t per = (uint32_t)(kItemsPerBlock / part_items);
+  const ScanIn in{in_a, nullptr, aux, aux_block};
   ProfScope prof(s, kKScan);
-  hipLaunchKernelGGL((scan_apply_kernel<kScanFlag, true>), dim3(nb), dim3(kBlock), 0, s, in, out, nullptr,
-                     (uint32_t)max_count, parts, total, (uint32_t)(kItemsPerBlock / kBlock));
+  if (mode == kScanFlag)
+    hipLaunchKernelGGL((scan_apply_kernel<kScanFlag, true>), dim3(nb), dim3(kBlock), 0, s, in, out, nullptr,
+                       (uint32_t)max_count, parts, total, per);
+  else
+    hipLaunchKernelGGL((scan_apply_kernel<kScanPlain, true>), dim3(nb), dim3(kBlock), 0, s, in, out, nullptr,
+                       (uint32_t)max_count, parts, total, per);
   return hipGetLastError();
 }
 
@@ -978,12 +994,12 @@ hipError_t launch_compact(const uint32_t* tiles, const uint32_t* depth_keys, con
 
 hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* ry, const uint32_t* row_base,
                        const uint32_t* first_entry, int64_t V, int64_t R, const float4* splats, bool tight,
-                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, hipStream_t s) {
+                       uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, uint32_t* block_pairs, hipStream_t s) {
   if (V <= 0 || R <= 0) return hipSuccess;
   ProfScope prof(s, kKRows);
   hipLaunchKernelGGL(rows_kernel, dim3((unsigned)ceil_div(R, kRowsPerBlock)), dim3(kBlock), 0, s, ids, rx, ry, row_base,
                      first_entry,
-                     (uint32_t)V, (uint32_t)R, splats, tight ? 1 : 0, row_cnt, row_g, row_yc);
+                     (uint32_t)V, (uint32_t)R, splats, tight ? 1 : 0, row_cnt, row_g, row_yc, block_pairs);
   return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ Layout make_layout(int64_t n, int32_t nviews, const int32_t* widths, const int32
   L.pixel_last = take((size_t)L.total_pixels * 4);
   L.block_tiles = take((size_t)ceil_div((int64_t)nn, kBlock) * nviews * 4);
   const int64_t kk = kcap > 0 ? kcap : 1;
-  const int64_t nb_max = std::max(radix_blocks((int64_t)nv, 3), radix_blocks(kk, 1));
+  const int64_t nb_max = std::max({radix_blocks((int64_t)nv, 3), radix_blocks(kk, 1), ceil_div(kk, kDupItems)});
   // radix histograms; before the depth sort also the compaction's per-block
   // stats (one uint4 per 256 entries)
   L.hist = take(std::max((size_t)nb_max * kRadix * 4, (size_t)ceil_div((int64_t)nv, kBlock) * 32));

@@ -50,8 +50,11 @@ enum ScanMode {
   kScanRows = 4,      // row count of the rect (in_a[i] = x0 | y0 << 16, in_b[i] = x1 | y1 << 16)
 };
 
-// Output slots (pairs) per duplication block, rows per rows-kernel block.
-constexpr int kDupItems = kBlock * kIptPayload1;
+// Output slots (pairs) per duplication block (the duplication is also the
+// tile sort's first radix pass, with blocks of its own size), rows per
+// rows-kernel block.
+constexpr int kDupIpt = 8;
+constexpr int kDupItems = kBlock * kDupIpt;
 constexpr int kRowsPerThread = 4;
 constexpr int kRowsPerBlock = kBlock * kRowsPerThread;
 

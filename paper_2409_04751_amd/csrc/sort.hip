@@ -753,8 +753,8 @@ __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row
   __syncthreads();
   const uint32_t cnt = o_end - o_begin;
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t my_key[kIptPayload1], my_val[kIptPayload1][1];
-  for (int it = 0; it < kIptPayload1; ++it) {
+  uint32_t my_key[kDupIpt], my_val[kDupIpt][1];
+  for (int it = 0; it < kDupIpt; ++it) {
     const uint32_t e = wave * kPerWave + it * 64 + lane;
     my_key[it] = e < cnt ? s_keys[pad_index(e)] : 0u;
     my_val[it][0] = e < cnt ? s_vals[pad_index(e)] : 0u;
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row
   const ScatterLds<RB> L{wave_count, start, smem, s_kv};
   ValPtrs<1> vout;
   vout.p[0] = out_vals;
-  rank_stage_write<1, kIptPayload1, RB>(my_key, my_val, cnt, 0u, 0, digit_bits, nblocks, chunk, scanned_hist, L,
+  rank_stage_write<1, kDupIpt, RB>(my_key, my_val, cnt, 0u, 0, digit_bits, nblocks, chunk, scanned_hist, L,
                                         s_keys, sv, out_keys, vout, K);
 }
 

@@ -374,7 +374,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   HIP_TRY(launch_duplicate_sorted(U(L.row_off), row_g, row_yc, U(L.block_first), R, K, b, n, L.tile_bits, hist,
                                   partials, U(L.tkeys_a), U(L.tvals_a), s),
           "duplicate");
-  RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr}};
+  RadixBuffers TB{1, U(L.tkeys_a), U(L.tkeys_b), {U(L.tvals_a), nullptr, nullptr}, {U(L.tvals_b), nullptr, nullptr},
+                  tile_keys16(L.tile_bits)};
   HIP_TRY(launch_radix_sort(TB, nullptr, K, L.tile_bits, hist, partials, s, kKTileHist, kKTileScatter, 1),
           "tile sort");
   uint2* ranges = reinterpret_cast<uint2*>(ws + L.ranges);

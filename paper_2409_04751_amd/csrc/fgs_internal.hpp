@@ -65,6 +65,9 @@ struct RadixBuffers {
   uint32_t* keys_b;
   uint32_t* vals_a[3];
   uint32_t* vals_b[3];
+  // payload 1: keys_a holds uint16_t keys for the first pass that runs (the
+  // duplication's output, tile_keys16); every pass writes uint32_t keys
+  bool keys16 = false;
 };
 
 // Kernels known to the event profiler (fgs_profile_*).
@@ -250,13 +253,18 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
                        const uint32_t* first_entry, int64_t V, int64_t R, const float4* splats, bool tight,
                        uint32_t* row_cnt, uint32_t* row_g, uint32_t* row_yc, uint32_t* block_pairs, hipStream_t s);
 
+// Whether the duplication leaves its keys as uint16_t for the tile sort's
+// second pass: two passes (the first one fused) over ids that fit 16 bits.
+bool tile_keys16(int tile_bits);
+
 // One (tile, id) pair per kept tile of each row, at the row's offset
 // row_off[t] (exclusive scan of the counts) in depth order, K pairs in
 // total, put through the first pass of the tile sort (the tile_bits-bit
 // sort launch_radix_sort would do, first digit) on the way: the pairs land
 // in out_keys / out_vals in that pass's order.  Ids are view-major (view * n
 // + Gaussian); the pair's key is the view's tile_base plus the tile index
-// inside the view.  hist and partials are the radix sort's scratch.
+// inside the view (uint16_t keys if tile_keys16(tile_bits)).  hist and
+// partials are the radix sort's scratch.
 // first_row[b]: the row that holds pair b * kDupItems (the row-count scan's aux)
 hipError_t launch_duplicate_sorted(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
                                    const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,

@@ -237,8 +237,9 @@ struct ValPtrs {
 };
 
 // IPT items per thread; one block covers kBlock * IPT consecutive items.
-template <int IPT>
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* keys, const uint32_t* d_count,
+// KT: the stored key type (uint16_t for tile ids that fit 16 bits).
+template <int IPT, class KT = uint32_t>
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT* keys, const uint32_t* d_count,
                                                             uint32_t max_count, uint32_t key_bias, int shift, int bits,
                                                             uint32_t nblocks, uint32_t* hist) {
   __shared__ uint32_t h[kRadix];
@@ -288,11 +289,11 @@ __device__ inline void wave_sync() {
 // are items whose place would be at or past out_limit (only a histogram
 // that disagrees with the items could put them there).
 // stage_keys / stage_vals[q] hold kBlock * IPT words each.
-template <int P, int IPT, int RB>
+template <int P, int IPT, int RB, class KO = uint32_t>
 __device__ inline void rank_stage_write(const uint32_t (&my_key)[IPT], const uint32_t (&my_val)[IPT][P],
                                         uint32_t nvalid, uint32_t key_bias, int shift, int bits, uint32_t nblocks,
                                         uint32_t chunk, const uint32_t* scanned_hist, const ScatterLds<RB>& L,
-                                        uint32_t* stage_keys, uint32_t* const (&stage_vals)[P], uint32_t* keys_out,
+                                        uint32_t* stage_keys, uint32_t* const (&stage_vals)[P], KO* keys_out,
                                         const ValPtrs<P>& vout, uint32_t out_limit) {
   constexpr int kItems = kBlock * IPT;
   constexpr int kPerWave = kItems / kWaves;
@@ -366,7 +367,7 @@ __device__ inline void rank_stage_write(const uint32_t (&my_key)[IPT], const uin
     const uint32_t digit = ((key - key_bias) >> shift) & mask;
     const uint32_t dst = L.start[digit] + e;
     if (dst >= out_limit) continue;
-    keys_out[dst] = key;
+    keys_out[dst] = (KO)key;
     for (int q = 0; q < P; ++q) vout.p[q][dst] = stage_vals[q][e];
   }
 }
@@ -374,8 +375,9 @@ __device__ inline void rank_stage_write(const uint32_t (&my_key)[IPT], const uin
 // Stable scatter of one pass; P u32 payload words per key.
 // RB: the widest digit this instantiation handles (its LDS tables are 1 << RB
 // long, so narrow digits keep the footprint, and the occupancy, of their width)
-template <int P, int IPT, int RB>
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* keys_in, ValPtrs<P> vin,
+// KT: the stored type of the input keys (the output keys are uint32_t).
+template <int P, int IPT, int RB, class KT = uint32_t>
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const KT* keys_in, ValPtrs<P> vin,
                                                                uint32_t* keys_out, ValPtrs<P> vout,
                                                                const uint32_t* d_count, uint32_t max_count,
                                                                uint32_t key_bias, int shift, int bits, uint32_t nblocks,
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* k
   for (int it = 0; it < IPT; ++it) {
     const uint32_t idx = wave_base + it * 64 + lane;
     const bool valid = idx < count;
-    my_key[it] = valid ? keys_in[idx] : 0u;
+    my_key[it] = valid ? (uint32_t)keys_in[idx] : 0u;
     for (int q = 0; q < P; ++q) my_val[it][q] = valid ? vin.p[q][idx] : 0u;
   }
   uint32_t* const stage_keys = reinterpret_cast<uint32_t*>(stage);
@@ -697,12 +699,14 @@ __global__ __launch_bounds__(kBlock) void dup_hist_kernel(const uint32_t* row_of
 // into LDS, in slot order.  The waves then take the pairs in slot order and
 // scatter them by the first digit as a radix block does.
 constexpr int kDupGenRows = 4;
-template <int RB>
+// KO: the stored key type of the output (uint16_t when a later pass reads
+// the keys and the tile ids fit 16 bits).
+template <int RB, class KO>
 __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row_off, const uint32_t* row_g,
                                                              const uint32_t* row_yc, const uint32_t* first_row,
                                                              uint32_t R, uint32_t K, TileMap map, int digit_bits,
                                                              uint32_t nblocks, const uint32_t* scanned_hist,
-                                                             uint32_t* out_keys, uint32_t* out_vals) {
+                                                             KO* out_keys, uint32_t* out_vals) {
   constexpr int kPerWave = kDupItems / kWaves;
   // pairs in slot order (keys, then ids; one pad word per 32), then the
   // scatter's match tables and staging planes
@@ -764,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void dup_scatter_kernel(const uint32_t* row
   const ScatterLds<RB> L{wave_count, start, smem, s_kv};
   ValPtrs<1> vout;
   vout.p[0] = out_vals;
-  rank_stage_write<1, kDupIpt, RB>(my_key, my_val, cnt, 0u, 0, digit_bits, nblocks, chunk, scanned_hist, L,
+  rank_stage_write<1, kDupIpt, RB, KO>(my_key, my_val, cnt, 0u, 0, digit_bits, nblocks, chunk, scanned_hist, L,
                                         s_keys, sv, out_keys, vout, K);
 }
 
@@ -836,24 +840,47 @@ hipError_t radix_sort_impl(const RadixBuffers& B, const uint32_t* d_count, int64
       shift += pb;
       continue;
     }
+    // the first pass that runs may read 16-bit keys (the caller's, see
+    // RadixBuffers::keys16); every pass writes 32-bit keys
+    const bool k16 = P == 1 && B.keys16 && p == first_pass;
     {
       ProfScope prof(s, hist_id);
-      hipLaunchKernelGGL((radix_hist_kernel<IPT>), dim3(nb), dim3(kBlock), 0, s, ki, d_count, (uint32_t)max_count,
-                         key_bias, shift, pb, nb, hist);
+      if (k16)
+        hipLaunchKernelGGL((radix_hist_kernel<IPT, uint16_t>), dim3(nb), dim3(kBlock), 0, s,
+                           reinterpret_cast<const uint16_t*>(ki), d_count, (uint32_t)max_count, key_bias, shift, pb,
+                           nb, hist);
+      else
+        hipLaunchKernelGGL((radix_hist_kernel<IPT>), dim3(nb), dim3(kBlock), 0, s, ki, d_count, (uint32_t)max_count,
+                           key_bias, shift, pb, nb, hist);
     }
     hipError_t e = launch_scan(hist, nullptr, nullptr, (int64_t)nb << pb, kScanPlain, partials, nullptr, hist, s);
     if (e != hipSuccess) return e;
     {
       ProfScope prof(s, scatter_id);
-      if (pb <= 7)
-        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 7>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
-                           (uint32_t)max_count, key_bias, shift, pb, nb, hist);
-      else if (pb == 8)
-        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 8>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
-                           (uint32_t)max_count, key_bias, shift, pb, nb, hist);
-      else
-        hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, kRadixBits>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo,
-                           d_count, (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+      auto scatter32 = [&]() {
+        if (pb <= 7)
+          hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 7>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
+                             (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+        else if (pb == 8)
+          hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, 8>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, d_count,
+                             (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+        else
+          hipLaunchKernelGGL((radix_scatter_kernel<P, IPT, kRadixBits>), dim3(nb), dim3(kBlock), 0, s, ki, vi, ko,
+                             vo, d_count, (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+      };
+      if constexpr (P == 1) {
+        const uint16_t* k16i = reinterpret_cast<const uint16_t*>(ki);
+        if (k16 && pb <= 7)
+          hipLaunchKernelGGL((radix_scatter_kernel<1, IPT, 7, uint16_t>), dim3(nb), dim3(kBlock), 0, s, k16i, vi, ko,
+                             vo, d_count, (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+        else if (k16)  // 16-bit ids: the second of two passes has at most 8 bits
+          hipLaunchKernelGGL((radix_scatter_kernel<1, IPT, 8, uint16_t>), dim3(nb), dim3(kBlock), 0, s, k16i, vi, ko,
+                             vo, d_count, (uint32_t)max_count, key_bias, shift, pb, nb, hist);
+        else
+          scatter32();
+      } else {
+        scatter32();
+      }
     }
     shift += pb;
     uint32_t* t = ki;
@@ -1003,6 +1030,8 @@ hipError_t launch_rows(const uint32_t* ids, const uint32_t* rx, const uint32_t* 
   return hipGetLastError();
 }
 
+bool tile_keys16(int tile_bits) { return radix_passes(tile_bits) == 2 && tile_bits <= 16; }
+
 hipError_t launch_duplicate_sorted(const uint32_t* row_off, const uint32_t* row_g, const uint32_t* row_yc,
                                    const uint32_t* first_row, int64_t R, int64_t K, const ViewBatch& b, int64_t n,
                                    int tile_bits, uint32_t* hist, uint32_t* partials, uint32_t* out_keys,
@@ -1026,15 +1055,23 @@ hipError_t launch_duplicate_sorted(const uint32_t* row_off, const uint32_t* row_
   hipError_t e = launch_scan(hist, nullptr, nullptr, (int64_t)nb << first_bits, kScanPlain, partials, nullptr, hist, s);
   if (e != hipSuccess) return e;
   ProfScope prof(s, kKDuplicate);
-  if (first_bits <= 7)
-    hipLaunchKernelGGL(dup_scatter_kernel<7>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
-                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
-  else if (first_bits == 8)
-    hipLaunchKernelGGL(dup_scatter_kernel<8>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
-                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
-  else
-    hipLaunchKernelGGL(dup_scatter_kernel<kRadixBits>, dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, first_row,
-                       (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
+  uint16_t* const out16 = reinterpret_cast<uint16_t*>(out_keys);
+  const bool k16 = tile_keys16(tile_bits);
+#define FGS_DUP(RB)                                                                                             \
+  if (k16)                                                                                                       \
+    hipLaunchKernelGGL((dup_scatter_kernel<RB, uint16_t>), dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, \
+                       first_row, (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out16, out_vals);        \
+  else                                                                                                           \
+    hipLaunchKernelGGL((dup_scatter_kernel<RB, uint32_t>), dim3(nb), dim3(kBlock), 0, s, row_off, row_g, row_yc, \
+                       first_row, (uint32_t)R, (uint32_t)K, map, first_bits, nb, hist, out_keys, out_vals);
+  if (first_bits <= 7) {
+    FGS_DUP(7)
+  } else if (first_bits == 8) {
+    FGS_DUP(8)
+  } else {
+    FGS_DUP(kRadixBits)
+  }
+#undef FGS_DUP
   return hipGetLastError();
 }
 

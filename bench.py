@@ -44,13 +44,13 @@ def kernel_bytes(name: str, N: int, V: int, K: int, P: int, S: int) -> float | N
         return 16.0 * N
     if name == "depth_sort_hist":
         return 4.0 * N
-    if name == "duplicate":  # K pairs out, in the tile sort's first-pass order (the rows' offsets, ids
-        # and columns are read once per row)
-        return 8.0 * K
-    if name == "tile_sort_hist":
-        return 4.0 * K
-    if name == "tile_sort_scatter":
-        return 16.0 * K
+    if name == "duplicate":  # K pairs out, in the tile sort's first-pass order, with 16-bit keys (the rows'
+        # offsets, ids and columns are read once per row)
+        return 6.0 * K
+    if name == "tile_sort_hist":  # the second pass's histogram over the 16-bit keys
+        return 2.0 * K
+    if name == "tile_sort_scatter":  # the second pass: 16-bit keys and ids in, 32-bit keys and ids out
+        return 14.0 * K
     if name == "ranges":
         return 4.0 * K
     if name == "preprocess_backward":  # colour and geometry parts in one launch: tile count and mean of

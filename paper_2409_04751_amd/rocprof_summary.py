@@ -132,7 +132,7 @@ KERNELS = {
     "rows": "::rows_kernel(",
     "duplicate_hist": "::dup_hist_kernel(",
     "duplicate": "::dup_scatter_kernel<",
-    "tile_sort_hist": "::radix_hist_kernel<12>",
+    "tile_sort_hist": "::radix_hist_kernel<12,",
     "tile_sort_scatter": "::radix_scatter_kernel<1,",
     "ranges": "::ranges_kernel(",
     "blend_forward": "::blend_forward_kernel<false>",

@@ -11,14 +11,15 @@
 // keeps the depth order inside every tile, so the result is the order of
 // (tile, depth, id) with 16-20 fewer key bits moved per intersection.
 //
-// Radix passes are 8-bit LSD: a histogram kernel, an exclusive scan of the
-// digit-major histogram table, and a stable scatter.  The scatter ranks keys
-// inside a block with wave64 ballots (each lane learns which lanes share its
-// digit from one ballot per key bit), keeps per-wave digit counters in LDS,
-// and stages the block's items in LDS in sorted order so the global writes go
-// out as runs of consecutive addresses.  Item counts may live in device
-// memory (the visible count): grids are sized for the host-side bound and
-// blocks past the device count do nothing.
+// Radix passes are LSD with digits of up to 9 bits: a histogram kernel, an
+// exclusive scan of the digit-major histogram table, and a stable scatter.
+// The scatter ranks keys inside a block with one 64-bit lane mask per digit
+// and wave in LDS (each lane sets its bit, reads the mask back and clears
+// it), keeps per-wave digit counters in LDS, and stages the block's items in
+// LDS in sorted order so the global writes go out as runs of consecutive
+// addresses.  The tile sort's first pass runs inside the duplication.  Item
+// counts may live in device memory (the visible count): grids are sized for
+// the host-side bound and blocks past the device count do nothing.
 #include "fgs_internal.hpp"
 #include "reach.hpp"
 

@@ -301,8 +301,8 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
                         U(L.offsets), s),
             "visibility scan");
   HIP_TRY(launch_compact(U(L.tiles), U(L.depth_keys), reinterpret_cast<const uint2*>(ws + L.rects),
-                         U(L.rowrange), tight, U(L.offsets), nv, U(L.dkeys_a),
-                         U(L.dvals_a), U(L.drx_a), U(L.dry_a), counters, reinterpret_cast<uint4*>(hist), s),
+                         U(L.rowrange), tight, U(L.offsets), nv, U(L.dkeys_b),
+                         U(L.dvals_b), U(L.drx_b), U(L.dry_b), counters, reinterpret_cast<uint4*>(hist), s),
           "compact");
   uint32_t host_counters[kNumCounters];
   HIP_TRY(read_counters(counters, host_counters, s), "read counts");
@@ -335,17 +335,18 @@ int forward_impl(const fgs_gaussians* g, int32_t nviews, const fgs_pose* poses, 
   // sort below separates them again and keeps each view's depth order.
   const uint32_t kmin = host_counters[kCountKeyMin], kmax = host_counters[kCountKeyMax];
   const int depth_bits = V > 1 ? bits_for((int64_t)(kmax - kmin) + 1) : 0;
-  RadixBuffers DB{3, U(L.dkeys_a), U(L.dkeys_b), {U(L.dvals_a), U(L.drx_a), U(L.dry_a)},
-                  {U(L.dvals_b), U(L.drx_b), U(L.dry_b)}};
+  // the compaction filled the *_b planes, so the usual odd number of passes
+  // (3) leaves the order in the *_a planes, where the layout's depth_order
+  // points; after an even number the id plane is copied there
+  RadixBuffers DB{3, U(L.dkeys_b), U(L.dkeys_a), {U(L.dvals_b), U(L.drx_b), U(L.dry_b)},
+                  {U(L.dvals_a), U(L.drx_a), U(L.dry_a)}};
   HIP_TRY(launch_radix_sort(DB, nullptr, V, depth_bits, hist, partials, s, kKDepthHist, kKDepthScatter, 0, kmin),
           "depth sort");
-  // an odd number of passes leaves the order in the *_b planes; the id plane
-  // is copied back so the layout's depth_order always holds it
   const bool odd = radix_passes(depth_bits) % 2 == 1;
-  uint32_t* d_ids = odd ? U(L.dvals_b) : U(L.dvals_a);
-  uint32_t* d_rx = odd ? U(L.drx_b) : U(L.drx_a);
-  uint32_t* d_ry = odd ? U(L.dry_b) : U(L.dry_a);
-  if (odd && V > 0)
+  uint32_t* d_ids = odd ? U(L.dvals_a) : U(L.dvals_b);
+  uint32_t* d_rx = odd ? U(L.drx_a) : U(L.drx_b);
+  uint32_t* d_ry = odd ? U(L.dry_a) : U(L.dry_b);
+  if (!odd && V > 0)
     HIP_TRY(hipMemcpyAsync(U(L.dvals_a), d_ids, (size_t)V * 4, hipMemcpyDeviceToDevice, s), "depth order");
   // binning by rows: the depth-ordered entries' rows to bin (offsets = the
   // exclusive scan of their row ranges), each row's kept columns, the rows'

@@ -188,9 +188,9 @@ struct BatchOut {
 
 // ---- launchers (each returns hipSuccess or the first HIP error) ----------
 
-// Preprocess: writes splats, depth_keys, tiles, rects, radii, and seeds the
-// depth sort with (key, id) in dkeys_a / dvals_a.  Also clears the device
-// counters, storing `flags` in their flags slot.
+// Preprocess: writes splats, depth_keys, tiles, rects, radii (and, for one
+// view, each block's kept count).  Also clears the device counters, storing
+// `flags` in their flags slot.
 hipError_t launch_preprocess(const fgs_gaussians& g, const ViewBatch& b, bool tight, uint32_t flags, char* ws,
                              const Layout& L, hipStream_t s);
 

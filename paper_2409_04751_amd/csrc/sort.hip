@@ -491,13 +491,24 @@ __global__ __launch_bounds__(kStatsThreads) void stats_reduce_kernel(const uint4
   __syncthreads();
   unsigned long long k64 = 0, r64 = 0;
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
-  for (uint32_t b = threadIdx.x; b < nblocks; b += kStatsThreads) {
-    const uint4 st = block_stats[2 * b], sr = block_stats[2 * b + 1];
+  auto fold = [&](const uint4& st, const uint4& sr) {
     k64 += (unsigned long long)st.x | ((unsigned long long)st.y << 32);
     r64 += (unsigned long long)sr.x | ((unsigned long long)sr.y << 32);
     kmin = min(kmin, st.z);
     kmax = max(kmax, st.w);
+  };
+  uint32_t b = threadIdx.x;
+  for (; b + 3u * kStatsThreads < nblocks; b += 4u * kStatsThreads) {  // four blocks' loads in flight
+    uint4 st[4], sr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      st[q] = block_stats[2 * (b + (uint32_t)q * kStatsThreads)];
+      sr[q] = block_stats[2 * (b + (uint32_t)q * kStatsThreads) + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fold(st[q], sr[q]);
   }
+  for (; b < nblocks; b += kStatsThreads) fold(block_stats[2 * b], block_stats[2 * b + 1]);
   for (int d = 32; d >= 1; d >>= 1) {
     k64 += __shfl_xor(k64, d, 64);
     r64 += __shfl_xor(r64, d, 64);
